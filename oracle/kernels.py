@@ -1,0 +1,149 @@
+"""Mode-II kernels of the spectral BIEM, for the oracle.
+
+All kernels are written in the dimensionless time T = c_s |k| t, with
+r = c_s^2/c_p^2, q = 1/r and eta = c_p/c_s, so that c_p |k| t = eta T.
+
+* W(x) = 1 - x J0(x) + J1(x) - psi(x), psi(x) = (pi/2) x (J1 H0 - J0 H1)
+  (section 2.3, equations for W and psi; H0, H1 are Struve functions).
+  W is also the tail integral of J1(t)/t from x to infinity (appendix A).
+* C^T_II(T) = (T^2 + r) W(eta T) - (T^2 + 1) W(T) - r J1(eta T) + J1(T)/2
+  - (T/eta) J0(eta T) + T J0(T)                       (section 2.3, eq. Ct)
+* C^N_II(T) = ((q-2)^2 r/2 - r - T^2) W(eta T) + (1 + T^2 - q/2) W(T)
+  + (r - (q-2)^2 r/2) J1(eta T) + (q/2 - 1) J1(T) + (T/eta) J0(eta T)
+  - T J0(T)                                           (section 2.4)
+* c^T_II, the rate kernel whose primitive is C^T_II (section 2.3, and the
+  "primitive for shear" of appendix A).  The two printed versions disagree
+  (a factor 1/2 and the power of t); the reading used is the one that is
+  dimensionally consistent, in units of c_s|k|:
+  c^T(T) = (1/2) [J1(T)/T + 4 T (W(eta T) - W(T)) - (4/eta) J0(eta T)
+  + 3 J0(T)].  It is only used to pin C^T (dC^T/dT = c^T).
+
+Two evaluators:
+
+* ``*_mp``: mpmath with 30 significant digits, then rounded to FP64.  The
+  closed forms cancel (terms of size ~T^(1/2) give a result of size
+  ~T^(-1/2)), so FP64 evaluation loses about 1e-9 relative near T = 100;
+  30 digits leave more than 20 correct.
+* ``*_fp``: the same closed forms in FP64 with scipy's Bessel and Struve
+  functions.  Accurate to about 1e-10 absolute for T <= 250; used where a
+  test's tolerance is 1e-7 or looser.
+"""
+
+from __future__ import annotations
+
+import os
+from concurrent.futures import ProcessPoolExecutor
+
+import mpmath as mp
+import numpy as np
+from scipy.special import j0 as _j0, j1 as _j1, struve as _struve
+
+MP_DPS = 30
+
+
+def _mp_consts(cs, cp):
+    cs = mp.mpf(cs)
+    cp = mp.mpf(cp)
+    r = (cs / cp) ** 2
+    return r, 1 / r, cp / cs
+
+
+def W_mp(x):
+    """W(x) = 1 - x J0 + J1 - psi with psi = (pi/2) x (J1 H0 - J0 H1)."""
+    with mp.workdps(max(MP_DPS, mp.mp.dps)):
+        x = mp.mpf(x)
+        J0 = mp.besselj(0, x)
+        J1 = mp.besselj(1, x)
+        psi = mp.pi / 2 * x * (J1 * mp.struveh(0, x) - J0 * mp.struveh(1, x))
+        return 1 - x * J0 + J1 - psi
+
+
+def W_integral_mp(x):
+    """W(x) by its definition: the integral of J1(t)/t from x to infinity."""
+    with mp.workdps(max(MP_DPS, mp.mp.dps)):
+        return mp.quadosc(lambda t: mp.besselj(1, t) / t, [mp.mpf(x), mp.inf], omega=1)
+
+
+def kernels_mp(T, cs, cp):
+    """(C^T_II(T), C^N_II(T)) as mpmath numbers, 30 significant digits."""
+    with mp.workdps(max(MP_DPS, mp.mp.dps)):
+        r, q, eta = _mp_consts(cs, cp)
+        T = mp.mpf(T)
+        a = eta * T
+        Wa, Wb = W_mp(a), W_mp(T)
+        J0a, J1a = mp.besselj(0, a), mp.besselj(1, a)
+        J0b, J1b = mp.besselj(0, T), mp.besselj(1, T)
+        ct = ((T ** 2 + r) * Wa - (T ** 2 + 1) * Wb - r * J1a + J1b / 2
+              - (T / eta) * J0a + T * J0b)
+        cn = (((q - 2) ** 2 * r / 2 - r - T ** 2) * Wa + (1 + T ** 2 - q / 2) * Wb
+              + (r - (q - 2) ** 2 * r / 2) * J1a + (q / 2 - 1) * J1b
+              + (T / eta) * J0a - T * J0b)
+        return ct, cn
+
+
+def rate_kernel_T_mp(T, cs, cp):
+    """c^T_II(T) in units of c_s|k| (reading stated in the module docstring)."""
+    with mp.workdps(max(MP_DPS, mp.mp.dps)):
+        r, q, eta = _mp_consts(cs, cp)
+        T = mp.mpf(T)
+        return (mp.besselj(1, T) / T + 4 * T * (W_mp(eta * T) - W_mp(T))
+                - (4 / eta) * mp.besselj(0, eta * T) + 3 * mp.besselj(0, T)) / 2
+
+
+def _W_fp(x):
+    x = np.asarray(x, dtype=np.float64)
+    psi = np.pi / 2 * x * (_j1(x) * _struve(0, x) - _j0(x) * _struve(1, x))
+    return 1.0 - x * _j0(x) + _j1(x) - psi
+
+
+def kernels_fp(T, cs, cp):
+    """(C^T_II(T), C^N_II(T)) in FP64 (scipy), vectorised over T."""
+    T = np.asarray(T, dtype=np.float64)
+    r = (cs / cp) ** 2
+    q = 1.0 / r
+    eta = cp / cs
+    a = eta * T
+    Wa, Wb = _W_fp(a), _W_fp(T)
+    J0a, J1a, J0b, J1b = _j0(a), _j1(a), _j0(T), _j1(T)
+    ct = ((T ** 2 + r) * Wa - (T ** 2 + 1) * Wb - r * J1a + J1b / 2
+          - (T / eta) * J0a + T * J0b)
+    cn = (((q - 2) ** 2 * r / 2 - r - T ** 2) * Wa + (1 + T ** 2 - q / 2) * Wb
+          + (r - (q - 2) ** 2 * r / 2) * J1a + (q / 2 - 1) * J1b
+          + (T / eta) * J0a - T * J0b)
+    return ct, cn
+
+
+def _table_chunk(args):
+    ps, delta_str, cs, cp = args
+    with mp.workdps(max(MP_DPS, mp.mp.dps)):
+        delta = mp.mpf(delta_str)
+        out = np.empty((len(ps), 2))
+        for i, p in enumerate(ps):
+            ct, cn = kernels_mp(p * delta, cs, cp)
+            out[i, 0] = float(ct)
+            out[i, 1] = float(cn)
+        return out
+
+
+def kernel_table_mp(delta, p_max, cs, cp, processes=None):
+    """C^T and C^N at T_p = p * delta for p = 0..p_max, 30-digit evaluation.
+
+    ``delta`` may be a string to carry more than FP64 digits.  Returns two
+    FP64 arrays of length p_max + 1.  Work is spread over a process pool.
+    """
+    delta_str = delta if isinstance(delta, str) else repr(float(delta))
+    ps = np.arange(p_max + 1)
+    nproc = processes or min(16, os.cpu_count() or 1)
+    chunks = [(ps[i::nproc * 8].tolist(), delta_str, cs, cp) for i in range(nproc * 8)]
+    CT = np.empty(p_max + 1)
+    CN = np.empty(p_max + 1)
+    if nproc == 1:
+        results = [_table_chunk(c) for c in chunks]
+    else:
+        with ProcessPoolExecutor(nproc) as ex:
+            results = list(ex.map(_table_chunk, chunks))
+    for i, res in enumerate(results):
+        sel = ps[i::nproc * 8]
+        CT[sel] = res[:, 0]
+        CN[sel] = res[:, 1]
+    return CT, CN

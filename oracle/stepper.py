@@ -1,0 +1,173 @@
+"""Two-pass predictor-corrector time step (section 3.3), FP64 oracle.
+
+One step from t to t + dt, following the paper's order:
+
+pass 1 (V_c = V_0, thetadot_c = thetadot_0), pass 2 (V_c = (V_0 + V_1)/2,
+thetadot_c = (thetadot_0 + thetadot_1)/2), each pass doing
+
+  (1) predict slip u_p = u_0 + dt V_c and state theta_p = theta_0 + dt thetadot_c
+  (2) tractions at t + dt: static term on the predicted slip, the current
+      interval's rate V_c with weight w_{n,0} (the integral over [0, dt]),
+      and the stored history with weights w_{n,j}, j >= 1 (section 3.1)
+  (3) Newton solve of the momentum balance for V_p, then
+      thetadot_p = 1 - theta_p V_p / Dc (aging law).
+
+The step ends with u = u_2, V = V_2, theta = theta_2, thetadot = thetadot_2,
+and the rate stored in the spectral history for the interval [t, t+dt] is
+(V_0 + V_1)/2, the rate that moved the slip in pass 2.
+
+Readings (the paper is silent on them):
+* loading is backslip at the plate rate V_pl: the elastic terms act on
+  Delta u - V_pl t and V - V_pl, and a uniform V_pl is an exact steady state;
+  an optional uniform shear-load rate adds tau_rate * t;
+* the history before the first step is V = V_pl (zero in the backslip
+  frame);
+* theta update: ``theta_mode="paper"`` is the explicit update above (the
+  paper's); ``"exp"`` integrates the aging law exactly at the fixed rate
+  V_c: theta_p = Dc/V_c + (theta_0 - Dc/V_c) exp(-V_c dt / Dc), which stays
+  positive where the explicit update is unstable (V dt / Dc > 2).
+* a failed step (normal traction not compressive, state not positive, or a
+  Newton solve that does not converge) raises ``OracleStepError`` and leaves
+  the state at the start of the step (section 3.2).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .friction import solve_newton
+from .spectral import curvature, dft, idft_real, odd_sign, wavenumbers
+from .windows import KernelTable, midpoint_weights
+
+ERR_NEWTON = -4
+ERR_STATE = -5
+ERR_OPEN = -6
+
+
+class OracleStepError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(msg)
+        self.code = code
+
+
+class OracleFault:
+    """One periodic fault integrated by the oracle's two-pass scheme."""
+
+    def __init__(self, N, L, mu, cs, cp, *, dt, friction, h=None, kappa=None,
+                 table: KernelTable | None = None, theta_mode="paper"):
+        self.N, self.L, self.mu, self.cs, self.cp, self.dt = N, L, mu, cs, cp, dt
+        self.r = (cs / cp) ** 2
+        if kappa is None:
+            kappa = curvature(np.zeros(N) if h is None else np.asarray(h, float), L)
+        self.kappa = np.asarray(kappa, dtype=np.float64)
+        self.kabs = np.abs(wavenumbers(N, L))
+        self.s = odd_sign(N)
+        self.w = midpoint_weights(N, L, cs, cp, dt, table)
+        f = friction
+        self.a, self.b = np.asarray(f["a"], float), np.asarray(f["b"], float)
+        self.Dc, self.V_ref, self.f0 = f["Dc"], f["V_ref"], f["f0"]
+        self.sigma_load = np.asarray(f["sigma_load"], float)
+        self.tau_load = np.asarray(f["tau_load"], float)
+        self.tau_rate = float(f.get("tau_load_rate", 0.0))
+        self.V_pl = float(f["V_pl"])
+        self.eta_rad = mu / (2.0 * cs)
+        self.theta_mode = theta_mode
+        # history of lags j = 1..M_n-1, newest first, flat per mode
+        M = self.w.M
+        self.hM = np.maximum(M - 1, 0)
+        self.hoff = np.concatenate([[0], np.cumsum(self.hM)[:-1]]).astype(np.int64)
+        tot = int(self.hM.sum())
+        self.HT = np.zeros(tot, dtype=np.complex128)
+        self.HN = np.zeros(tot, dtype=np.complex128)
+        mode_of = np.repeat(np.arange(N), self.hM)
+        lag = np.arange(tot) - np.repeat(self.hoff, self.hM) + 1       # j = 1..M-1
+        self._hist_mode = mode_of
+        self._wT_hist = self.w.wT[self.w.off[mode_of] + lag]
+        self._wN_hist = self.w.wN[self.w.off[mode_of] + lag]
+        self._w0T = self.w.wT[self.w.off]
+        self._w0N = self.w.wN[self.w.off]
+        # shift map: entry at lag j moves to lag j+1; lag 1 receives the push
+        src = np.arange(tot) - 1
+        first = np.zeros(tot, dtype=bool)
+        first[self.hoff[self.hM > 0]] = True
+        self._shift_src = np.where(first, 0, src)
+        self._first = first
+        self.set_state(f["slip0"], f["V0"], f["theta0"], 0.0)
+
+    # ------------------------------------------------------------------
+    def set_state(self, slip, V, theta, t):
+        self.slip = np.array(slip, dtype=np.float64)
+        self.V = np.array(V, dtype=np.float64)
+        self.theta = np.array(theta, dtype=np.float64)
+        self.thetadot = 1.0 - self.theta * self.V / self.Dc
+        self.t = float(t)
+        self.HT[:] = 0
+        self.HN[:] = 0
+        self.tau_el = np.zeros(self.N)
+        self.sigma_el = np.zeros(self.N)
+        self.nsteps = 0
+
+    def history_sums(self):
+        """S^X_n = sum_{j>=1} w^X_{n,j} H^X_n(lag j)."""
+        ST = np.bincount(self._hist_mode, weights=(self._wT_hist * self.HT).real, minlength=self.N) \
+            + 1j * np.bincount(self._hist_mode, weights=(self._wT_hist * self.HT).imag, minlength=self.N)
+        SN = np.bincount(self._hist_mode, weights=(self._wN_hist * self.HN).real, minlength=self.N) \
+            + 1j * np.bincount(self._hist_mode, weights=(self._wN_hist * self.HN).imag, minlength=self.N)
+        return ST, SN
+
+    def tractions(self, slip_p, V_c, t_new, ST, SN):
+        """Elastic tau, sigma at t_new for predicted slip and current rate V_c."""
+        u = slip_p - self.V_pl * t_new
+        v = V_c - self.V_pl
+        U, G = dft(u), dft(self.kappa * u)
+        Vh, GV = dft(v), dft(self.kappa * v)
+        tau_hat = -self.mu * self.kabs * ((1 - self.r) * U + self._w0T * Vh + ST)
+        sig_hat = -1j * self.s * self.mu * ((1 - self.r) * G + self._w0N * GV + SN)
+        return idft_real(tau_hat), idft_real(sig_hat), Vh, GV
+
+    def _pass(self, V_c, thd_c, ST, SN):
+        dt = self.dt
+        t_new = self.t + dt
+        slip_p = self.slip + dt * V_c
+        if self.theta_mode == "exp":
+            ss = self.Dc / V_c
+            theta_p = ss + (self.theta - ss) * np.exp(-V_c * dt / self.Dc)
+        else:
+            theta_p = self.theta + dt * thd_c
+        tau_el, sig_el, Vh, GV = self.tractions(slip_p, V_c, t_new, ST, SN)
+        tau = self.tau_load + self.tau_rate * t_new + tau_el
+        sig = self.sigma_load + sig_el
+        if np.any(sig <= 0):
+            raise OracleStepError(ERR_OPEN, "normal traction not compressive")
+        if np.any(theta_p <= 0) or not np.all(np.isfinite(theta_p)):
+            raise OracleStepError(ERR_STATE, "state variable not positive")
+        V_p, ok = solve_newton(tau, sig, theta_p, self.a, self.b, self.f0, self.V_ref,
+                               self.Dc, self.eta_rad, V_guess=V_c)
+        if not np.all(ok) or not np.all(np.isfinite(V_p)):
+            raise OracleStepError(ERR_NEWTON, "Newton solve did not converge")
+        thd_p = 1.0 - theta_p * V_p / self.Dc
+        return slip_p, theta_p, V_p, thd_p, tau_el, sig_el, Vh, GV
+
+    def step(self):
+        ST, SN = self.history_sums()
+        V0, thd0 = self.V, self.thetadot
+        _, _, V1, thd1, _, _, _, _ = self._pass(V0, thd0, ST, SN)
+        Vc = 0.5 * (V0 + V1)
+        slip2, theta2, V2, thd2, tau_el, sig_el, Vh, GV = self._pass(Vc, 0.5 * (thd0 + thd1), ST, SN)
+        # push (V0 + V1)/2 as the rate of the interval [t, t + dt]
+        self.HT = np.where(self._first, Vh[self._hist_mode], self.HT[self._shift_src])
+        self.HN = np.where(self._first, GV[self._hist_mode], self.HN[self._shift_src])
+        self.slip, self.V, self.theta, self.thetadot = slip2, V2, theta2, thd2
+        self.tau_el, self.sigma_el = tau_el, sig_el
+        self.t += self.dt
+        self.nsteps += 1
+
+    def run(self, nsteps, record_every=0):
+        rec = []
+        for i in range(nsteps):
+            self.step()
+            if record_every and (i + 1) % record_every == 0:
+                rec.append(dict(step=self.nsteps, slip=self.slip.copy(), V=self.V.copy(),
+                                theta=self.theta.copy(), tau_el=self.tau_el.copy(),
+                                sigma_el=self.sigma_el.copy()))
+        return rec

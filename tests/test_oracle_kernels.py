@@ -1,0 +1,131 @@
+"""Pins of the oracle's kernel functions against what the paper and the
+mathematics fix (no GPU)."""
+
+import mpmath as mp
+import numpy as np
+import pytest
+from scipy.integrate import quad
+from scipy.special import j0, j1
+
+from oracle.kernels import (MP_DPS, W_integral_mp, W_mp, kernels_fp, kernels_mp,
+                            rate_kernel_T_mp)
+
+CS, CP = 3464.0, 6000.0
+R = (CS / CP) ** 2
+Q = 1 / R
+ETA = CP / CS
+
+
+def test_static_dynamic_cancellation_at_t0():
+    # Sections 2.3/2.4: both kernels start at -(1 - c_s^2/c_p^2) so the static
+    # and dynamic terms cancel at t = 0.
+    for T in (0, mp.mpf("1e-20")):
+        ct, cn = kernels_mp(T, CS, CP)
+        assert abs(float(ct) + (1 - R)) < 1e-15
+        assert abs(float(cn) + (1 - R)) < 1e-15
+
+
+@pytest.mark.parametrize("T", [0.5, 3.0, 20.0, 120.0])
+def test_shear_kernel_is_primitive_of_rate_kernel(T):
+    # Section 2.3: C^T_II is the time primitive of the Geubelle-Rice rate kernel.
+    with mp.workdps(MP_DPS):
+        d = mp.diff(lambda x: kernels_mp(x, CS, CP)[0], mp.mpf(T))
+        c = rate_kernel_T_mp(T, CS, CP)
+        assert abs(d - c) < mp.mpf("1e-20")
+
+
+@pytest.mark.parametrize("x", [0.3, 2.0, 17.0, 60.0])
+def test_W_closed_form_matches_integral_definition(x):
+    # Appendix A: W(x) is the integral of J1(t)/t from x to infinity.
+    with mp.workdps(MP_DPS):
+        assert abs(W_mp(x) - W_integral_mp(x)) < mp.mpf("1e-18")
+
+
+def _A(z, W):
+    return z * j0(z) + j1(z) + 1 + z ** 2 - (1 + z ** 2) * W
+
+
+def _B(z, W):
+    return 1 + j1(z) - W
+
+
+@pytest.mark.parametrize("T", [0.3, 2.0, 9.0, 40.0, 150.0])
+def test_normal_kernel_matches_appendix_B_rebuild(T):
+    # Appendix B: the normal-traction kernel assembled from the two Fourier
+    # pairs, the Lame relations lambda^2/mu^2 = (q-2)^2, lambda+2mu = mu q,
+    # P-wave (argument eta T) and S-wave (argument T) parts, minus the static
+    # part (1 - r).  Evaluated here in mpmath from scratch.
+    with mp.workdps(MP_DPS):
+        T = mp.mpf(T)
+
+        def blocks(z):
+            J0, J1 = mp.besselj(0, z), mp.besselj(1, z)
+            W = 1 - z * J0 + J1 - mp.pi / 2 * z * (J1 * mp.struveh(0, z) - J0 * mp.struveh(1, z))
+            A = z * J0 + J1 + 1 + z ** 2 - (1 + z ** 2) * W
+            B = 1 + J1 - W
+            return A, B
+
+        r = (mp.mpf(CS) / CP) ** 2
+        q = 1 / r
+        Ap, Bp = blocks(mp.mpf(CP) / CS * T)
+        As, Bs = blocks(T)
+        rebuild = r * Ap - r / 2 * (q - 2) ** 2 * Bp - As + q / 2 * Bs - (1 - r)
+        cn = kernels_mp(T, CS, CP)[1]
+        assert abs(rebuild - cn) < mp.mpf("1e-22")
+
+
+@pytest.mark.parametrize("k", [0.7, 3.0, 11.0])
+def test_fourier_pair_1_fixes_forward_sign(k):
+    # Appendix B, first pair (b = 1): F[rect(x/2)/(x sqrt(1-x^2))](k)
+    # = -i pi (1 + J1(k) - W(k)) with F[f](k) = int f exp(-ikx) dx.
+    # The function is odd, so F = -2i int_0^1 f sin(kx) dx.
+    v = quad(lambda x: np.sin(k * x) / (x * np.sqrt(1 - x * x)), 0, 1, limit=400)[0]
+    W = float(W_mp(k))
+    assert abs(-2 * v - (-np.pi * _B(k, W))) < 1e-9
+
+
+@pytest.mark.parametrize("k", [0.7, 3.0, 11.0])
+def test_fourier_pair_2_fixes_forward_sign(k):
+    # Appendix B, second pair (b = 1), Hadamard finite part at x = 0:
+    # F[sqrt(1-x^2)/x^3 rect(x/2)](k) = (i pi / 2) A(k).
+    g = lambda x: np.sin(k * x) * np.sqrt(1 - x * x) / x  # noqa: E731
+    fp = quad(lambda x: (g(x) - k) / x ** 2, 0, 1, limit=400)[0] - k
+    W = float(W_mp(k))
+    assert abs(-2 * fp - 0.5 * np.pi * _A(k, W)) < 1e-9
+
+
+def test_kernels_decay_and_long_time_integrals():
+    # Section 3.1: both kernels tend to zero at large argument.  Their time
+    # integrals over (0, inf) are -1/2 (shear: matches the radiation-damping
+    # coefficient mu/(2 c_s) once multiplied by -mu|k|/(c_s|k|)) and 0
+    # (normal).  The integrals converge slowly (oscillating ~T^-1/2), so the
+    # running integral is Cesaro-averaged over [X/2, X].
+    T = np.linspace(0.0, 1200.0, 1_200_001)
+    ct, cn = kernels_fp(T, CS, CP)
+    for c, target in ((ct, -0.5), (cn, 0.0)):
+        run = np.concatenate([[0.0], np.cumsum(0.5 * (c[1:] + c[:-1]) * np.diff(T))])
+        lo = np.searchsorted(T, 600.0)
+        assert abs(run[lo:].mean() - target) < 2e-4
+    big = T > 150
+    assert np.abs(ct[big]).max() < 0.05 and np.abs(cn[big]).max() < 0.15
+
+
+def test_fp64_evaluator_agrees_with_30_digit_evaluator():
+    # The FP64 closed form loses accuracy to cancellation; bound it.
+    Ts = np.concatenate([np.linspace(0.01, 5, 7), np.linspace(10, 250, 13)])
+    ct_fp, cn_fp = kernels_fp(Ts, CS, CP)
+    for i, T in enumerate(Ts):
+        ct, cn = kernels_mp(T, CS, CP)
+        assert abs(ct_fp[i] - float(ct)) < 3e-9
+        assert abs(cn_fp[i] - float(cn)) < 3e-9
+
+
+def test_golden_kernel_table_is_oracle_output():
+    # The stored 30-digit table equals fresh oracle evaluations at spot points.
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "kernel_table_L10km_beta05_N256.npz")
+    z = np.load(path)
+    for p in (0, 1, 17, 1023, 20000, int(z["p_max"])):
+        with mp.workdps(MP_DPS):
+            ct, cn = kernels_mp(mp.mpf(repr(float(z["delta"]))) * p, CS, CP)
+        assert z["CT"][p] == float(ct) and z["CN"][p] == float(cn)
