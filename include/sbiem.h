@@ -1,0 +1,233 @@
+/*
+ * sbiem.h - C ABI of the MI355X spectral boundary-integral (sBIEM) hot path
+ * for a mildly non-planar 1-D fault in a 2-D in-plane elastic medium
+ * (Romanet & Ozawa, "Fully dynamic earthquake cycle simulations on a
+ * non-planar fault using the spectral boundary integral element method").
+ *
+ * What one time step computes (section 3, "Model and algorithm"):
+ *   - the elastic shear traction tau^el (section 2.3, eq. Ct and the
+ *     truncated form of section 3.1) and the small-slope normal traction
+ *     sigma^el driven by curvature x slip (section 2.4), each a static term
+ *     plus a per-wavenumber truncated time convolution of the slip-rate
+ *     spectra with the closed-form kernels C^T_II and C^N_II, truncation
+ *     window T_w(k) of section 3.1, midpoint weights;
+ *   - the rate-and-state (aging law) momentum balance solved per element for
+ *     the slip rate, inside the two-pass predictor-corrector step of
+ *     section 3.3.
+ *
+ * Conventions used throughout:
+ *   - N elements at x_i = i L / N on a periodic fault of length L (metres);
+ *     N must be a power of two with 8 <= N <= 2^22.
+ *   - Wavenumber index n = 0..N/2, k_n = 2 pi n / L; the forward transform is
+ *     F_n = sum_i f_i exp(-i k_n x_i) (the sign fixed by the Fourier pairs of
+ *     appendix B).
+ *   - Shear traction and slip are positive in the same sense; the normal
+ *     traction sigma is compression-positive; the normal elastic traction
+ *     uses the multiplier -i sgn(k) mu (Nyquist bin dropped).
+ *   - The momentum balance carries radiation damping -mu V / (2 c_s)
+ *     (section 2.3: the S-wave inertia term contains it).
+ *   - Loading is backslip at the plate rate V_pl: the elastic terms act on
+ *     slip - V_pl t and V - V_pl, so uniform sliding at V_pl is a steady
+ *     state.  The slip-rate history before the first step is V_pl.
+ *   - All arrays passed through this ABI are host memory, FP64, length N,
+ *     element-major, owned by the caller; inputs are copied before return and
+ *     outputs are fully written before return (host-pointer calls synchronise
+ *     the plan's stream).  A plan owns all of its device memory.
+ *   - Return value: SBIEM_OK (0) or a negative status; sbiem_last_error()
+ *     gives a message.  A plan is not thread-safe; distinct plans are
+ *     independent.
+ */
+#ifndef SBIEM_H
+#define SBIEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SBIEM_ABI_VERSION 1
+
+typedef struct sbiem_plan sbiem_plan;
+typedef struct sbiem_batch sbiem_batch;
+
+enum sbiem_status {
+  SBIEM_OK = 0,
+  SBIEM_EINVAL = -1,    /* invalid argument or call order                       */
+  SBIEM_ENOMEM = -2,    /* device or host allocation failed                     */
+  SBIEM_EDEVICE = -3,   /* HIP runtime error / no usable gfx950 device          */
+  SBIEM_ENEWTON = -4,   /* momentum balance did not converge (section 3.2)      */
+  SBIEM_ESTATE = -5,    /* state variable became non-positive (section 3.2)     */
+  SBIEM_EOPEN = -6,     /* normal traction not compressive (section 3.2)        */
+  SBIEM_ENOTREADY = -7  /* friction, state or time step not set yet             */
+};
+
+/* Precision of the history convolution and the FFTs.  Slip, slip rate,
+ * state, the spectral slip accumulators and the friction solve are FP64 in
+ * both modes.  SBIEM_FP32CONV keeps the slip-rate history in FP32 and
+ * evaluates the kernel weights on the fly from an interpolated table. */
+enum sbiem_precision { SBIEM_FP64 = 0, SBIEM_FP32CONV = 1 };
+
+/* State update of each pass (section 3.3).  PAPER: theta_p = theta_0 +
+ * dt * thetadot_c (the paper's explicit update).  EXP: exact integration of
+ * the aging law at the pass's constant rate V_c,
+ * theta_p = Dc/V_c + (theta_0 - Dc/V_c) exp(-V_c dt / Dc); it stays positive
+ * where the explicit update is unstable (V dt / Dc > 2). */
+enum sbiem_theta_mode { SBIEM_THETA_PAPER = 0, SBIEM_THETA_EXP = 1 };
+
+/* ABI version of the loaded library (SBIEM_ABI_VERSION it was built with). */
+int sbiem_abi_version(void);
+
+/* Human-readable name of a status code (static string). */
+const char* sbiem_status_string(int status);
+
+/* Create a plan for one fault.
+ *   N       number of elements (power of two, 8..2^22)
+ *   L       periodic fault length [m] (> 0)
+ *   mu      shear modulus [Pa] (> 0)
+ *   nu      Poisson's ratio; only checked for consistency with the wave
+ *           speeds: 0 < nu < 0.5 and |nu - nu(c_s, c_p)| <= 1e-3, where
+ *           c_p^2/c_s^2 = 2(1-nu)/(1-2nu).  The kernels use r = c_s^2/c_p^2.
+ *   cs, cp  shear and dilatational wave speeds [m/s], 0 < cs < cp
+ *   h       fault profile h(x_i) [m], length N, copied; NULL = planar.
+ *           The curvature kappa = h'' (section 2.2, small-slope
+ *           approximation) is computed spectrally on the device in FP64.
+ * Selects a device (the current HIP device) and allocates the per-element
+ * buffers.  Errors: EINVAL (bad arguments, non-finite h), EDEVICE, ENOMEM.
+ * On error *out is NULL. */
+int sbiem_plan_create(sbiem_plan** out, int64_t N, double L, double mu, double nu,
+                      double cs, double cp, const double* h);
+
+/* Release a plan and all its device memory (NULL is a no-op). */
+int sbiem_plan_destroy(sbiem_plan* p);
+
+/* Message of the last failing call on p; with p == NULL, the last failing
+ * call of this thread that had no plan (e.g. sbiem_plan_create).  The string
+ * is owned by the library and valid until the next call on the same plan. */
+const char* sbiem_last_error(const sbiem_plan* p);
+
+/* Choose SBIEM_FP64 (default) or SBIEM_FP32CONV.  Must precede
+ * sbiem_set_dt / the first step; EINVAL afterwards. */
+int sbiem_set_precision(sbiem_plan* p, int mode);
+
+/* Choose SBIEM_THETA_PAPER (default) or SBIEM_THETA_EXP; may change
+ * between steps. */
+int sbiem_set_theta_mode(sbiem_plan* p, int mode);
+
+/* Rate-and-state friction and loading (section 3, eq. momentum; aging law).
+ *   a, b         [N] direct and evolution effects (a > 0)
+ *   Dc, V_ref, f0  critical slip [m], reference velocity [m/s] (the law's
+ *                "V0"), reference friction
+ *   sigma_load   [N] normal load [Pa], compression positive
+ *   tau_load     [N] shear load [Pa] at t = 0; grows as tau_load_rate * t
+ *   V_pl         plate rate [m/s] of the backslip loading (may be 0)
+ * Errors: EINVAL (non-finite values, a <= 0, Dc <= 0, V_ref <= 0). */
+int sbiem_set_friction(sbiem_plan* p, const double* a, const double* b, double Dc,
+                       double V_ref, double f0, const double* sigma_load,
+                       const double* tau_load, double tau_load_rate, double V_pl);
+
+/* Set slip [m], slip rate [m/s] (> 0) and state [s] (> 0) at time t and
+ * clear the slip-rate history (rates before t are V_pl).  thetadot is set
+ * from the aging law, 1 - theta V / Dc, so set_friction must come first
+ * (else ENOTREADY).  Clears a pending failure. */
+int sbiem_set_state(sbiem_plan* p, const double* slip, const double* V,
+                    const double* theta, double t);
+
+/* Read the state after the last committed step.  Any output pointer may be
+ * NULL.  tau_el and sigma_el are the elastic tractions of the last pass
+ * (without radiation damping and without the loads); zero before the first
+ * step. */
+int sbiem_get_state(sbiem_plan* p, double* slip, double* V, double* theta,
+                    double* tau_el, double* sigma_el, double* t);
+
+/* The device-computed curvature kappa = h'' [1/m], length N. */
+int sbiem_get_curvature(const sbiem_plan* p, double* kappa);
+
+/* Fix the time step dt [s] (> 0): computes the windows M_n (section 3.1:
+ * T_w(k) = (L/c_s) min(1, k_c/|k|), k_c = 200/L, M_n = ceil(T_w/dt) with a
+ * 1e-9 relative guard), the midpoint weights w_{n,j} = dt C(c_s|k_n|(j+1/2)dt)
+ * and allocates the zeroed history ring.  Clears the history.  Called
+ * implicitly by the first sbiem_step/sbiem_run. */
+int sbiem_set_dt(sbiem_plan* p, double dt);
+
+/* Window lengths M_n for n = 1..N/2 (M[0] is mode 1) at time step dt,
+ * computed on the host; does not change the plan. */
+int sbiem_window_lengths(const sbiem_plan* p, double dt, int64_t* M);
+
+/* Stress-only evaluation of the spectral-time functional (section 3.1):
+ * the elastic tractions at t_nt of a slip history slip_hist
+ * [(nt+1) * N], oldest snapshot first, snapshot m at t_m = m dt.  The rate of
+ * interval [t_l, t_{l+1}] is the first difference of the snapshots; the
+ * static terms act on the last snapshot; no backslip (V_pl = 0), no
+ * radiation damping.  Uses the plan's precision; does not touch the
+ * stepping state.  Errors: EINVAL (nt < 0, dt <= 0). */
+int sbiem_stress(sbiem_plan* p, const double* slip_hist, int64_t nt, double dt,
+                 double* tau_out, double* sigma_out);
+
+/* One two-pass step of length dt (section 3.3).  dt must equal the plan's
+ * dt once set (variable dt is not supported: EINVAL).  Synchronous: returns
+ * ENEWTON / ESTATE / EOPEN if the step failed, leaving the state at the
+ * start of the step (section 3.2).  ENOTREADY without friction and state. */
+int sbiem_step(sbiem_plan* p, double dt);
+
+/* nsteps steps launched back to back without host synchronisation (a
+ * captured HIP graph replayed), then one synchronisation.  The first
+ * failing step stops the run: the state is left at the start of that step
+ * and its status returned; sbiem_steps_done tells how far it got. */
+int sbiem_run(sbiem_plan* p, double dt, int64_t nsteps);
+
+/* Number of committed steps since the last set_state / set_dt. */
+int sbiem_steps_done(const sbiem_plan* p, int64_t* nsteps);
+
+/* Failure report of the last step/run: number of failing elements of the
+ * failing pass and the first failing element index (-1 if none). */
+int sbiem_failures(const sbiem_plan* p, int64_t* count, int64_t* first_index);
+
+/* Run the plan's work on this HIP stream (hipStream_t passed as void*,
+ * e.g. torch.cuda.current_stream().cuda_stream).  Default: the null
+ * stream.  Invalidates captured graphs. */
+int sbiem_set_stream(sbiem_plan* p, void* hip_stream);
+
+/* Process-wide device allocator used for plan and batch memory allocated
+ * after this call (e.g. a caching allocator).  alloc returns NULL on
+ * failure; both NULL restores hipMalloc/hipFree. */
+int sbiem_set_allocator(void* (*alloc)(size_t bytes, void* ctx),
+                        void (*release)(void* ptr, void* ctx), void* ctx);
+
+/* Host evaluation (extended precision) of the kernels of sections 2.3/2.4
+ * and their derivatives at dimensionless times T[i] = c_s |k| t >= 0.
+ * Any output may be NULL.  Used to build the weight tables; exported for
+ * verification. */
+int sbiem_kernel_eval(double cs, double cp, const double* T, int64_t n, double* CT,
+                      double* CN, double* dCT, double* dCN);
+
+/* Per-launch timing of the history-convolution kernel with HIP events on
+ * the plan's stream.  While on, sbiem_run replays steps without a graph so
+ * that each launch is bracketed.  sbiem_profile returns the accumulated
+ * milliseconds and launch count, the algorithmic bytes one launch reads
+ * and writes (ring records of lags 2..M_n-1, partial sums) and resets the
+ * counters. */
+int sbiem_set_profiling(sbiem_plan* p, int on);
+int sbiem_profile(sbiem_plan* p, double* conv_ms, int64_t* conv_launches,
+                  double* conv_bytes_per_launch);
+
+/* Ensembles: independent faults of uneven N stepped together (one launch
+ * per phase for all faults, graph-captured).  The plans keep their own
+ * state and must share precision; each must have friction, state and dt
+ * set.  A batch holds references to the plans (destroy the batch first). */
+int sbiem_batch_create(sbiem_batch** out, sbiem_plan* const* plans, int64_t n);
+int sbiem_batch_destroy(sbiem_batch* b);
+/* nsteps steps of every member; returns the first failing member's status
+ * (other members keep stepping; each failed member stops at the start of its
+ * failing step). */
+int sbiem_batch_run(sbiem_batch* b, int64_t nsteps);
+int sbiem_batch_set_profiling(sbiem_batch* b, int on);
+int sbiem_batch_profile(sbiem_batch* b, double* conv_ms, int64_t* conv_launches,
+                        double* conv_bytes_per_launch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBIEM_H */

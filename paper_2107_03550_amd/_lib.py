@@ -1,0 +1,271 @@
+"""ctypes binding of libsbiem (argument marshalling only).
+
+Every ``sbiem_*`` function of the C ABI is available on ``lib`` with its
+argument types set.  ``Plan`` and ``Batch`` wrap the handles and convert
+numpy arrays (FP64, C order) to pointers; each method calls the C function
+of the same name and raises ``SbiemError`` on a negative status.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "lib", "libsbiem.so")
+
+if not os.path.exists(lib_path):
+    raise ImportError(f"{lib_path} is missing: build it with "
+                      "'python -m paper_2107_03550_amd.build' (hipcc, gfx950)")
+lib = ctypes.CDLL(lib_path)
+
+SBIEM_FP64 = 0
+SBIEM_FP32CONV = 1
+SBIEM_THETA_PAPER = 0
+SBIEM_THETA_EXP = 1
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+_VP = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_dbl = ctypes.c_double
+_int = ctypes.c_int
+_PLAN = ctypes.c_void_p
+_PPLAN = ctypes.POINTER(ctypes.c_void_p)
+_ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+_SIGS = {
+    "sbiem_abi_version": (_int, []),
+    "sbiem_status_string": (ctypes.c_char_p, [_int]),
+    "sbiem_plan_create": (_int, [_PPLAN, _i64, _dbl, _dbl, _dbl, _dbl, _dbl, _D]),
+    "sbiem_plan_destroy": (_int, [_PLAN]),
+    "sbiem_last_error": (ctypes.c_char_p, [_PLAN]),
+    "sbiem_set_precision": (_int, [_PLAN, _int]),
+    "sbiem_set_theta_mode": (_int, [_PLAN, _int]),
+    "sbiem_set_friction": (_int, [_PLAN, _D, _D, _dbl, _dbl, _dbl, _D, _D, _dbl, _dbl]),
+    "sbiem_set_state": (_int, [_PLAN, _D, _D, _D, _dbl]),
+    "sbiem_get_state": (_int, [_PLAN, _D, _D, _D, _D, _D, _D]),
+    "sbiem_get_curvature": (_int, [_PLAN, _D]),
+    "sbiem_set_dt": (_int, [_PLAN, _dbl]),
+    "sbiem_window_lengths": (_int, [_PLAN, _dbl, _I64]),
+    "sbiem_stress": (_int, [_PLAN, _D, _i64, _dbl, _D, _D]),
+    "sbiem_step": (_int, [_PLAN, _dbl]),
+    "sbiem_run": (_int, [_PLAN, _dbl, _i64]),
+    "sbiem_steps_done": (_int, [_PLAN, _I64]),
+    "sbiem_failures": (_int, [_PLAN, _I64, _I64]),
+    "sbiem_set_stream": (_int, [_PLAN, _VP]),
+    "sbiem_set_allocator": (_int, [_ALLOC, _FREE, _VP]),
+    "sbiem_kernel_eval": (_int, [_dbl, _dbl, _D, _i64, _D, _D, _D, _D]),
+    "sbiem_set_profiling": (_int, [_PLAN, _int]),
+    "sbiem_profile": (_int, [_PLAN, _D, _I64, _D]),
+    "sbiem_batch_create": (_int, [_PPLAN, ctypes.POINTER(ctypes.c_void_p), _i64]),
+    "sbiem_batch_destroy": (_int, [_VP]),
+    "sbiem_batch_run": (_int, [_VP, _i64]),
+    "sbiem_batch_set_profiling": (_int, [_VP, _int]),
+    "sbiem_batch_profile": (_int, [_VP, _D, _I64, _D]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED_NAMES = tuple(_SIGS)
+
+
+class SbiemError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{lib.sbiem_status_string(status).decode()} ({status}): {message}")
+        self.status = status
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_D)
+
+
+def _arr(x, n=None, name="array"):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    if n is not None and a.size != n:
+        raise ValueError(f"{name}: expected {n} values, got {a.size}")
+    return a
+
+
+def _check(status, handle=None):
+    if status != 0:
+        msg = lib.sbiem_last_error(handle)
+        raise SbiemError(status, msg.decode() if msg else "")
+    return status
+
+
+def abi_version():
+    return lib.sbiem_abi_version()
+
+
+def kernel_eval(T, cs, cp):
+    """C^T, C^N, dC^T/dT, dC^N/dT at T (host extended precision)."""
+    T = _arr(T)
+    outs = [np.empty(T.size) for _ in range(4)]
+    _check(lib.sbiem_kernel_eval(cs, cp, _ptr(T), T.size, *[_ptr(o) for o in outs]))
+    return tuple(outs)
+
+
+_torch_alloc_refs = []
+
+
+def set_torch_allocator():
+    """Route plan memory through torch's caching allocator (current stream)."""
+    import torch
+
+    def _alloc(nbytes, ctx):
+        return torch.cuda.caching_allocator_alloc(int(nbytes))
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a, f = _ALLOC(_alloc), _FREE(_free)
+    _torch_alloc_refs[:] = [a, f]
+    _check(lib.sbiem_set_allocator(a, f, None))
+
+
+class Plan:
+    """One fault (wraps sbiem_plan)."""
+
+    def __init__(self, N, L, mu, nu, cs, cp, h=None):
+        self.N = int(N)
+        hh = None if h is None else _arr(h, self.N, "h")
+        handle = ctypes.c_void_p()
+        _check(lib.sbiem_plan_create(ctypes.byref(handle), self.N, L, mu, nu, cs, cp, _ptr(hh)))
+        self.handle = handle
+        self.L, self.mu, self.nu, self.cs, self.cp = L, mu, nu, cs, cp
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib.sbiem_plan_destroy(h)
+            self.handle = None
+
+    def _c(self, st):
+        return _check(st, self.handle)
+
+    def set_precision(self, mode):
+        self._c(lib.sbiem_set_precision(self.handle, mode))
+
+    def set_theta_mode(self, mode):
+        self._c(lib.sbiem_set_theta_mode(self.handle, mode))
+
+    def set_friction(self, a, b, Dc, V_ref, f0, sigma_load, tau_load, tau_load_rate=0.0, V_pl=0.0):
+        n = self.N
+        a, b, s, t = (_arr(v, n, k) for v, k in ((a, "a"), (b, "b"), (sigma_load, "sigma_load"),
+                                                 (tau_load, "tau_load")))
+        self._c(lib.sbiem_set_friction(self.handle, _ptr(a), _ptr(b), Dc, V_ref, f0, _ptr(s),
+                                       _ptr(t), tau_load_rate, V_pl))
+
+    def set_state(self, slip, V, theta, t=0.0):
+        n = self.N
+        s, v, th = _arr(slip, n, "slip"), _arr(V, n, "V"), _arr(theta, n, "theta")
+        self._c(lib.sbiem_set_state(self.handle, _ptr(s), _ptr(v), _ptr(th), t))
+
+    def get_state(self):
+        n = self.N
+        out = {k: np.empty(n) for k in ("slip", "V", "theta", "tau_el", "sigma_el")}
+        t = ctypes.c_double()
+        self._c(lib.sbiem_get_state(self.handle, _ptr(out["slip"]), _ptr(out["V"]),
+                                    _ptr(out["theta"]), _ptr(out["tau_el"]),
+                                    _ptr(out["sigma_el"]), ctypes.byref(t)))
+        out["t"] = t.value
+        return out
+
+    def get_curvature(self):
+        k = np.empty(self.N)
+        self._c(lib.sbiem_get_curvature(self.handle, _ptr(k)))
+        return k
+
+    def set_dt(self, dt):
+        self._c(lib.sbiem_set_dt(self.handle, dt))
+
+    def window_lengths(self, dt):
+        M = np.empty(self.N // 2, dtype=np.int64)
+        self._c(lib.sbiem_window_lengths(self.handle, dt, M.ctypes.data_as(_I64)))
+        return M
+
+    def stress(self, slip_hist, dt):
+        h = _arr(slip_hist).reshape(-1, self.N)
+        tau, sig = np.empty(self.N), np.empty(self.N)
+        self._c(lib.sbiem_stress(self.handle, _ptr(h), h.shape[0] - 1, dt, _ptr(tau), _ptr(sig)))
+        return tau, sig
+
+    def step(self, dt):
+        self._c(lib.sbiem_step(self.handle, dt))
+
+    def run(self, dt, nsteps):
+        self._c(lib.sbiem_run(self.handle, dt, int(nsteps)))
+
+    def run_status(self, dt, nsteps):
+        """Like run() but returns the status instead of raising."""
+        return lib.sbiem_run(self.handle, dt, int(nsteps))
+
+    def steps_done(self):
+        n = ctypes.c_int64()
+        self._c(lib.sbiem_steps_done(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def failures(self):
+        c, i = ctypes.c_int64(), ctypes.c_int64()
+        self._c(lib.sbiem_failures(self.handle, ctypes.byref(c), ctypes.byref(i)))
+        return c.value, i.value
+
+    def set_stream(self, stream_ptr):
+        self._c(lib.sbiem_set_stream(self.handle, ctypes.c_void_p(int(stream_ptr))))
+
+    def set_profiling(self, on=True):
+        self._c(lib.sbiem_set_profiling(self.handle, 1 if on else 0))
+
+    def profile(self):
+        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        self._c(lib.sbiem_profile(self.handle, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+        return ms.value, n.value, b.value
+
+    def last_error(self):
+        m = lib.sbiem_last_error(self.handle)
+        return m.decode() if m else ""
+
+
+class Batch:
+    """Ensemble of plans stepped together (wraps sbiem_batch)."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        handle = ctypes.c_void_p()
+        _check(lib.sbiem_batch_create(ctypes.byref(handle), arr, len(self.plans)))
+        self.handle = handle
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib.sbiem_batch_destroy(h)
+            self.handle = None
+
+    def run(self, nsteps):
+        st = lib.sbiem_batch_run(self.handle, int(nsteps))
+        if st != 0:
+            raise SbiemError(st, lib.sbiem_last_error(None).decode())
+
+    def run_status(self, nsteps):
+        return lib.sbiem_batch_run(self.handle, int(nsteps))
+
+    def set_profiling(self, on=True):
+        _check(lib.sbiem_batch_set_profiling(self.handle, 1 if on else 0))
+
+    def profile(self):
+        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib.sbiem_batch_profile(self.handle, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+        return ms.value, n.value, b.value

@@ -1,0 +1,544 @@
+// Execution contexts of libsbiem: launch sequences of the two-pass step for
+// one fault or a batch of faults, HIP-graph replay, failure reporting,
+// per-launch timing and the stress-only path.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace sbiem {
+
+namespace {
+constexpr int kGraphSteps = 16;  // steps captured in one replayable graph
+}
+
+Exec::~Exec() { drop_graph(); }
+
+hipError_t EventPool::ensure(size_t n) {
+  while (ev.size() < n) {
+    hipEvent_t x = nullptr;
+    hipError_t e = hipEventCreate(&x);
+    if (e) return e;
+    ev.push_back(x);
+  }
+  return hipSuccess;
+}
+
+EventPool::~EventPool() {
+  for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+}
+
+void Exec::drop_graph() {
+  if (graph) (void)hipGraphExecDestroy(graph);
+  if (graph_def) (void)hipGraphDestroy(graph_def);
+  graph = nullptr;
+  graph_def = nullptr;
+  graph_steps = 0;
+}
+
+int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>& dts,
+               const std::vector<DynData*>& dyns, const std::vector<FaultDev>& descs,
+               int precision, Exec** out, std::string* err) {
+  (void)dyns;
+  *out = nullptr;
+  Exec* ex = new Exec();
+  ex->precision = precision;
+  ex->nfaults = (int)plans.size();
+  ex->host_faults = descs;
+  std::vector<Tile> tiles;
+  std::vector<int2> nmap;
+  double bytes = 0.0;
+  const double rec = precision == SBIEM_FP32CONV ? 16.0 : 32.0;
+  for (int f = 0; f < ex->nfaults; ++f) {
+    DtData* d = dts[f];
+    ex->host_faults[f].tile_base = (int)tiles.size();
+    for (Tile t : d->tiles) {
+      t.fault = f;
+      tiles.push_back(t);
+    }
+    // algorithmic bytes: ring records of lags 2..M_n-1 and one partial per tile
+    for (size_t n = 1; n < d->Rn.size(); ++n)
+      if (d->Rn[n] > 1) bytes += rec * (d->Rn[n] - 1);
+    bytes += rec * d->tiles.size();
+    const int N = (int)plans[f]->N;
+    ex->max_N = std::max(ex->max_N, N);
+    for (int i = 0; i < N; i += kNewtonThreads) nmap.push_back(make_int2(f, i));
+    if (precision == SBIEM_FP32CONV) {
+      if (d->table_len > ex->table_len) {
+        ex->table_len = d->table_len;
+        ex->table = d->table;
+      }
+    }
+  }
+  if (precision == SBIEM_FP32CONV && ex->nfaults > 1) {
+    // all faults must share the table (same dt, c_s, c_p)
+    for (int f = 0; f < ex->nfaults; ++f) {
+      sbiem_plan* p = plans[f];
+      sbiem_plan* q = plans[0];
+      if (dts[f]->dt != dts[0]->dt || p->cs != q->cs || p->cp != q->cp) {
+        *err = "FP32 batch members must share dt, cs and cp";
+        delete ex;
+        return SBIEM_EINVAL;
+      }
+    }
+  }
+  ex->ntiles = (int)tiles.size();
+  ex->newton_blocks = (int)nmap.size();
+  ex->conv_bytes = bytes;
+  ex->conv_grid = conv_grid_size(precision, ex->ntiles, ex->table_len);
+  const size_t part = precision == SBIEM_FP32CONV ? 16 : 32;
+  ex->d_faults = (FaultDev*)ex->mem.get(sizeof(FaultDev) * ex->nfaults);
+  ex->d_tiles = (Tile*)ex->mem.get(sizeof(Tile) * std::max(1, ex->ntiles));
+  ex->d_partials = ex->mem.get(part * std::max(1, ex->ntiles));
+  ex->d_newton_map = (int2*)ex->mem.get(sizeof(int2) * std::max(1, ex->newton_blocks));
+  if (!ex->d_faults || !ex->d_tiles || !ex->d_partials || !ex->d_newton_map) {
+    *err = "device allocation of the execution context failed";
+    delete ex;
+    return SBIEM_ENOMEM;
+  }
+  hipError_t e = hipMemcpy(ex->d_faults, ex->host_faults.data(), sizeof(FaultDev) * ex->nfaults,
+                           hipMemcpyHostToDevice);
+  if (!e && ex->ntiles)
+    e = hipMemcpy(ex->d_tiles, tiles.data(), sizeof(Tile) * ex->ntiles, hipMemcpyHostToDevice);
+  if (!e)
+    e = hipMemcpy(ex->d_newton_map, nmap.data(), sizeof(int2) * ex->newton_blocks, hipMemcpyHostToDevice);
+  if (!e) e = setup_kernel_attributes(precision);
+  if (e) {
+    *err = std::string("building the execution context: ") + hipGetErrorString(e);
+    delete ex;
+    return SBIEM_EDEVICE;
+  }
+  *out = ex;
+  return SBIEM_OK;
+}
+
+int refresh_desc(sbiem_plan* p) {
+  FaultDev f = make_fault_desc(p, p->dtd, p->dyn, p->V_pl, p->t0, 0);
+  hipError_t e = hipSetDevice(p->device);
+  if (!e) e = hipStreamSynchronize(p->stream);
+  if (!e) e = hipMemcpy(p->d_desc, &f, sizeof(f), hipMemcpyHostToDevice);
+  if (e) return hip_fail(p, e, "updating the fault descriptor");
+  if (p->exec) {
+    f.tile_base = p->exec->host_faults[0].tile_base;
+    p->exec->host_faults[0] = f;
+    e = hipMemcpy(p->exec->d_faults, &f, sizeof(f), hipMemcpyHostToDevice);
+    if (e) return hip_fail(p, e, "updating the fault descriptor");
+  }
+  return SBIEM_OK;
+}
+
+int rebuild_exec(sbiem_plan* p) {
+  delete p->exec;
+  p->exec = nullptr;
+  if (!p->dtd) return SBIEM_OK;
+  FaultDev f = make_fault_desc(p, p->dtd, p->dyn, p->V_pl, p->t0, 0);
+  std::string err;
+  Exec* ex = nullptr;
+  int st = build_exec({p}, {p->dtd}, {p->dyn}, {f}, p->precision, &ex, &err);
+  if (st) return fail(p, st, err);
+  p->exec = ex;
+  return refresh_desc(p);
+}
+
+// step counter 0, no pending failure, empty history (zero ring and lag-1 record).
+int reset_history(sbiem_plan* p) {
+  DynData* d = p->dyn;
+  hipStream_t s = p->stream;
+  const size_t M = (size_t)(p->N / 2 + 1);
+  hipError_t e = hipMemsetAsync(d->step, 0, sizeof(long long), s);
+  const int init[3] = {0, 0, 0x7fffffff};
+  if (!e) e = hipMemcpyAsync(d->err, init, sizeof(init), hipMemcpyHostToDevice, s);
+  if (!e) e = hipMemsetAsync(d->hprev_v, 0, M * sizeof(double2), s);
+  if (!e) e = hipMemsetAsync(d->hprev_g, 0, M * sizeof(double2), s);
+  if (!e && p->dtd) {
+    const size_t rec = p->precision == SBIEM_FP32CONV ? 16 : 32;
+    e = hipMemsetAsync(p->dtd->ring, 0, (size_t)std::max<long long>(p->dtd->ring_slots, 1) * rec, s);
+  }
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return hip_fail(p, e, "resetting the history");
+  return SBIEM_OK;
+}
+
+// Move the committed state to buffer 0 with t0 = its time (dt about to change).
+int rebase_state(sbiem_plan* p) {
+  DynData* d = p->dyn;
+  long long step = 0;
+  hipError_t e = hipMemcpy(&step, d->step, sizeof(step), hipMemcpyDeviceToHost);
+  if (e) return hip_fail(p, e, "rebase");
+  const int cur = (int)(step & 1);
+  const size_t bytes = (size_t)p->N * sizeof(double);
+  if (cur == 1) {
+    e = hipMemcpy(d->slip[0], d->slip[1], bytes, hipMemcpyDeviceToDevice);
+    if (!e) e = hipMemcpy(d->V[0], d->V[1], bytes, hipMemcpyDeviceToDevice);
+    if (!e) e = hipMemcpy(d->theta[0], d->theta[1], bytes, hipMemcpyDeviceToDevice);
+    if (!e) e = hipMemcpy(d->thd[0], d->thd[1], bytes, hipMemcpyDeviceToDevice);
+    if (!e) e = hipMemcpy(d->tau_el[0], d->tau_el[1], bytes, hipMemcpyDeviceToDevice);
+    if (!e) e = hipMemcpy(d->sigma_el[0], d->sigma_el[1], bytes, hipMemcpyDeviceToDevice);
+    if (e) return hip_fail(p, e, "rebase");
+  }
+  p->t0 += (double)step * (p->dtd ? p->dtd->dt : 0.0);
+  e = hipMemset(d->step, 0, sizeof(long long));
+  if (e) return hip_fail(p, e, "rebase");
+  return SBIEM_OK;
+}
+
+// u_hat = F[slip - V_pl t], g_hat = F[kappa (slip - V_pl t)],
+// v_hat0 = F[V - V_pl], gv_hat0 = F[kappa (V - V_pl)] from host arrays.
+int spectral_state_from_host(sbiem_plan* p, const double* slip, const double* V, double t) {
+  const int64_t N = p->N;
+  std::vector<double> x(N), y(N);
+  for (int64_t i = 0; i < N; ++i) {
+    x[i] = slip[i] - p->V_pl * t;
+    y[i] = V[i] - p->V_pl;
+  }
+  DynData* d = p->dyn;
+  hipStream_t s = p->stream;
+  const size_t bytes = (size_t)N * sizeof(double);
+  hipError_t e = hipMemcpyAsync(d->V1, x.data(), bytes, hipMemcpyHostToDevice, s);
+  if (!e) e = hipMemcpyAsync(d->thd1, y.data(), bytes, hipMemcpyHostToDevice, s);
+  if (!e) e = setup_kernel_attributes(p->precision);
+  if (!e) e = launch_spectra(p->d_desc, p->precision, (int)N, d->V1, nullptr, 1.0, d->u_hat, d->g_hat,
+                             1, 0, 0, s);
+  if (!e) e = launch_spectra(p->d_desc, p->precision, (int)N, d->thd1, nullptr, 1.0, d->v_hat0,
+                             d->gv_hat0, 1, 0, 0, s);
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return hip_fail(p, e, "computing the spectral state");
+  return SBIEM_OK;
+}
+
+int spectral_state_from_device(sbiem_plan* p) {
+  const int64_t N = p->N;
+  std::vector<double> slip(N), V(N);
+  double t = 0.0;
+  if (int st = sbiem_get_state(p, slip.data(), V.data(), nullptr, nullptr, nullptr, &t)) return st;
+  return spectral_state_from_host(p, slip.data(), V.data(), t);
+}
+
+namespace {
+
+int check_failure(sbiem_plan* p) {
+  DynData* d = p->dyn;
+  int h[3];
+  hipError_t e = hipMemcpy(h, d->err, sizeof(h), hipMemcpyDeviceToHost);
+  if (e) return hip_fail(p, e, "reading the failure flag");
+  if (h[0] == 0) {
+    p->last_fail_count = 0;
+    p->last_fail_index = -1;
+    return SBIEM_OK;
+  }
+  p->last_fail_count = h[1];
+  p->last_fail_index = h[2];
+  const int init[3] = {0, 0, 0x7fffffff};
+  e = hipMemcpy(d->err, init, sizeof(init), hipMemcpyHostToDevice);
+  if (e) return hip_fail(p, e, "clearing the failure flag");
+  const char* what = h[0] == SBIEM_EOPEN ? "normal traction not compressive"
+                     : h[0] == SBIEM_ESTATE ? "state variable not positive"
+                                            : "momentum balance did not converge";
+  return fail(p, h[0], std::string("step failed: ") + what + " at element " + std::to_string(h[2]));
+}
+
+int ready(sbiem_plan* p, double dt) {
+  if (!p->friction_set || !p->state_set)
+    return fail(p, SBIEM_ENOTREADY, "set_friction and set_state must precede stepping");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(p, SBIEM_EINVAL, "dt must be > 0");
+  if (!p->dtd) return sbiem_set_dt(p, dt);
+  if (dt != p->dtd->dt)
+    return fail(p, SBIEM_EINVAL, "variable dt is not supported: dt differs from the plan's");
+  return SBIEM_OK;
+}
+
+hipError_t ensure_graph(Exec* ex, hipStream_t s) {
+  if (ex->graph && ex->graph_stream == s) return hipSuccess;
+  ex->drop_graph();
+  hipStream_t cap = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (e) return e;
+  e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (!e) {
+    for (int k = 0; k < kGraphSteps && !e; ++k) e = launch_step(*ex, cap, false, nullptr, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cap, &g);
+    if (!e) e = e2;
+    if (!e) {
+      e = hipGraphInstantiate(&ex->graph, g, nullptr, nullptr, 0);
+      ex->graph_def = g;
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  }
+  (void)hipStreamDestroy(cap);
+  if (!e) {
+    ex->graph_steps = kGraphSteps;
+    ex->graph_stream = s;
+  } else {
+    ex->drop_graph();
+  }
+  return e;
+}
+
+// Run nsteps of an execution context on stream s.  While profiling, every
+// step is launched directly with a pair of events around its conv launch
+// (no host synchronisation inside the run); the elapsed times are summed
+// once the run has finished.
+hipError_t run_steps(Exec* ex, int64_t nsteps, hipStream_t s, bool profile, EventPool* pool,
+                     double* prof_ms, int64_t* prof_launches) {
+  hipError_t e = hipSuccess;
+  if (profile) {
+    const int64_t chunk = 4096;
+    for (int64_t done = 0; done < nsteps && !e; done += chunk) {
+      const int64_t n = std::min(chunk, nsteps - done);
+      e = pool->ensure((size_t)(2 * n));
+      for (int64_t k = 0; k < n && !e; ++k)
+        e = launch_step(*ex, s, true, pool->ev[2 * k], pool->ev[2 * k + 1]);
+      if (!e) e = hipEventSynchronize(pool->ev[2 * n - 1]);
+      for (int64_t k = 0; k < n && !e; ++k) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, pool->ev[2 * k], pool->ev[2 * k + 1]);
+        if (!e) {
+          *prof_ms += ms;
+          *prof_launches += 1;
+        }
+      }
+    }
+    return e;
+  }
+  int64_t left = nsteps;
+  if (left >= kGraphSteps) {
+    e = ensure_graph(ex, s);
+    if (e) return e;
+    while (left >= kGraphSteps && !e) {
+      e = hipGraphLaunch(ex->graph, s);
+      left -= kGraphSteps;
+    }
+  }
+  for (int64_t k = 0; k < left && !e; ++k) e = launch_step(*ex, s, false, nullptr, nullptr);
+  return e;
+}
+
+}  // namespace
+
+}  // namespace sbiem
+
+using namespace sbiem;
+
+extern "C" {
+
+int sbiem_step(sbiem_plan* p, double dt) { return sbiem_run(p, dt, 1); }
+
+int sbiem_run(sbiem_plan* p, double dt, int64_t nsteps) {
+  if (!p) return fail_global(SBIEM_EINVAL, "NULL plan");
+  if (nsteps < 0) return fail(p, SBIEM_EINVAL, "nsteps must be >= 0");
+  if (int st = ready(p, dt)) return st;
+  hipError_t e = hipSetDevice(p->device);
+  if (e) return hip_fail(p, e, "hipSetDevice");
+  if (!p->exec) {
+    if (int st = rebuild_exec(p)) return st;
+  }
+  e = run_steps(p->exec, nsteps, p->stream, p->profiling, &p->events, &p->prof_ms,
+                &p->prof_launches);
+  if (!e) e = hipStreamSynchronize(p->stream);
+  if (e) return hip_fail(p, e, "running the time steps");
+  return check_failure(p);
+}
+
+int sbiem_steps_done(const sbiem_plan* p, int64_t* nsteps) {
+  if (!p || !nsteps) return fail_global(SBIEM_EINVAL, "NULL argument");
+  long long step = 0;
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (!e) e = hipMemcpy(&step, p->dyn->step, sizeof(step), hipMemcpyDeviceToHost);
+  if (e) return hip_fail(const_cast<sbiem_plan*>(p), e, "steps_done");
+  *nsteps = step;
+  return SBIEM_OK;
+}
+
+int sbiem_failures(const sbiem_plan* p, int64_t* count, int64_t* first_index) {
+  if (!p) return fail_global(SBIEM_EINVAL, "NULL plan");
+  if (count) *count = p->last_fail_count;
+  if (first_index) *first_index = p->last_fail_count ? p->last_fail_index : -1;
+  return SBIEM_OK;
+}
+
+int sbiem_set_profiling(sbiem_plan* p, int on) {
+  if (!p) return fail_global(SBIEM_EINVAL, "NULL plan");
+  p->profiling = on != 0;
+  p->prof_ms = 0.0;
+  p->prof_launches = 0;
+  return SBIEM_OK;
+}
+
+int sbiem_profile(sbiem_plan* p, double* conv_ms, int64_t* conv_launches,
+                  double* conv_bytes_per_launch) {
+  if (!p) return fail_global(SBIEM_EINVAL, "NULL plan");
+  if (conv_ms) *conv_ms = p->prof_ms;
+  if (conv_launches) *conv_launches = p->prof_launches;
+  if (conv_bytes_per_launch) *conv_bytes_per_launch = p->exec ? p->exec->conv_bytes : 0.0;
+  p->prof_ms = 0.0;
+  p->prof_launches = 0;
+  return SBIEM_OK;
+}
+
+int sbiem_stress(sbiem_plan* p, const double* slip_hist, int64_t nt, double dt, double* tau_out,
+                 double* sigma_out) {
+  if (!p) return fail_global(SBIEM_EINVAL, "NULL plan");
+  if (nt < 0 || !(dt > 0) || !std::isfinite(dt) || !slip_hist || !tau_out || !sigma_out)
+    return fail(p, SBIEM_EINVAL, "stress: need nt >= 0, dt > 0 and arrays");
+  const int64_t N = p->N;
+  for (int64_t i = 0; i < (nt + 1) * N; ++i)
+    if (!std::isfinite(slip_hist[i])) return fail(p, SBIEM_EINVAL, "stress: slip must be finite");
+  hipError_t e = hipSetDevice(p->device);
+  if (e) return hip_fail(p, e, "hipSetDevice");
+  hipStream_t s = p->stream;
+  e = hipStreamSynchronize(s);
+  if (e) return hip_fail(p, e, "stress");
+  DtData* dtd = nullptr;
+  if (int st = build_dt_data(p, dt, &dtd)) return st;
+  DynData* dyn = nullptr;
+  if (int st = build_dyn_data(p, &dyn)) {
+    delete dtd;
+    return st;
+  }
+  FaultDev f = make_fault_desc(p, dtd, dyn, 0.0, 0.0, 0);
+  std::string err;
+  Exec* ex = nullptr;
+  int st = build_exec({p}, {dtd}, {dyn}, {f}, p->precision, &ex, &err);
+  if (st) {
+    delete dyn;
+    delete dtd;
+    return fail(p, st, err);
+  }
+  DevArena tmp;
+  const int M = (int)(N / 2 + 1);
+  const int64_t nint = nt;
+  double* d_hist = (double*)tmp.get((size_t)(nt + 1) * N * sizeof(double));
+  double* d_rates = (double*)tmp.get((size_t)std::max<int64_t>(nint, 1) * N * sizeof(double));
+  double2* RV = (double2*)tmp.get((size_t)std::max<int64_t>(nint, 1) * M * sizeof(double2));
+  double2* RG = (double2*)tmp.get((size_t)std::max<int64_t>(nint, 1) * M * sizeof(double2));
+  if (!d_hist || !d_rates || !RV || !RG) {
+    delete ex;
+    delete dyn;
+    delete dtd;
+    return fail(p, SBIEM_ENOMEM, "stress: device allocation failed");
+  }
+  e = hipMemcpyAsync(d_hist, slip_hist, (size_t)(nt + 1) * N * sizeof(double), hipMemcpyHostToDevice, s);
+  // interval rates as first differences of the snapshots
+  if (!e && nint > 0) e = launch_rates(d_hist, d_rates, (long long)nint * N, N, dt, s);
+  const FaultDev* dfd = ex->d_faults;
+  if (!e && nint > 0)
+    e = launch_spectra(dfd, p->precision, (int)N, d_rates, nullptr, 1.0, RV, RG, (int)nint, N, M, s);
+  // static part on snapshot nt-1 (its slip plus dt times the last rate is snapshot nt)
+  const int64_t base = nint > 0 ? nt - 1 : 0;
+  if (!e)
+    e = launch_spectra(dfd, p->precision, (int)N, d_hist + base * N, nullptr, 1.0, dyn->u_hat,
+                       dyn->g_hat, 1, 0, 0, s);
+  if (!e && nint > 0) {
+    e = hipMemcpyAsync(dyn->v_hat0, RV + (nint - 1) * M, M * sizeof(double2), hipMemcpyDeviceToDevice, s);
+    if (!e) e = hipMemcpyAsync(dyn->gv_hat0, RG + (nint - 1) * M, M * sizeof(double2), hipMemcpyDeviceToDevice, s);
+  }
+  if (!e) e = launch_fill_ring(dfd, p->precision, M - 1, RV, RG, (int)nint, s);
+  const long long step = nint > 0 ? nint - 1 : 0;
+  if (!e) e = hipMemcpyAsync(dyn->step, &step, sizeof(step), hipMemcpyHostToDevice, s);
+  if (!e) e = launch_conv(*ex, s);
+  if (!e) e = launch_pass1(*ex, s);
+  if (!e) e = hipStreamSynchronize(s);
+  const int slot = (int)((step + 1) & 1);
+  if (!e) e = hipMemcpy(tau_out, dyn->tau_el[slot], N * sizeof(double), hipMemcpyDeviceToHost);
+  if (!e) e = hipMemcpy(sigma_out, dyn->sigma_el[slot], N * sizeof(double), hipMemcpyDeviceToHost);
+  delete ex;
+  delete dyn;
+  delete dtd;
+  if (e) return hip_fail(p, e, "stress");
+  return SBIEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+int sbiem_batch_create(sbiem_batch** out, sbiem_plan* const* plans, int64_t n) {
+  if (!out || !plans || n <= 0) return fail_global(SBIEM_EINVAL, "batch_create: need plans");
+  *out = nullptr;
+  const int prec = plans[0]->precision;
+  std::vector<sbiem_plan*> ps(plans, plans + n);
+  std::vector<DtData*> dts;
+  std::vector<DynData*> dyns;
+  std::vector<FaultDev> descs;
+  for (sbiem_plan* p : ps) {
+    if (!p) return fail_global(SBIEM_EINVAL, "batch_create: NULL plan");
+    if (p->precision != prec) return fail_global(SBIEM_EINVAL, "batch_create: mixed precision");
+    if (!p->friction_set || !p->state_set || !p->dtd)
+      return fail_global(SBIEM_ENOTREADY, "batch_create: members need friction, state and dt");
+    if (p->device != plans[0]->device) return fail_global(SBIEM_EINVAL, "batch_create: one device");
+    dts.push_back(p->dtd);
+    dyns.push_back(p->dyn);
+    descs.push_back(make_fault_desc(p, p->dtd, p->dyn, p->V_pl, p->t0, 0));
+  }
+  std::string err;
+  Exec* ex = nullptr;
+  (void)hipSetDevice(plans[0]->device);
+  int st = build_exec(ps, dts, dyns, descs, prec, &ex, &err);
+  if (st) return fail_global(st, err);
+  sbiem_batch* b = new sbiem_batch();
+  b->plans = ps;
+  b->exec = ex;
+  b->stream = plans[0]->stream;
+  b->device = plans[0]->device;
+  for (sbiem_plan* p : ps) p->batch_refs++;
+  *out = b;
+  return SBIEM_OK;
+}
+
+int sbiem_batch_destroy(sbiem_batch* b) {
+  if (!b) return SBIEM_OK;
+  (void)hipSetDevice(b->device);
+  (void)hipStreamSynchronize(b->stream);
+  for (sbiem_plan* p : b->plans) p->batch_refs--;
+  delete b->exec;
+  delete b;
+  return SBIEM_OK;
+}
+
+int sbiem_batch_run(sbiem_batch* b, int64_t nsteps) {
+  if (!b || nsteps < 0) return fail_global(SBIEM_EINVAL, "batch_run: bad arguments");
+  hipError_t e = hipSetDevice(b->device);
+  // descriptors may have changed (theta mode, loads): refresh
+  for (size_t f = 0; f < b->plans.size() && !e; ++f) {
+    FaultDev d = make_fault_desc(b->plans[f], b->plans[f]->dtd, b->plans[f]->dyn, b->plans[f]->V_pl,
+                                 b->plans[f]->t0, b->exec->host_faults[f].tile_base);
+    if (std::memcmp(&d, &b->exec->host_faults[f], sizeof(d)) != 0) {
+      b->exec->host_faults[f] = d;
+      e = hipMemcpy(b->exec->d_faults + f, &d, sizeof(d), hipMemcpyHostToDevice);
+    }
+  }
+  if (!e)
+    e = run_steps(b->exec, nsteps, b->stream, b->profiling, &b->events, &b->prof_ms,
+                  &b->prof_launches);
+  if (!e) e = hipStreamSynchronize(b->stream);
+  if (e) return fail_global(SBIEM_EDEVICE, std::string("batch_run: ") + hipGetErrorString(e));
+  int first = SBIEM_OK;
+  for (sbiem_plan* p : b->plans) {
+    int st = check_failure(p);
+    if (st && first == SBIEM_OK) first = st;
+  }
+  return first;
+}
+
+int sbiem_batch_set_profiling(sbiem_batch* b, int on) {
+  if (!b) return fail_global(SBIEM_EINVAL, "NULL batch");
+  b->profiling = on != 0;
+  b->prof_ms = 0.0;
+  b->prof_launches = 0;
+  return SBIEM_OK;
+}
+
+int sbiem_batch_profile(sbiem_batch* b, double* conv_ms, int64_t* conv_launches,
+                        double* conv_bytes_per_launch) {
+  if (!b) return fail_global(SBIEM_EINVAL, "NULL batch");
+  if (conv_ms) *conv_ms = b->prof_ms;
+  if (conv_launches) *conv_launches = b->prof_launches;
+  if (conv_bytes_per_launch) *conv_bytes_per_launch = b->exec->conv_bytes;
+  b->prof_ms = 0.0;
+  b->prof_launches = 0;
+  return SBIEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,738 @@
+// Plan management of libsbiem: validation, curvature, windows, weight tables,
+// device buffers, state upload/download and the stress-only path.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <sstream>
+
+#include "internal.h"
+
+namespace sbiem {
+
+namespace {
+thread_local std::string g_last_error;
+const long double kPiL = 3.141592653589793238462643383279502884L;
+}  // namespace
+
+DeviceAllocator& allocator() {
+  static DeviceAllocator a;
+  return a;
+}
+
+void* dev_alloc(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  DeviceAllocator& a = allocator();
+  if (a.alloc) return a.alloc(bytes, a.ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void dev_free(void* p) {
+  if (!p) return;
+  DeviceAllocator& a = allocator();
+  if (a.release) a.release(p, a.ctx);
+  else (void)hipFree(p);
+}
+
+void* DevArena::get(size_t bytes) {
+  void* p = dev_alloc(bytes);
+  if (p) ptrs.push_back(p);
+  return p;
+}
+
+void DevArena::release_all() {
+  for (void* p : ptrs) dev_free(p);
+  ptrs.clear();
+}
+
+int fail(sbiem_plan* p, int status, const std::string& msg) {
+  if (p) p->last_error = msg;
+  else g_last_error = msg;
+  return status;
+}
+
+int fail_global(int status, const std::string& msg) {
+  g_last_error = msg;
+  return status;
+}
+
+int hip_fail(sbiem_plan* p, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(p, e == hipErrorOutOfMemory ? SBIEM_ENOMEM : SBIEM_EDEVICE, m);
+}
+
+namespace {
+
+bool all_finite(const double* x, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(x[i])) return false;
+  return true;
+}
+
+// In-place iterative radix-2 FFT in long double (sign -1: forward).
+void host_fft(std::vector<std::complex<long double>>& a, int sign) {
+  const size_t n = a.size();
+  for (size_t i = 1, j = 0; i < n; ++i) {
+    size_t bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  for (size_t len = 2; len <= n; len <<= 1) {
+    for (size_t i = 0; i < n; i += len) {
+      for (size_t k = 0; k < len / 2; ++k) {
+        long double ang = sign * 2.0L * kPiL * (long double)k / (long double)len;
+        std::complex<long double> w(cosl(ang), sinl(ang));
+        std::complex<long double> u = a[i + k], v = a[i + k + len / 2] * w;
+        a[i + k] = u + v;
+        a[i + k + len / 2] = u - v;
+      }
+    }
+  }
+}
+
+// kappa = h'' spectrally: IDFT(-k^2 DFT(h)) with the Nyquist term kept.
+std::vector<double> curvature_host(const double* h, int64_t N, double L) {
+  std::vector<std::complex<long double>> a(N);
+  for (int64_t i = 0; i < N; ++i) a[i] = h ? h[i] : 0.0;
+  host_fft(a, -1);
+  for (int64_t n = 0; n < N; ++n) {
+    int64_t ns = n <= N / 2 ? n : n - N;
+    long double k = 2.0L * kPiL * (long double)ns / (long double)L;
+    a[n] *= -k * k;
+  }
+  host_fft(a, +1);
+  std::vector<double> out(N);
+  for (int64_t i = 0; i < N; ++i) out[i] = (double)(a[i].real() / (long double)N);
+  return out;
+}
+
+template <typename T>
+T* upload(sbiem::DevArena& mem, const std::vector<T>& v, hipStream_t s, hipError_t* err) {
+  T* d = (T*)mem.get(v.size() * sizeof(T));
+  if (!d) {
+    *err = hipErrorOutOfMemory;
+    return nullptr;
+  }
+  if (!v.empty()) *err = hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+  return d;
+}
+
+}  // namespace
+
+// Window lengths M_n (n = 0..N/2) exactly as the windows are defined:
+// T_w = (L/c_s) min(1, k_c/|k|), k_c = 200/L, M = ceil(x - 1e-9 x), x = T_w/dt.
+std::vector<int> window_steps(int64_t N, double L, double cs, double dt) {
+  std::vector<int> M(N / 2 + 1);
+  const double kc = 200.0 / (1.0 * L);
+  for (int64_t n = 0; n <= N / 2; ++n) {
+    const double k = 2.0 * M_PI * (double)n / L;
+    const double ratio = k > kc ? kc / k : 1.0;
+    const double Tw = (1.0 * L / cs) * ratio;
+    const double x = Tw / dt;
+    double m = std::ceil(x - 1e-9 * x);
+    if (m < 1) m = 1;
+    M[n] = (int)m;
+  }
+  return M;
+}
+
+int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
+  *out = nullptr;
+  DtData* d = new DtData();
+  d->dt = dt;
+  const int64_t N = p->N;
+  const int half = (int)(N / 2);
+  d->M = window_steps(N, p->L, p->cs, dt);
+  d->Rn.assign(half + 1, 0);
+  d->ring_off.assign(half + 1, 0);
+  long long slots = 0;
+  for (int n = 1; n <= half; ++n) {
+    d->Rn[n] = d->M[n] - 1;
+    d->ring_off[n] = slots;
+    slots += d->Rn[n];
+  }
+  d->ring_slots = slots;
+  // conv tiles
+  const int tile = p->precision == SBIEM_FP32CONV ? kTileSlots32 : kTileSlots64;
+  d->tile_start.assign(half + 2, 0);
+  for (int n = 0; n <= half; ++n) {
+    d->tile_start[n] = (int)d->tiles.size();
+    if (n == 0) continue;
+    for (int p0 = 0; p0 < d->Rn[n]; p0 += tile)
+      d->tiles.push_back(Tile{0, n, p0, std::min(tile, d->Rn[n] - p0)});
+  }
+  d->tile_start[half + 1] = (int)d->tiles.size();
+
+  // per-mode constants
+  const long double cs = p->cs, cp = p->cp;
+  const long double theta_unit = kPiL * cs * (long double)dt / (long double)p->L;  // c_s k_1 dt / 2
+  std::vector<double> kabs(half + 1), w0T(half + 1), w0N(half + 1), w1T(half + 1), w1N(half + 1),
+      th(half + 1);
+  for (int n = 0; n <= half; ++n) {
+    kabs[n] = 2.0 * M_PI * (double)n / p->L;
+    const long double theta = theta_unit * n;  // c_s |k_n| dt / 2
+    long double CT, CN;
+    kernel_values(theta, cs, cp, &CT, &CN, nullptr, nullptr);
+    w0T[n] = (double)(dt * CT);
+    w0N[n] = (double)(dt * CN);
+    if (d->M[n] >= 2) {
+      kernel_values(3.0L * theta, cs, cp, &CT, &CN, nullptr, nullptr);
+      w1T[n] = (double)(dt * CT);
+      w1N[n] = (double)(dt * CN);
+    } else {
+      w1T[n] = w1N[n] = 0.0;
+    }
+    th[n] = (double)(theta / (long double)kTableStep);
+  }
+  hipError_t e = hipSuccess;
+  hipStream_t s = p->stream;
+  d->kabs = upload(d->mem, kabs, s, &e);
+  if (!e) d->w0T = upload(d->mem, w0T, s, &e);
+  if (!e) d->w0N = upload(d->mem, w0N, s, &e);
+  if (!e) d->w1T = upload(d->mem, w1T, s, &e);
+  if (!e) d->w1N = upload(d->mem, w1N, s, &e);
+  if (!e) d->theta_h = upload(d->mem, th, s, &e);
+  if (!e) d->d_Rn = upload(d->mem, d->Rn, s, &e);
+  if (!e) d->d_ring_off = upload(d->mem, d->ring_off, s, &e);
+  if (!e) d->d_tile_start = upload(d->mem, d->tile_start, s, &e);
+  const size_t rec = p->precision == SBIEM_FP32CONV ? 16 : 32;
+  if (!e) {
+    d->ring = d->mem.get((size_t)std::max<long long>(slots, 1) * rec);
+    if (!d->ring) e = hipErrorOutOfMemory;
+    else e = hipMemsetAsync(d->ring, 0, (size_t)std::max<long long>(slots, 1) * rec, s);
+  }
+  if (!e && p->precision == SBIEM_FP64) {
+    // FP64 weights in ring order: slot q of mode n holds the weights of lag
+    // j = R_n - q + 1 (q >= 1); q = 0 is the lag-1 slot, weight 0.
+    std::vector<double2> w(std::max<long long>(slots, 1));
+    for (int n = 1; n <= half; ++n) {
+      const int Rn = d->Rn[n];
+      if (Rn <= 0) continue;
+      const long long off = d->ring_off[n];
+      w[off] = make_double2(0.0, 0.0);
+      for (int q = 1; q < Rn; ++q) {
+        const int j = Rn - q + 1;
+        long double CT, CN;
+        kernel_values(theta_unit * (long double)n * (long double)(2 * j + 1), cs, cp, &CT, &CN,
+                      nullptr, nullptr);
+        w[off + q] = make_double2((double)(dt * CT), (double)(dt * CN));
+      }
+    }
+    d->wrev = upload(d->mem, w, s, &e);
+  }
+  if (!e && p->precision == SBIEM_FP32CONV) {
+    // Hermite table on T = i h covering every lag (plus the skipped slot).
+    double Tmax = 0.0;
+    for (int n = 1; n <= half; ++n)
+      Tmax = std::max(Tmax, (double)(theta_unit * n) * (2.0 * d->M[n] + 3.0));
+    const int K = (int)std::ceil(Tmax / kTableStep) + 3;
+    if ((size_t)K * sizeof(float4) > (size_t)kMaxDynLds) {
+      e = hipErrorInvalidValue;
+    } else {
+      std::vector<float4> tab(K);
+      for (int i = 0; i < K; ++i) {
+        long double CT, CN, dCT, dCN;
+        kernel_values((long double)i * kTableStep, cs, cp, &CT, &CN, &dCT, &dCN);
+        tab[i] = make_float4((float)(dt * CT), (float)(dt * kTableStep * dCT), (float)(dt * CN),
+                             (float)(dt * kTableStep * dCN));
+      }
+      d->table_len = K;
+      d->table = upload(d->mem, tab, s, &e);
+    }
+  }
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) {
+    delete d;
+    return hip_fail(p, e, "building the weight tables");
+  }
+  *out = d;
+  return SBIEM_OK;
+}
+
+int build_dyn_data(sbiem_plan* p, DynData** out) {
+  *out = nullptr;
+  DynData* d = new DynData();
+  const size_t N = (size_t)p->N, M = (size_t)(p->N / 2 + 1);
+  bool ok = true;
+  auto el = [&](double** ptr) {
+    *ptr = (double*)d->mem.get(N * sizeof(double));
+    ok = ok && *ptr;
+  };
+  auto sp = [&](double2** ptr) {
+    *ptr = (double2*)d->mem.get(M * sizeof(double2));
+    ok = ok && *ptr;
+  };
+  for (int k = 0; k < 2; ++k) {
+    el(&d->slip[k]);
+    el(&d->V[k]);
+    el(&d->theta[k]);
+    el(&d->thd[k]);
+    el(&d->tau_el[k]);
+    el(&d->sigma_el[k]);
+  }
+  el(&d->V1);
+  el(&d->thd1);
+  sp(&d->u_hat);
+  sp(&d->g_hat);
+  sp(&d->v_hat0);
+  sp(&d->gv_hat0);
+  sp(&d->v_hat1);
+  sp(&d->gv_hat1);
+  sp(&d->hprev_v);
+  sp(&d->hprev_g);
+  sp(&d->S_T);
+  sp(&d->S_N);
+  d->zbuf = d->mem.get(N * sizeof(double2));
+  d->step = (long long*)d->mem.get(sizeof(long long) * 2);
+  d->err = (int*)d->mem.get(sizeof(int) * 4);
+  ok = ok && d->zbuf && d->step && d->err;
+  if (!ok) {
+    delete d;
+    return fail(p, SBIEM_ENOMEM, "device allocation of the state buffers failed");
+  }
+  d->err_count = d->err + 1;
+  d->err_index = d->err + 2;
+  hipStream_t s = p->stream;
+  hipError_t e = hipSuccess;
+  // zero everything that is read before being written
+  for (int k = 0; k < 2 && !e; ++k) {
+    e = hipMemsetAsync(d->tau_el[k], 0, N * sizeof(double), s);
+    if (!e) e = hipMemsetAsync(d->sigma_el[k], 0, N * sizeof(double), s);
+  }
+  double2* spec[] = {d->u_hat, d->g_hat, d->v_hat0, d->gv_hat0, d->v_hat1,
+                     d->gv_hat1, d->hprev_v, d->hprev_g, d->S_T, d->S_N};
+  for (double2* q : spec)
+    if (!e) e = hipMemsetAsync(q, 0, M * sizeof(double2), s);
+  if (!e) e = hipMemsetAsync(d->step, 0, sizeof(long long) * 2, s);
+  const int init[4] = {0, 0, 0x7fffffff, 0};
+  if (!e) e = hipMemcpyAsync(d->err, init, sizeof(init), hipMemcpyHostToDevice, s);
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) {
+    delete d;
+    return hip_fail(p, e, "initialising the state buffers");
+  }
+  *out = d;
+  return SBIEM_OK;
+}
+
+FaultDev make_fault_desc(sbiem_plan* p, DtData* dtd, DynData* dyn, double V_pl, double t0,
+                         int tile_base) {
+  FaultDev f;
+  std::memset(&f, 0, sizeof(f));
+  f.N = (int)p->N;
+  f.log2N = p->log2N;
+  f.nmodes = (int)(p->N / 2);
+  f.theta_mode = p->theta_mode;
+  f.L = p->L;
+  f.mu = p->mu;
+  f.r = p->r;
+  f.cs = p->cs;
+  f.dt = dtd ? dtd->dt : 0.0;
+  f.eta_rad = p->mu / (2.0 * p->cs);
+  f.V_pl = V_pl;
+  f.Dc = p->Dc;
+  f.V_ref = p->V_ref;
+  f.f0 = p->f0;
+  f.tau_rate = p->tau_rate;
+  f.t0 = t0;
+  f.a = p->a;
+  f.b = p->b;
+  f.sigma_load = p->sigma_load;
+  f.tau_load = p->tau_load;
+  f.kappa = p->kappa;
+  for (int k = 0; k < 2; ++k) {
+    f.slip[k] = dyn->slip[k];
+    f.V[k] = dyn->V[k];
+    f.theta[k] = dyn->theta[k];
+    f.thd[k] = dyn->thd[k];
+    f.tau_el[k] = dyn->tau_el[k];
+    f.sigma_el[k] = dyn->sigma_el[k];
+  }
+  f.V1 = dyn->V1;
+  f.thd1 = dyn->thd1;
+  f.u_hat = dyn->u_hat;
+  f.g_hat = dyn->g_hat;
+  f.v_hat0 = dyn->v_hat0;
+  f.gv_hat0 = dyn->gv_hat0;
+  f.v_hat1 = dyn->v_hat1;
+  f.gv_hat1 = dyn->gv_hat1;
+  f.hprev_v = dyn->hprev_v;
+  f.hprev_g = dyn->hprev_g;
+  f.S_T = dyn->S_T;
+  f.S_N = dyn->S_N;
+  if (dtd) {
+    f.kabs = dtd->kabs;
+    f.w0T = dtd->w0T;
+    f.w0N = dtd->w0N;
+    f.w1T = dtd->w1T;
+    f.w1N = dtd->w1N;
+    f.Rn = dtd->d_Rn;
+    f.ring_off = dtd->d_ring_off;
+    f.theta_h = dtd->theta_h;
+    f.tile_start = dtd->d_tile_start;
+    f.ring = dtd->ring;
+    f.wrev = dtd->wrev;
+  }
+  f.tile_base = tile_base;
+  f.zbuf = dyn->zbuf;
+  f.twiddle = p->twiddle;
+  f.step = dyn->step;
+  f.err = dyn->err;
+  f.err_count = dyn->err_count;
+  f.err_index = dyn->err_index;
+  return f;
+}
+
+}  // namespace sbiem
+
+using namespace sbiem;
+
+namespace {
+
+int check_plan(sbiem_plan* p) {
+  if (!p) return fail_global(SBIEM_EINVAL, "NULL plan");
+  return SBIEM_OK;
+}
+
+// The spectral kernels keep one N-point complex transform in LDS.
+int check_fft_fits(sbiem_plan* p) {
+  const int64_t lim = p->precision == SBIEM_FP32CONV ? 16384 : 8192;
+  if (p->N > lim)
+    return fail(p, SBIEM_EINVAL,
+                p->precision == SBIEM_FP64 ? "FP64 transforms hold at most 8192 points: use SBIEM_FP32CONV"
+                                           : "FP32 transforms hold at most 16384 points");
+  return SBIEM_OK;
+}
+
+int ensure_device(sbiem_plan* p) {
+  hipError_t e = hipSetDevice(p->device);
+  if (e) return hip_fail(p, e, "hipSetDevice");
+  return SBIEM_OK;
+}
+
+int upload_twiddles(sbiem_plan* p) {
+  const int64_t N = p->N;
+  std::vector<double2> t64(N);
+  std::vector<float2> t32(N);
+  for (int64_t t = 0; t < N; ++t) {
+    long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)t / (long double)N;
+    t64[t] = make_double2((double)cosl(ang), (double)sinl(ang));
+    t32[t] = make_float2((float)cosl(ang), (float)sinl(ang));
+  }
+  hipError_t e = hipSuccess;
+  if (!p->twiddle64) p->twiddle64 = upload(p->mem, t64, p->stream, &e);
+  if (e) return hip_fail(p, e, "uploading twiddles");
+  if (p->precision == SBIEM_FP32CONV) {
+    p->twiddle = upload(p->mem, t32, p->stream, &e);
+  } else {
+    p->twiddle = p->twiddle64;
+  }
+  if (!e) e = hipStreamSynchronize(p->stream);
+  if (e) return hip_fail(p, e, "uploading twiddles");
+  return SBIEM_OK;
+}
+
+}  // namespace
+
+// Forward declarations of exec.cpp helpers
+namespace sbiem {
+int rebuild_exec(sbiem_plan* p);
+int refresh_desc(sbiem_plan* p);
+int reset_history(sbiem_plan* p);
+int rebase_state(sbiem_plan* p);
+int spectral_state_from_host(sbiem_plan* p, const double* slip, const double* V, double t);
+int spectral_state_from_device(sbiem_plan* p);
+}  // namespace sbiem
+
+extern "C" {
+
+int sbiem_abi_version(void) { return SBIEM_ABI_VERSION; }
+
+const char* sbiem_status_string(int status) {
+  switch (status) {
+    case SBIEM_OK: return "SBIEM_OK";
+    case SBIEM_EINVAL: return "SBIEM_EINVAL";
+    case SBIEM_ENOMEM: return "SBIEM_ENOMEM";
+    case SBIEM_EDEVICE: return "SBIEM_EDEVICE";
+    case SBIEM_ENEWTON: return "SBIEM_ENEWTON";
+    case SBIEM_ESTATE: return "SBIEM_ESTATE";
+    case SBIEM_EOPEN: return "SBIEM_EOPEN";
+    case SBIEM_ENOTREADY: return "SBIEM_ENOTREADY";
+    default: return "unknown status";
+  }
+}
+
+const char* sbiem_last_error(const sbiem_plan* p) {
+  return p ? p->last_error.c_str() : g_last_error.c_str();
+}
+
+int sbiem_set_allocator(void* (*alloc)(size_t, void*), void (*release)(void*, void*), void* ctx) {
+  if ((alloc == nullptr) != (release == nullptr))
+    return fail_global(SBIEM_EINVAL, "allocator: give both functions or neither");
+  DeviceAllocator& a = allocator();
+  a.alloc = alloc;
+  a.release = release;
+  a.ctx = ctx;
+  return SBIEM_OK;
+}
+
+int sbiem_kernel_eval(double cs, double cp, const double* T, int64_t n, double* CT, double* CN,
+                      double* dCT, double* dCN) {
+  if (!(cs > 0) || !(cp > cs) || n < 0 || (n > 0 && !T))
+    return fail_global(SBIEM_EINVAL, "kernel_eval: need 0 < cs < cp and T");
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(T[i] >= 0) || !std::isfinite(T[i])) return fail_global(SBIEM_EINVAL, "kernel_eval: T must be finite and >= 0");
+    long double a, b, c, d;
+    kernel_values(T[i], cs, cp, &a, &b, &c, &d);
+    if (CT) CT[i] = (double)a;
+    if (CN) CN[i] = (double)b;
+    if (dCT) dCT[i] = (double)c;
+    if (dCN) dCN[i] = (double)d;
+  }
+  return SBIEM_OK;
+}
+
+int sbiem_plan_create(sbiem_plan** out, int64_t N, double L, double mu, double nu, double cs,
+                      double cp, const double* h) {
+  if (!out) return fail_global(SBIEM_EINVAL, "plan_create: NULL out");
+  *out = nullptr;
+  if (N < 8 || N > (1 << 22) || (N & (N - 1)))
+    return fail_global(SBIEM_EINVAL, "plan_create: N must be a power of two in [8, 2^22]");
+  if (!(L > 0) || !(mu > 0) || !(cs > 0) || !(cp > cs) || !std::isfinite(L) || !std::isfinite(mu) ||
+      !std::isfinite(cp))
+    return fail_global(SBIEM_EINVAL, "plan_create: need L, mu > 0 and 0 < cs < cp");
+  if (!(nu > 0 && nu < 0.5)) return fail_global(SBIEM_EINVAL, "plan_create: need 0 < nu < 0.5");
+  const double q = (cp * cp) / (cs * cs);
+  const double nu_w = (q - 2.0) / (2.0 * (q - 1.0));
+  if (std::fabs(nu - nu_w) > 1e-3) {
+    std::ostringstream m;
+    m << "plan_create: nu = " << nu << " inconsistent with cp/cs (nu = " << nu_w << ")";
+    return fail_global(SBIEM_EINVAL, m.str());
+  }
+  if (h && !all_finite(h, N)) return fail_global(SBIEM_EINVAL, "plan_create: h must be finite");
+  const int maxN = 16384;
+  if (N > maxN)
+    return fail_global(SBIEM_EINVAL, "plan_create: N above 16384 needs the multi-workgroup FFT (not built)");
+
+  sbiem_plan* p = new sbiem_plan();
+  hipError_t e = hipGetDevice(&p->device);
+  if (e) {
+    delete p;
+    return fail_global(SBIEM_EDEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
+  }
+  p->N = N;
+  p->log2N = 0;
+  while ((int64_t(1) << p->log2N) < N) ++p->log2N;
+  p->L = L;
+  p->mu = mu;
+  p->nu = nu;
+  p->cs = cs;
+  p->cp = cp;
+  p->r = (cs * cs) / (cp * cp);
+  p->kappa_host = curvature_host(h, N, L);
+  const size_t bytes = (size_t)N * sizeof(double);
+  p->kappa = (double*)p->mem.get(bytes);
+  p->a = (double*)p->mem.get(bytes);
+  p->b = (double*)p->mem.get(bytes);
+  p->sigma_load = (double*)p->mem.get(bytes);
+  p->tau_load = (double*)p->mem.get(bytes);
+  if (!p->kappa || !p->a || !p->b || !p->sigma_load || !p->tau_load) {
+    delete p;
+    return fail_global(SBIEM_ENOMEM, "plan_create: device allocation failed");
+  }
+  e = hipMemcpy(p->kappa, p->kappa_host.data(), bytes, hipMemcpyHostToDevice);
+  if (e) {
+    delete p;
+    return fail_global(SBIEM_EDEVICE, std::string("plan_create: ") + hipGetErrorString(e));
+  }
+  int st = upload_twiddles(p);
+  if (st) {
+    std::string m = p->last_error;
+    delete p;
+    return fail_global(st, m);
+  }
+  st = build_dyn_data(p, &p->dyn);
+  if (!st) {
+    p->d_desc = (FaultDev*)p->mem.get(sizeof(FaultDev));
+    if (!p->d_desc) st = fail(p, SBIEM_ENOMEM, "plan_create: device allocation failed");
+  }
+  if (!st) st = refresh_desc(p);
+  if (st) {
+    std::string m = p->last_error;
+    delete p;
+    return fail_global(st, m);
+  }
+  *out = p;
+  return SBIEM_OK;
+}
+
+int sbiem_plan_destroy(sbiem_plan* p) {
+  if (!p) return SBIEM_OK;
+  if (p->batch_refs > 0) return fail(p, SBIEM_EINVAL, "plan is still used by a batch");
+  (void)hipSetDevice(p->device);
+  (void)hipStreamSynchronize(p->stream);
+  delete p->exec;
+  delete p->dtd;
+  delete p->dyn;
+  delete p;
+  return SBIEM_OK;
+}
+
+int sbiem_set_precision(sbiem_plan* p, int mode) {
+  if (int s = check_plan(p)) return s;
+  if (mode != SBIEM_FP64 && mode != SBIEM_FP32CONV) return fail(p, SBIEM_EINVAL, "unknown precision");
+  if (p->dtd) return fail(p, SBIEM_EINVAL, "precision must be chosen before the time step is set");
+  if (mode == p->precision) return SBIEM_OK;
+  if (int s = ensure_device(p)) return s;
+  p->precision = mode;
+  if (int st = upload_twiddles(p)) return st;
+  return refresh_desc(p);
+}
+
+int sbiem_set_theta_mode(sbiem_plan* p, int mode) {
+  if (int s = check_plan(p)) return s;
+  if (mode != SBIEM_THETA_PAPER && mode != SBIEM_THETA_EXP) return fail(p, SBIEM_EINVAL, "unknown theta mode");
+  p->theta_mode = mode;
+  return refresh_desc(p);
+}
+
+int sbiem_set_friction(sbiem_plan* p, const double* a, const double* b, double Dc, double V_ref,
+                       double f0, const double* sigma_load, const double* tau_load,
+                       double tau_load_rate, double V_pl) {
+  if (int s = check_plan(p)) return s;
+  const int64_t N = p->N;
+  if (!a || !b || !sigma_load || !tau_load) return fail(p, SBIEM_EINVAL, "set_friction: NULL array");
+  if (!all_finite(a, N) || !all_finite(b, N) || !all_finite(sigma_load, N) || !all_finite(tau_load, N))
+    return fail(p, SBIEM_EINVAL, "set_friction: arrays must be finite");
+  for (int64_t i = 0; i < N; ++i)
+    if (!(a[i] > 0)) return fail(p, SBIEM_EINVAL, "set_friction: a must be > 0");
+  if (!(Dc > 0) || !(V_ref > 0) || !std::isfinite(f0) || !std::isfinite(tau_load_rate) ||
+      !(V_pl >= 0) || !std::isfinite(Dc) || !std::isfinite(V_ref) || !std::isfinite(V_pl))
+    return fail(p, SBIEM_EINVAL, "set_friction: need Dc, V_ref > 0, V_pl >= 0, finite f0 and rate");
+  if (int s = ensure_device(p)) return s;
+  const size_t bytes = (size_t)N * sizeof(double);
+  hipError_t e = hipMemcpyAsync(p->a, a, bytes, hipMemcpyHostToDevice, p->stream);
+  if (!e) e = hipMemcpyAsync(p->b, b, bytes, hipMemcpyHostToDevice, p->stream);
+  if (!e) e = hipMemcpyAsync(p->sigma_load, sigma_load, bytes, hipMemcpyHostToDevice, p->stream);
+  if (!e) e = hipMemcpyAsync(p->tau_load, tau_load, bytes, hipMemcpyHostToDevice, p->stream);
+  if (!e) e = hipStreamSynchronize(p->stream);
+  if (e) return hip_fail(p, e, "set_friction");
+  p->Dc = Dc;
+  p->V_ref = V_ref;
+  p->f0 = f0;
+  p->tau_rate = tau_load_rate;
+  const bool reframe = p->state_set && V_pl != p->V_pl;
+  p->V_pl = V_pl;
+  p->friction_set = true;
+  if (int st = refresh_desc(p)) return st;
+  // the spectral state is kept in the backslip frame of V_pl
+  if (reframe) return spectral_state_from_device(p);
+  return SBIEM_OK;
+}
+
+int sbiem_set_state(sbiem_plan* p, const double* slip, const double* V, const double* theta, double t) {
+  if (int s = check_plan(p)) return s;
+  if (!p->friction_set) return fail(p, SBIEM_ENOTREADY, "set_state: set_friction first");
+  if (int s = check_fft_fits(p)) return s;
+  const int64_t N = p->N;
+  if (!slip || !V || !theta) return fail(p, SBIEM_EINVAL, "set_state: NULL array");
+  if (!all_finite(slip, N) || !all_finite(V, N) || !all_finite(theta, N) || !std::isfinite(t))
+    return fail(p, SBIEM_EINVAL, "set_state: values must be finite");
+  for (int64_t i = 0; i < N; ++i)
+    if (!(V[i] > 0) || !(theta[i] > 0)) return fail(p, SBIEM_EINVAL, "set_state: V and theta must be > 0");
+  if (int s = ensure_device(p)) return s;
+  std::vector<double> thd(N);
+  for (int64_t i = 0; i < N; ++i) thd[i] = 1.0 - theta[i] * V[i] / p->Dc;
+  DynData* d = p->dyn;
+  const size_t bytes = (size_t)N * sizeof(double);
+  hipStream_t s = p->stream;
+  hipError_t e = hipMemcpyAsync(d->slip[0], slip, bytes, hipMemcpyHostToDevice, s);
+  if (!e) e = hipMemcpyAsync(d->V[0], V, bytes, hipMemcpyHostToDevice, s);
+  if (!e) e = hipMemcpyAsync(d->theta[0], theta, bytes, hipMemcpyHostToDevice, s);
+  if (!e) e = hipMemcpyAsync(d->thd[0], thd.data(), bytes, hipMemcpyHostToDevice, s);
+  for (int k = 0; k < 2 && !e; ++k) {
+    e = hipMemsetAsync(d->tau_el[k], 0, bytes, s);
+    if (!e) e = hipMemsetAsync(d->sigma_el[k], 0, bytes, s);
+  }
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return hip_fail(p, e, "set_state");
+  p->t0 = t;
+  p->state_set = true;
+  p->last_fail_count = 0;
+  p->last_fail_index = -1;
+  if (int st = reset_history(p)) return st;
+  return spectral_state_from_host(p, slip, V, t);
+}
+
+int sbiem_get_state(sbiem_plan* p, double* slip, double* V, double* theta, double* tau_el,
+                    double* sigma_el, double* t) {
+  if (int s = check_plan(p)) return s;
+  if (!p->state_set) return fail(p, SBIEM_ENOTREADY, "get_state: no state set");
+  if (int s = ensure_device(p)) return s;
+  DynData* d = p->dyn;
+  long long step = 0;
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (!e) e = hipMemcpy(&step, d->step, sizeof(step), hipMemcpyDeviceToHost);
+  if (e) return hip_fail(p, e, "get_state");
+  const int cur = (int)(step & 1);
+  const size_t bytes = (size_t)p->N * sizeof(double);
+  if (!e && slip) e = hipMemcpy(slip, d->slip[cur], bytes, hipMemcpyDeviceToHost);
+  if (!e && V) e = hipMemcpy(V, d->V[cur], bytes, hipMemcpyDeviceToHost);
+  if (!e && theta) e = hipMemcpy(theta, d->theta[cur], bytes, hipMemcpyDeviceToHost);
+  if (!e && tau_el) e = hipMemcpy(tau_el, d->tau_el[cur], bytes, hipMemcpyDeviceToHost);
+  if (!e && sigma_el) e = hipMemcpy(sigma_el, d->sigma_el[cur], bytes, hipMemcpyDeviceToHost);
+  if (e) return hip_fail(p, e, "get_state");
+  if (t) *t = p->t0 + (double)step * (p->dtd ? p->dtd->dt : 0.0);
+  return SBIEM_OK;
+}
+
+int sbiem_get_curvature(const sbiem_plan* p, double* kappa) {
+  if (!p) return fail_global(SBIEM_EINVAL, "NULL plan");
+  if (!kappa) return fail(const_cast<sbiem_plan*>(p), SBIEM_EINVAL, "NULL kappa");
+  std::memcpy(kappa, p->kappa_host.data(), (size_t)p->N * sizeof(double));
+  return SBIEM_OK;
+}
+
+int sbiem_window_lengths(const sbiem_plan* p, double dt, int64_t* M) {
+  if (!p) return fail_global(SBIEM_EINVAL, "NULL plan");
+  if (!(dt > 0) || !M) return fail(const_cast<sbiem_plan*>(p), SBIEM_EINVAL, "window_lengths: need dt > 0");
+  std::vector<int> m = window_steps(p->N, p->L, p->cs, dt);
+  for (int64_t n = 1; n <= p->N / 2; ++n) M[n - 1] = m[n];
+  return SBIEM_OK;
+}
+
+int sbiem_set_dt(sbiem_plan* p, double dt) {
+  if (int s = check_plan(p)) return s;
+  if (int s = check_fft_fits(p)) return s;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(p, SBIEM_EINVAL, "set_dt: need dt > 0");
+  if (int s = ensure_device(p)) return s;
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e) return hip_fail(p, e, "set_dt");
+  // keep the current state: move it to buffer 0 at t0 = current time
+  if (p->state_set && p->dtd) {
+    if (int st = rebase_state(p)) return st;
+  }
+  DtData* d = nullptr;
+  if (int s = build_dt_data(p, dt, &d)) return s;
+  delete p->exec;
+  p->exec = nullptr;
+  delete p->dtd;
+  p->dtd = d;
+  if (int st = rebuild_exec(p)) return st;
+  if (int st = reset_history(p)) return st;
+  if (p->state_set) return spectral_state_from_device(p);
+  return SBIEM_OK;
+}
+
+int sbiem_set_stream(sbiem_plan* p, void* hip_stream) {
+  if (int s = check_plan(p)) return s;
+  (void)hipStreamSynchronize(p->stream);
+  p->stream = (hipStream_t)hip_stream;
+  if (p->exec) p->exec->drop_graph();
+  return SBIEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,194 @@
+"""GPU parity of the HIP path against the CPU oracle (through the C ABI).
+
+Tolerances (norm-wise relative, max over the compared steps): 1e-10 in
+FP64; 1e-5 on tau^el and sigma^el in the FP32 convolution path.
+"""
+
+import numpy as np
+import pytest
+
+from scenarios import (DT_10KM, Scenario, golden_table, make_oracle, make_plan, rel,
+                       rough_10km, seamount_h, MU, NU, CS, CP)
+from sbiem_inputs import FrictionSpec
+
+pytestmark = pytest.mark.gpu
+
+
+def _pkg():
+    import paper_2107_03550_amd as pkg
+    return pkg
+
+
+def _history(N, nt, seed, scale=1e-3):
+    rng = np.random.default_rng(seed)
+    x = np.arange(N) / N
+    rates = rng.random((nt, N)) * scale * (1 + np.cos(2 * np.pi * x))[None, :]
+    base = 0.3 * scale * (1.0 + 0.5 * np.sin(2 * np.pi * 3 * x) + 0.2 * rng.standard_normal(N))
+    return np.vstack([np.zeros((1, N)), np.cumsum(rates, axis=0)]) + base[None, :]
+
+
+# ---------------------------------------------------------------- windows
+@pytest.mark.parametrize("N,L", [(256, 10e3), (8192, 80e3), (1024, 10240.0)])
+def test_window_lengths_match_oracle(N, L):
+    from oracle.windows import window_steps
+    pkg = _pkg()
+    p = pkg.Plan(N, L, MU, NU, CS, CP)
+    dt = 0.5 * L / N / CS
+    M = p.window_lengths(dt)
+    ref = window_steps(N, L, CS, dt)[1:N // 2 + 1]
+    assert np.array_equal(M, ref)
+
+
+# ---------------------------------------------------------------- stress path
+@pytest.mark.parametrize("N,nt", [(32, 600), (256, 700), (256, 3), (64, 0), (64, 1)])
+def test_stress_fp64_matches_oracle(N, nt):
+    from oracle.spectral import curvature
+    from oracle.stress import stress_from_history
+    from oracle.windows import midpoint_weights
+    pkg = _pkg()
+    L, dt = 10e3, DT_10KM
+    h = rough_10km(N, seed=4, alpha=3e-3)
+    hist = _history(N, nt, seed=N + nt)
+    p = pkg.Plan(N, L, MU, NU, CS, CP, h)
+    tau, sig = p.stress(hist, dt)
+    w = midpoint_weights(N, L, CS, CP, dt, golden_table())
+    rt, rs = stress_from_history(hist, dt, L, MU, CS, CP, curvature(h, L), w)
+    assert rel(tau, rt) < 1e-10 and rel(sig, rs) < 1e-10, (rel(tau, rt), rel(sig, rs))
+
+
+@pytest.mark.parametrize("N,nt", [(1024, 300), (512, 1100)])
+def test_stress_fp32_matches_oracle(N, nt):
+    from oracle.spectral import curvature
+    from oracle.stress import stress_from_history
+    from oracle.windows import midpoint_weights
+    pkg = _pkg()
+    L = 10.0 * N
+    dt = 0.5 * (L / N) / CS
+    h = rough_10km(N, seed=9, alpha=5e-3) * (L / 10e3)
+    hist = _history(N, nt, seed=nt)
+    p = pkg.Plan(N, L, MU, NU, CS, CP, h)
+    p.set_precision(pkg.SBIEM_FP32CONV)
+    tau, sig = p.stress(hist, dt)
+    w = midpoint_weights(N, L, CS, CP, dt)
+    rt, rs = stress_from_history(hist, dt, L, MU, CS, CP, curvature(h, L), w)
+    assert rel(tau, rt) < 1e-5 and rel(sig, rs) < 1e-5, (rel(tau, rt), rel(sig, rs))
+
+
+# ---------------------------------------------------------------- time step
+def test_step_fp64_rough_N256_2000_steps():
+    """The N = 256 rough-fault FP64 workload, 2000 fixed steps."""
+    pkg = _pkg()
+    sc = Scenario(256, 10e3, DT_10KM, rough_10km(256, seed=0, alpha=1e-3))
+    p = make_plan(sc, pkg.SBIEM_FP64)
+    o = make_oracle(sc, golden_table())
+    worst = {k: 0.0 for k in ("slip", "V", "theta", "tau_el", "sigma_el")}
+    done = 0
+    for chunk in (1, 9, 90, 400, 500, 1000):
+        p.run(sc.dt, chunk)
+        o.run(chunk)
+        done += chunk
+        g = p.get_state()
+        ref = dict(slip=o.slip, V=o.V, theta=o.theta, tau_el=o.tau_el, sigma_el=o.sigma_el)
+        for k in worst:
+            worst[k] = max(worst[k], rel(g[k], ref[k]))
+        assert abs(g["t"] - o.t) < 1e-9
+    assert done == 2000 and p.steps_done() == 2000
+    assert all(v < 1e-10 for v in worst.values()), worst
+
+
+def test_step_fp64_dynamic_rupture():
+    """Strong overstress: slip rates up to m/s, exact theta update."""
+    pkg = _pkg()
+    spec = FrictionSpec(overstress=9e6, w_nuc=1500.0)
+    sc = Scenario(128, 10e3, DT_10KM, rough_10km(128, seed=2, alpha=3e-3), spec=spec,
+                  theta_mode="exp", consistent_V0=True)
+    p = make_plan(sc, pkg.SBIEM_FP64)
+    o = make_oracle(sc, golden_table())
+    worst = 0.0
+    for _ in range(6):
+        p.run(sc.dt, 50)
+        o.run(50)
+        g = p.get_state()
+        for k, ref in (("slip", o.slip), ("V", o.V), ("tau_el", o.tau_el), ("sigma_el", o.sigma_el)):
+            worst = max(worst, rel(g[k], ref))
+    assert o.V.max() > 1e-2
+    assert worst < 1e-9, worst
+
+
+def test_step_fp32_dynamic_rupture_N1024():
+    pkg = _pkg()
+    N = 1024
+    L = 10.0 * N
+    spec = FrictionSpec(overstress=9e6, w_nuc=1500.0)
+    h = rough_10km(N, seed=3, alpha=3e-3) * (L / 10e3)
+    sc = Scenario(N, L, 0.5 * (L / N) / CS, h, spec=spec, theta_mode="exp", consistent_V0=True)
+    p = make_plan(sc, pkg.SBIEM_FP32CONV)
+    o = make_oracle(sc)
+    worst = {"tau_el": 0.0, "sigma_el": 0.0, "slip": 0.0, "V": 0.0}
+    for _ in range(4):
+        p.run(sc.dt, 50)
+        o.run(50)
+        g = p.get_state()
+        for k, ref in (("slip", o.slip), ("V", o.V), ("tau_el", o.tau_el), ("sigma_el", o.sigma_el)):
+            worst[k] = max(worst[k], rel(g[k], ref))
+    print("fp32 N=1024 rupture worst relative errors", worst)
+    assert worst["tau_el"] < 1e-5 and worst["sigma_el"] < 1e-5, worst
+
+
+# ---------------------------------------------------------------- engine properties
+def test_run_with_graph_equals_single_steps_bitwise():
+    pkg = _pkg()
+    sc = Scenario(256, 10e3, DT_10KM, rough_10km(256, seed=1), theta_mode="exp",
+                  spec=FrictionSpec(overstress=8e6), consistent_V0=True)
+    a = make_plan(sc, pkg.SBIEM_FP32CONV)
+    b = make_plan(sc, pkg.SBIEM_FP32CONV)
+    a.run(sc.dt, 37)            # two graph replays + 5 single launches
+    for _ in range(37):
+        b.step(sc.dt)
+    ga, gb = a.get_state(), b.get_state()
+    for k in ("slip", "V", "theta", "tau_el", "sigma_el"):
+        assert np.array_equal(ga[k], gb[k]), k
+
+
+def test_failure_leaves_state_at_start_of_step():
+    pkg = _pkg()
+    sc = Scenario(64, 10e3, DT_10KM, rough_10km(64, seed=5, alpha=5e-2))
+    p = make_plan(sc, pkg.SBIEM_FP64)
+    p.run(sc.dt, 3)
+    before = p.get_state()
+    fr_sigma = np.full(64, 1.0)     # nearly no normal load: the curvature term opens the fault
+    from scenarios import fields
+    fr = fields(sc)
+    # a large slip makes the normal traction change exceed the tiny load
+    p.set_friction(fr["a"], fr["b"], fr["Dc"], fr["V_ref"], fr["f0"], -fr_sigma,
+                   fr["tau_load"], 0.0, fr["V_pl"])
+    st = p.run_status(sc.dt, 20)
+    assert st == -6
+    cnt, idx = p.failures()
+    assert cnt > 0 and 0 <= idx < 64
+    after = p.get_state()
+    assert p.steps_done() == 3
+    for k in ("slip", "V", "theta"):
+        assert np.array_equal(before[k], after[k])
+
+
+def test_batch_matches_individual_plans_bitwise():
+    pkg = _pkg()
+    plans_a, plans_b = [], []
+    for N, seed in ((256, 1), (1024, 2), (512, 3)):
+        L = 10.0 * N
+        sc = Scenario(N, L, 0.5 * 10.0 / CS, rough_10km(N, seed=seed, alpha=4e-3) * (L / 10e3),
+                      spec=FrictionSpec(overstress=8e6, w_nuc=300.0), theta_mode="exp",
+                      consistent_V0=True)
+        plans_a.append(make_plan(sc, pkg.SBIEM_FP32CONV))
+        plans_b.append(make_plan(sc, pkg.SBIEM_FP32CONV))
+    dt = 0.5 * 10.0 / CS
+    batch = pkg.Batch(plans_a)
+    batch.run(40)
+    for p in plans_b:
+        p.run(dt, 40)
+    for pa, pb in zip(plans_a, plans_b):
+        ga, gb = pa.get_state(), pb.get_state()
+        for k in ("slip", "V", "theta", "tau_el", "sigma_el"):
+            assert np.array_equal(ga[k], gb[k]), k
+    batch.close()

@@ -1,0 +1,84 @@
+"""Host-side checks of the HIP library (no GPU): it loads, exports every
+symbol of include/sbiem.h, validates arguments, and its extended-precision
+kernel tables agree with the oracle's 30-digit evaluation."""
+
+import ctypes
+import os
+import re
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CS, CP = 3464.0, 6000.0
+
+
+def _header_names():
+    with open(os.path.join(ROOT, "include", "sbiem.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(sbiem_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2107_03550_amd as pkg
+    names = _header_names()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(pkg.lib, n), n
+    assert set(names) == set(pkg.EXPORTED_NAMES)
+    assert pkg.abi_version() == 1
+
+
+def test_plan_create_validates_before_touching_the_device():
+    import paper_2107_03550_amd as pkg
+    lib = pkg.lib
+    h = ctypes.c_void_p()
+    bad = [
+        (100, 1e4, 30e9, 0.25, CS, CP),      # not a power of two
+        (256, 1e4, 30e9, 0.30, CS, CP),      # nu inconsistent with the speeds
+        (256, 1e4, 30e9, 0.25, CP, CS),      # cs > cp
+        (256, -1.0, 30e9, 0.25, CS, CP),     # L <= 0
+    ]
+    for args in bad:
+        st = lib.sbiem_plan_create(ctypes.byref(h), *args, None)
+        assert st == -1 and h.value is None
+        assert lib.sbiem_last_error(None)
+    hh = np.zeros(256)
+    hh[3] = np.nan
+    st = lib.sbiem_plan_create(ctypes.byref(h), 256, 1e4, 30e9, 0.25, CS, CP,
+                               hh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert st == -1
+
+
+def test_status_strings():
+    import paper_2107_03550_amd as pkg
+    assert pkg.lib.sbiem_status_string(-6) == b"SBIEM_EOPEN"
+    assert pkg.lib.sbiem_status_string(0) == b"SBIEM_OK"
+
+
+@pytest.mark.parametrize("T", [0.0, 1e-6, 0.3, 1.7, 5.0, 12.0, 28.8, 28.9, 49.9, 50.1, 87.0,
+                               150.0, 199.7, 230.0])
+def test_extended_precision_kernels_match_oracle(T):
+    from oracle.kernels import kernels_mp, rate_kernel_T_mp
+    import paper_2107_03550_amd as pkg
+    ct, cn, dct, dcn = (v[0] for v in pkg.kernel_eval([T], CS, CP))
+    with mp.workdps(30):
+        rct, rcn = kernels_mp(T, CS, CP)
+        assert abs(ct - float(rct)) < 3e-15
+        assert abs(cn - float(rcn)) < 3e-15
+        if T > 0:
+            # derivative of C^T is the rate kernel; of C^N by differentiation
+            assert abs(dct - float(rate_kernel_T_mp(T, CS, CP))) < 1e-13
+            with mp.workdps(40):
+                dn = mp.diff(lambda x: kernels_mp(x, CS, CP)[1], mp.mpf(T))
+            assert abs(dcn - float(dn)) < 1e-13
+
+
+def test_extended_precision_kernels_match_golden_table():
+    import paper_2107_03550_amd as pkg
+    z = np.load(os.path.join(ROOT, "tests", "golden", "kernel_table_L10km_beta05_N256.npz"))
+    p = np.arange(0, int(z["p_max"]) + 1, 37)
+    ct, cn, _, _ = pkg.kernel_eval(p * float(z["delta"]), CS, CP)
+    assert np.abs(ct - z["CT"][p]).max() < 3e-15
+    assert np.abs(cn - z["CN"][p]).max() < 3e-15
