@@ -26,7 +26,9 @@ Two evaluators:
   30 digits leave more than 20 correct.
 * ``*_fp``: the same closed forms in FP64 with scipy's Bessel and Struve
   functions.  Accurate to about 1e-10 absolute for T <= 250; used where a
-  test's tolerance is 1e-7 or looser.
+  test's tolerance is 1e-7 or looser.  scipy's Struve functions return NaN at
+  isolated arguments (e.g. near x = 25.76); those points are recomputed
+  with the 30-digit evaluator.
 """
 
 from __future__ import annotations
@@ -110,6 +112,15 @@ def kernels_fp(T, cs, cp):
     cn = (((q - 2) ** 2 * r / 2 - r - T ** 2) * Wa + (1 + T ** 2 - q / 2) * Wb
           + (r - (q - 2) ** 2 * r / 2) * J1a + (q / 2 - 1) * J1b
           + (T / eta) * J0a - T * J0b)
+    bad = ~(np.isfinite(ct) & np.isfinite(cn))
+    if np.any(bad):
+        ct = np.array(ct, dtype=np.float64)
+        cn = np.array(cn, dtype=np.float64)
+        flat_t, flat_ct, flat_cn = T.reshape(-1), ct.reshape(-1), cn.reshape(-1)
+        for i in np.flatnonzero(bad.reshape(-1)):
+            a, b = kernels_mp(float(flat_t[i]), cs, cp)
+            flat_ct[i] = float(a)
+            flat_cn[i] = float(b)
     return ct, cn
 
 

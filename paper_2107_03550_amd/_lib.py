@@ -19,6 +19,14 @@ lib_path = os.path.join(_HERE, "lib", "libsbiem.so")
 if not os.path.exists(lib_path):
     raise ImportError(f"{lib_path} is missing: build it with "
                       "'python -m paper_2107_03550_amd.build' (hipcc, gfx950)")
+# PyTorch bundles a HIP runtime with the same SONAME (libamdhip64.so.7) but
+# loads it under another file name, so whichever comes first decides whether
+# the process ends up with one runtime or two.  Load torch first: the library
+# then binds to torch's runtime and shares devices and streams with it.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 lib = ctypes.CDLL(lib_path)
 
 SBIEM_FP64 = 0

@@ -120,6 +120,17 @@ def test_fp64_evaluator_agrees_with_30_digit_evaluator():
         assert abs(cn_fp[i] - float(cn)) < 3e-9
 
 
+def test_fp64_evaluator_is_finite_where_scipy_struve_fails():
+    # scipy's Struve functions return NaN near x = 25.7646 (eta T with
+    # T = 14.8752 at these wave speeds); the evaluator must not.
+    T = np.linspace(14.87, 14.88, 20001)
+    ct, cn = kernels_fp(T, CS, CP)
+    assert np.all(np.isfinite(ct)) and np.all(np.isfinite(cn))
+    ref = kernels_mp(14.87520345, CS, CP)
+    v = kernels_fp(np.array([14.87520345]), CS, CP)
+    assert abs(v[0][0] - float(ref[0])) < 3e-9 and abs(v[1][0] - float(ref[1])) < 3e-9
+
+
 def test_golden_kernel_table_is_oracle_output():
     # The stored 30-digit table equals fresh oracle evaluations at spot points.
     import os
