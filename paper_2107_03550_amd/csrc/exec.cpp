@@ -47,20 +47,22 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
   ex->nfaults = (int)plans.size();
   ex->host_faults = descs;
   std::vector<Tile> tiles;
+  std::vector<ConvTask> tasks;
   std::vector<int2> nmap;
   double bytes = 0.0;
   const double rec = precision == SBIEM_FP32CONV ? 16.0 : 32.0;
   for (int f = 0; f < ex->nfaults; ++f) {
     DtData* d = dts[f];
-    ex->host_faults[f].tile_base = (int)tiles.size();
+    const int base = (int)tiles.size();
     for (Tile t : d->tiles) {
       t.fault = f;
       tiles.push_back(t);
     }
-    // algorithmic bytes: ring records of lags 2..M_n-1 and one partial per tile
+    for (ConvTask k : d->tasks) tasks.push_back(ConvTask{k.t0 + base, k.t1 + base});
+    // algorithmic bytes: ring records of lags 2..M_n-1 read, one history sum
+    // (2 complex FP64) written per mode
     for (size_t n = 1; n < d->Rn.size(); ++n)
-      if (d->Rn[n] > 1) bytes += rec * (d->Rn[n] - 1);
-    bytes += rec * d->tiles.size();
+      if (d->Rn[n] > 1) bytes += rec * (d->Rn[n] - 1) + 32.0;
     const int N = (int)plans[f]->N;
     ex->max_N = std::max(ex->max_N, N);
     for (int i = 0; i < N; i += kNewtonThreads) nmap.push_back(make_int2(f, i));
@@ -84,15 +86,15 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
     }
   }
   ex->ntiles = (int)tiles.size();
+  ex->ntasks = (int)tasks.size();
   ex->newton_blocks = (int)nmap.size();
   ex->conv_bytes = bytes;
-  ex->conv_grid = conv_grid_size(precision, ex->ntiles, ex->table_len);
-  const size_t part = precision == SBIEM_FP32CONV ? 16 : 32;
+  ex->conv_grid = conv_grid_size(precision, ex->ntasks, ex->table_len);
   ex->d_faults = (FaultDev*)ex->mem.get(sizeof(FaultDev) * ex->nfaults);
   ex->d_tiles = (Tile*)ex->mem.get(sizeof(Tile) * std::max(1, ex->ntiles));
-  ex->d_partials = ex->mem.get(part * std::max(1, ex->ntiles));
+  ex->d_tasks = (ConvTask*)ex->mem.get(sizeof(ConvTask) * std::max(1, ex->ntasks));
   ex->d_newton_map = (int2*)ex->mem.get(sizeof(int2) * std::max(1, ex->newton_blocks));
-  if (!ex->d_faults || !ex->d_tiles || !ex->d_partials || !ex->d_newton_map) {
+  if (!ex->d_faults || !ex->d_tiles || !ex->d_tasks || !ex->d_newton_map) {
     *err = "device allocation of the execution context failed";
     delete ex;
     return SBIEM_ENOMEM;
@@ -101,6 +103,8 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
                            hipMemcpyHostToDevice);
   if (!e && ex->ntiles)
     e = hipMemcpy(ex->d_tiles, tiles.data(), sizeof(Tile) * ex->ntiles, hipMemcpyHostToDevice);
+  if (!e && ex->ntasks)
+    e = hipMemcpy(ex->d_tasks, tasks.data(), sizeof(ConvTask) * ex->ntasks, hipMemcpyHostToDevice);
   if (!e)
     e = hipMemcpy(ex->d_newton_map, nmap.data(), sizeof(int2) * ex->newton_blocks, hipMemcpyHostToDevice);
   if (!e) e = setup_kernel_attributes(precision);
@@ -114,13 +118,12 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
 }
 
 int refresh_desc(sbiem_plan* p) {
-  FaultDev f = make_fault_desc(p, p->dtd, p->dyn, p->V_pl, p->t0, 0);
+  FaultDev f = make_fault_desc(p, p->dtd, p->dyn, p->V_pl, p->t0);
   hipError_t e = hipSetDevice(p->device);
   if (!e) e = hipStreamSynchronize(p->stream);
   if (!e) e = hipMemcpy(p->d_desc, &f, sizeof(f), hipMemcpyHostToDevice);
   if (e) return hip_fail(p, e, "updating the fault descriptor");
   if (p->exec) {
-    f.tile_base = p->exec->host_faults[0].tile_base;
     p->exec->host_faults[0] = f;
     e = hipMemcpy(p->exec->d_faults, &f, sizeof(f), hipMemcpyHostToDevice);
     if (e) return hip_fail(p, e, "updating the fault descriptor");
@@ -132,7 +135,7 @@ int rebuild_exec(sbiem_plan* p) {
   delete p->exec;
   p->exec = nullptr;
   if (!p->dtd) return SBIEM_OK;
-  FaultDev f = make_fault_desc(p, p->dtd, p->dyn, p->V_pl, p->t0, 0);
+  FaultDev f = make_fault_desc(p, p->dtd, p->dyn, p->V_pl, p->t0);
   std::string err;
   Exec* ex = nullptr;
   int st = build_exec({p}, {p->dtd}, {p->dyn}, {f}, p->precision, &ex, &err);
@@ -202,6 +205,7 @@ int spectral_state_from_host(sbiem_plan* p, const double* slip, const double* V,
                              1, 0, 0, s);
   if (!e) e = launch_spectra(p->d_desc, p->precision, (int)N, d->thd1, nullptr, 1.0, d->v_hat0,
                              d->gv_hat0, 1, 0, 0, s);
+  if (!e && p->dtd) e = launch_prepare(p->d_desc, (int)(N / 2), s);
   if (!e) e = hipStreamSynchronize(s);
   if (e) return hip_fail(p, e, "computing the spectral state");
   return SBIEM_OK;
@@ -398,7 +402,7 @@ int sbiem_stress(sbiem_plan* p, const double* slip_hist, int64_t nt, double dt, 
     delete dtd;
     return st;
   }
-  FaultDev f = make_fault_desc(p, dtd, dyn, 0.0, 0.0, 0);
+  FaultDev f = make_fault_desc(p, dtd, dyn, 0.0, 0.0);
   std::string err;
   Exec* ex = nullptr;
   int st = build_exec({p}, {dtd}, {dyn}, {f}, p->precision, &ex, &err);
@@ -436,6 +440,7 @@ int sbiem_stress(sbiem_plan* p, const double* slip_hist, int64_t nt, double dt, 
     if (!e) e = hipMemcpyAsync(dyn->gv_hat0, RG + (nint - 1) * M, M * sizeof(double2), hipMemcpyDeviceToDevice, s);
   }
   if (!e) e = launch_fill_ring(dfd, p->precision, M - 1, RV, RG, (int)nint, s);
+  if (!e) e = launch_prepare(dfd, M - 1, s);
   const long long step = nint > 0 ? nint - 1 : 0;
   if (!e) e = hipMemcpyAsync(dyn->step, &step, sizeof(step), hipMemcpyHostToDevice, s);
   if (!e) e = launch_conv(*ex, s);
@@ -470,7 +475,7 @@ int sbiem_batch_create(sbiem_batch** out, sbiem_plan* const* plans, int64_t n) {
     if (p->device != plans[0]->device) return fail_global(SBIEM_EINVAL, "batch_create: one device");
     dts.push_back(p->dtd);
     dyns.push_back(p->dyn);
-    descs.push_back(make_fault_desc(p, p->dtd, p->dyn, p->V_pl, p->t0, 0));
+    descs.push_back(make_fault_desc(p, p->dtd, p->dyn, p->V_pl, p->t0));
   }
   std::string err;
   Exec* ex = nullptr;
@@ -503,7 +508,7 @@ int sbiem_batch_run(sbiem_batch* b, int64_t nsteps) {
   // descriptors may have changed (theta mode, loads): refresh
   for (size_t f = 0; f < b->plans.size() && !e; ++f) {
     FaultDev d = make_fault_desc(b->plans[f], b->plans[f]->dtd, b->plans[f]->dyn, b->plans[f]->V_pl,
-                                 b->plans[f]->t0, b->exec->host_faults[f].tile_base);
+                                 b->plans[f]->t0);
     if (std::memcmp(&d, &b->exec->host_faults[f], sizeof(d)) != 0) {
       b->exec->host_faults[f] = d;
       e = hipMemcpy(b->exec->d_faults + f, &d, sizeof(d), hipMemcpyHostToDevice);

@@ -11,6 +11,17 @@
 
 namespace sbiem {
 
+// Per-mode constants of the traction assembly (mode n = 0..N/2):
+//   tau_hat   = mk (B_T + aT vc),  B_T = (1-r) u_hat + w1T hprev_v + S_T
+//   sigma_hat = -i ms (B_N + aN gvc), B_N likewise with the curvature spectra
+// with mk = -mu |k_n|, ms = s_n mu (0 at n = 0 and n = N/2) and
+// aX = (1-r) dt + w0X (the predicted slip dt vc plus the current interval).
+struct ModeCoef {
+  double mk, ms, aT, aN, w1T, w1N;
+  int part0;    // second conv partial of the mode (the first is parts[n])
+  int nparts;   // number of partials (0: no history records)
+};
+
 // ---------------------------------------------------------------------------
 // Device-visible description of one fault at one time step.  One array of
 // these per execution context (a plan, a batch, a stress evaluation); the
@@ -21,7 +32,7 @@ struct FaultDev {
   int N, log2N, nmodes;     // nmodes = N/2
   int theta_mode;
   double L, mu, r, cs, dt, eta_rad;
-  double V_pl, Dc, V_ref, f0, tau_rate, t0;
+  double V_pl, Dc, V_ref, f0, tau_rate, t0, ln_V_ref;
 
   // per element (FP64, length N)
   const double *a, *b, *sigma_load, *tau_load, *kappa;
@@ -34,23 +45,23 @@ struct FaultDev {
   double2 *v_hat0, *gv_hat0;    // F[V - V_pl], F[kappa (V - V_pl)] at step start
   double2 *v_hat1, *gv_hat1;    // same for the pass-1 solution
   double2 *hprev_v, *hprev_g;   // rate spectra of the last committed interval
-  double2 *S_T, *S_N;           // history sums over lags >= 2 (this step)
+  double2 *P_T, *P_N;           // (1-r) u_hat + w1 hprev, set at commit
+  double2 *B_T, *B_N;           // P + history sum S, set by pass 1 for pass 2
+  int* inv_exp;                 // log2 balancing scale of the inverse packing
+  double fwd_scale;             // power of two ~ 1/max|kappa| for the forward packing
 
   // per mode (length N/2+1)
-  const double* kabs;           // |k_n|
-  const double *w0T, *w0N;      // weights of lag 0 (current interval)
-  const double *w1T, *w1N;      // weights of lag 1 (last committed interval)
+  const ModeCoef* coef;
   const int* Rn;                // ring capacity M_n - 1 (0 for mode 0)
   const long long* ring_off;    // first ring record of mode n
   const double* theta_h;        // FP32 weights: c_s |k_n| dt / 2 / table spacing
-  const int* tile_start;        // first conv tile of mode n, n = 0..N/2+1 (relative)
-  int tile_base;                // this fault's first tile in the context's tile list
+  double4* parts;               // conv partials: (S_T re, im, S_N re, im)
 
   void* ring;                   // history records: float4 or 2 x double2 per slot
   const double2* wrev;          // FP64 weights per ring slot (see conv kernel)
 
   void* zbuf;                   // N complex in convolution precision (FFT input)
-  const void* twiddle;          // N complex: exp(-2 pi i t / N), t = 0..N-1
+  const void* twiddle;          // N/4+1 values cos(2 pi t / N), convolution precision
 
   long long* step;              // committed steps since state/dt were set
   int* err;                     // first failure status of the pending step (0 = none)
@@ -59,18 +70,33 @@ struct FaultDev {
 };
 
 // A conv tile: one wavefront sums up to kTileSlots ring records of one mode.
+// Per-mode constants ride along so that a wave needs no dependent lookups.
 struct Tile {
   int fault, mode, p0, len;
+  int Rn;          // ring capacity of the mode
+  int part;        // fault-local index of the (task, mode) partial sum
+  int pad0, pad1;
+  long long ring_off;
+  double th;       // FP32 weights: c_s |k_n| dt / 2 / table spacing
 };
+
+// A conv task: tiles [t0, t1) of one fault, handled by one workgroup.  A task
+// holds whole modes, or one piece of a mode longer than kTaskTiles tiles; it
+// writes one FP64 partial sum per (task, mode) and the spectral kernel adds a
+// mode's pieces in order.
+struct ConvTask {
+  int t0, t1;
+};
+constexpr int kTaskTiles = 16;  // at most this many tiles per task
 
 constexpr int kTileSlots32 = 512;   // FP32 records per wavefront tile
 constexpr int kTileSlots64 = 256;   // FP64 records per wavefront tile
-constexpr int kConvThreads = 256;   // 4 wavefronts
+constexpr int kConvThreads = 512;   // 8 wavefronts
 constexpr int kSpecThreads = 1024;  // spectral (FFT) kernels
-constexpr int kNewtonThreads = 256;
+constexpr int kNewtonThreads = 64;
 constexpr double kTableStep = 1.0 / 16.0;  // spacing of the FP32 kernel table in T
 constexpr int kMaxLdsBytes = 160 * 1024;
-constexpr int kMaxDynLds = kMaxLdsBytes - 1024;  // room for static LDS (reductions)
+constexpr int kMaxDynLds = kMaxLdsBytes - 4096;  // room for static LDS (reductions)
 
 // ---------------------------------------------------------------------------
 // Host side
@@ -105,14 +131,15 @@ struct DtData {
   std::vector<long long> ring_off;
   long long ring_slots = 0;
   std::vector<Tile> tiles;       // this fault's tiles (fault field = 0)
-  std::vector<int> tile_start;   // relative, n = 0..N/2+1
+  std::vector<ConvTask> tasks;   // this fault's tasks (tile indices local)
+  std::vector<int> part0, nparts;
   int table_len = 0;             // FP32 table nodes
   DevArena mem;
-  double *kabs = nullptr, *w0T = nullptr, *w0N = nullptr, *w1T = nullptr, *w1N = nullptr;
+  ModeCoef* coef = nullptr;
   double* theta_h = nullptr;
   int* d_Rn = nullptr;
   long long* d_ring_off = nullptr;
-  int* d_tile_start = nullptr;
+  double4* parts = nullptr;
   void* ring = nullptr;
   double2* wrev = nullptr;
   float4* table = nullptr;       // FP32 kernel table: dt*(C^T, h C^T', C^N, h C^N')
@@ -122,8 +149,9 @@ struct DtData {
 struct DynData {
   DevArena mem;
   double *slip[2], *V[2], *theta[2], *thd[2], *V1, *thd1, *tau_el[2], *sigma_el[2];
-  double2 *u_hat, *g_hat, *v_hat0, *gv_hat0, *v_hat1, *gv_hat1, *hprev_v, *hprev_g, *S_T,
-      *S_N;
+  double2 *u_hat, *g_hat, *v_hat0, *gv_hat0, *v_hat1, *gv_hat1, *hprev_v, *hprev_g, *B_T,
+      *B_N, *P_T, *P_N;
+  int* inv_exp;
   void* zbuf;
   long long* step;
   int *err, *err_count, *err_index;
@@ -144,7 +172,8 @@ struct Exec {
   FaultDev* d_faults = nullptr;
   Tile* d_tiles = nullptr;
   int ntiles = 0;
-  void* d_partials = nullptr;
+  ConvTask* d_tasks = nullptr;
+  int ntasks = 0;
   int2* d_newton_map = nullptr;  // per Newton block: fault, first element
   int newton_blocks = 0;
   int max_N = 0;
@@ -180,9 +209,9 @@ struct sbiem_plan {
   sbiem::DevArena mem;                 // per-element constants, twiddles
   double *a = nullptr, *b = nullptr, *sigma_load = nullptr, *tau_load = nullptr,
          *kappa = nullptr;
-  void* twiddle = nullptr;             // in the convolution precision
-  void* twiddle64 = nullptr;           // FP64 twiddles
+  void* twiddle = nullptr;             // quarter-wave table, convolution precision
   std::vector<double> kappa_host;
+  double fwd_scale = 1.0;              // 2^-ilogb(max|kappa|)
 
   sbiem::FaultDev* d_desc = nullptr;   // device copy of this fault's descriptor
   sbiem::DtData* dtd = nullptr;        // tables + ring for the stepping dt
@@ -216,8 +245,7 @@ int fail_global(int status, const std::string& msg);
 int hip_fail(sbiem_plan* p, hipError_t e, const char* what);
 
 // Build the descriptor of a fault for an execution context.
-FaultDev make_fault_desc(sbiem_plan* p, DtData* dtd, DynData* dyn, double V_pl, double t0,
-                         int tile_base);
+FaultDev make_fault_desc(sbiem_plan* p, DtData* dtd, DynData* dyn, double V_pl, double t0);
 // Allocate tables/ring for dt (host side computations + uploads).
 int build_dt_data(sbiem_plan* p, double dt, DtData** out);
 // Allocate the dynamic state buffers.
@@ -242,11 +270,11 @@ hipError_t launch_spectra(const FaultDev* d_fault, int precision, int max_N, con
 // stress-only path: fill the ring of a fault from interval spectra
 hipError_t launch_fill_ring(const FaultDev* d_fault, int precision, int nmodes,
                             const double2* RV, const double2* RG, int nint, hipStream_t s);
-hipError_t launch_set_spectral_state(const FaultDev* d_fault, int precision, int max_N,
-                                     hipStream_t s);
+// P = (1-r) u_hat + w1 hprev for every mode and an unset inverse scale
+hipError_t launch_prepare(const FaultDev* d_fault, int nmodes, hipStream_t s);
 hipError_t launch_rates(const double* hist, double* rates, long long count, long long N, double dt,
                         hipStream_t s);
-int conv_grid_size(int precision, int ntiles, int table_len);
+int conv_grid_size(int precision, int ntasks, int table_len);
 hipError_t setup_kernel_attributes(int precision);
 
 }  // namespace sbiem

@@ -92,8 +92,27 @@ template <typename C> __device__ __forceinline__ void dft8(C* x) {
   x[7] = csub(e3, w3);
 }
 
-template <typename C, int LR, int MAXPTS>
-__device__ __forceinline__ void fft_pass(C* buf, int N, int p, const C* __restrict__ tw) {
+// exp(-2 pi i m / N) for m in [0, N/2) from the quarter-wave table
+// q[r] = cos(2 pi r / N), r = 0..N/4 (sin(2 pi r / N) = q[N/4 - r]),
+// branch-free.
+template <typename C, typename R>
+__device__ __forceinline__ C twiddle_half(const R* __restrict__ q, int m, int N) {
+  const int Q = N >> 2;
+  const bool hi = m >= Q;  // angle in [pi/2, pi)
+  const int r = hi ? m - Q : m;
+  const R a = q[r], b = q[Q - r];  // cos, sin of the reduced angle
+  C w;
+  w.x = hi ? -b : a;   // cos
+  w.y = hi ? -a : -b;  // -sin
+  return w;
+}
+
+// LDS index of complex element x: one pad element per 2^ps elements, which
+// spreads the power-of-two strides of the Stockham passes over all banks.
+__device__ __forceinline__ int lx(int x, int ps) { return x + (x >> ps); }
+
+template <typename C, typename R, int LR, int MAXPTS>
+__device__ __forceinline__ void fft_pass(C* buf, int N, int p, const R* __restrict__ q, int ps) {
   constexpr int RD = 1 << LR;
   constexpr int MAXB = ((MAXPTS >> LR) + kSpecThreads - 1) / kSpecThreads;
   const int nb = N >> LR;
@@ -103,7 +122,7 @@ __device__ __forceinline__ void fft_pass(C* buf, int N, int p, const C* __restri
     const int i = threadIdx.x + b * kSpecThreads;
     if (i < nb) {
 #pragma unroll
-      for (int r = 0; r < RD; ++r) x[b][r] = buf[i + r * nb];
+      for (int r = 0; r < RD; ++r) x[b][r] = buf[lx(i + r * nb, ps)];
     }
   }
   __syncthreads();
@@ -113,32 +132,47 @@ __device__ __forceinline__ void fft_pass(C* buf, int N, int p, const C* __restri
     const int i = threadIdx.x + b * kSpecThreads;
     if (i < nb) {
       const int k = i & (p - 1);
-      if (k != 0) {
-#pragma unroll
-        for (int r = 1; r < RD; ++r) x[b][r] = cmul(x[b][r], tw[r * k * tws]);
+      if (p > 1) {
+        // w^r = exp(-2 pi i r k / (p RD)) from one lookup and products
+        const C w1 = twiddle_half<C, R>(q, k * tws, N);
+        x[b][1] = cmul(x[b][1], w1);
+        if (RD >= 4) {
+          const C w2 = cmul(w1, w1);
+          const C w3 = cmul(w2, w1);
+          x[b][2] = cmul(x[b][2], w2);
+          x[b][3] = cmul(x[b][3], w3);
+          if (RD == 8) {
+            const C w4 = cmul(w2, w2);
+            x[b][4] = cmul(x[b][4], w4);
+            x[b][5] = cmul(x[b][5], cmul(w4, w1));
+            x[b][6] = cmul(x[b][6], cmul(w4, w2));
+            x[b][7] = cmul(x[b][7], cmul(w4, w3));
+          }
+        }
       }
       if (RD == 8) dft8(x[b]);
       else if (RD == 4) dft4(x[b][0], x[b][1], x[b][2], x[b][3]);
       else dft2(x[b]);
       const int base = (i - k) * RD + k;
 #pragma unroll
-      for (int s = 0; s < RD; ++s) buf[base + s * p] = x[b][s];
+      for (int s = 0; s < RD; ++s) buf[lx(base + s * p, ps)] = x[b][s];
     }
   }
   __syncthreads();
 }
 
-// Forward FFT of buf[0..N) in LDS; caller has synchronised after filling it.
-template <typename C, int MAXPTS>
-__device__ void fft_lds(C* buf, int N, int log2N, const C* __restrict__ tw) {
+// Forward FFT of buf[0..N) in LDS (q: quarter-wave table in LDS); the caller
+// has synchronised after filling both.
+template <typename C, typename R, int MAXPTS>
+__device__ __forceinline__ void fft_lds(C* buf, int N, int log2N, const R* __restrict__ q, int ps) {
   int p = 1, rem = log2N;
   while (rem >= 3) {
-    fft_pass<C, 3, MAXPTS>(buf, N, p, tw);
+    fft_pass<C, R, 3, MAXPTS>(buf, N, p, q, ps);
     p <<= 3;
     rem -= 3;
   }
-  if (rem == 2) fft_pass<C, 2, MAXPTS>(buf, N, p, tw);
-  else if (rem == 1) fft_pass<C, 1, MAXPTS>(buf, N, p, tw);
+  if (rem == 2) fft_pass<C, R, 2, MAXPTS>(buf, N, p, q, ps);
+  else if (rem == 1) fft_pass<C, R, 1, MAXPTS>(buf, N, p, q, ps);
 }
 
 template <typename R> struct Prec;
@@ -157,6 +191,17 @@ template <> struct Prec<double> {
   static constexpr int kMaxPts = 8192;
   static constexpr int kTile = kTileSlots64;
 };
+
+// LDS bytes of a spectral kernel for N points: padded data + quarter table.
+template <typename R>
+__host__ __device__ inline size_t spec_lds_bytes(int N, int ps) {
+  return (size_t)(N + (N >> ps)) * sizeof(typename Prec<R>::C) + (size_t)(N / 4 + 1) * sizeof(R);
+}
+// Pad one element in 8 when it fits, else one in 16.
+template <typename R>
+__host__ __device__ inline int pad_shift(int N) {
+  return spec_lds_bytes<R>(N, 3) <= (size_t)kMaxDynLds ? 3 : 4;
+}
 
 // ---------------------------------------------------------------------------
 // History convolution.  Slot p of mode n's ring holds interval
@@ -193,40 +238,106 @@ __device__ __forceinline__ long long posmod(long long a, long long m) {
   return r < 0 ? r + m : r;
 }
 
+// a mod m for 0 <= a < 2^52, 0 < m < 2^31 (FP64 quotient estimate, corrected)
+__device__ __forceinline__ int mod_pos(long long a, int m) {
+  long long q = (long long)((double)a / (double)m);
+  long long r = a - q * (long long)m;
+  if (r < 0) r += m;
+  if (r >= m) r -= m;
+  return (int)r;
+}
+
+// Offset o = (-b) mod R with b = step - 1 >= -1.
+__device__ __forceinline__ int ring_phase(long long step, int Rn) {
+  const long long b = step - 1;
+  if (b < 0) return 1 % Rn;
+  const int r = mod_pos(b, Rn);
+  return r == 0 ? 0 : Rn - r;
+}
+
+// One workgroup per task (a run of tiles of one fault): each wave sums tiles
+// of the task, the per-tile FP64 partials go to LDS, and after a barrier the
+// first thread of each (task, mode) run adds its tiles in order and stores
+// the sum in parts[part].  The spectral kernel adds a mode's parts in order,
+// so every sum has a fixed order and results are reproducible.
+struct TaskLds {
+  double4 part[kTaskTiles];
+  int id[kTaskTiles];
+};
+
+__device__ __forceinline__ void finish_task(const FaultDev& fd, const TaskLds& L, int nt) {
+  const int k = threadIdx.x;
+  if (k < nt && (k == 0 || L.id[k - 1] != L.id[k])) {
+    double4 a = L.part[k];
+    for (int j = k + 1; j < nt && L.id[j] == L.id[k]; ++j) {
+      const double4 b = L.part[j];
+      a.x += b.x;
+      a.y += b.y;
+      a.z += b.z;
+      a.w += b.w;
+    }
+    fd.parts[L.id[k]] = a;
+  }
+}
+
 __global__ void __launch_bounds__(kConvThreads)
-k_conv64(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles, int ntiles,
-         Rec64* __restrict__ partials) {
+k_conv64(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
+         const ConvTask* __restrict__ tasks, int ntasks) {
+  constexpr int U = kTileSlots64 / 64;
+  __shared__ TaskLds L;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wpb = kConvThreads / 64;
-  for (int t = blockIdx.x * wpb + wave; t < ntiles; t += gridDim.x * wpb) {
-    const Tile tl = tiles[t];
-    const FaultDev& fd = faults[tl.fault];
-    Rec64 acc;
-    acc.v = d2(0, 0);
-    acc.g = d2(0, 0);
-    if (*fd.err == 0) {
-      const int Rn = fd.Rn[tl.mode];
-      const long long off = fd.ring_off[tl.mode];
-      const long long b = *fd.step - 1;
-      const int o = (int)posmod(-b, Rn);
-      const Rec64* __restrict__ ring = (const Rec64*)fd.ring + off;
-      const double2* __restrict__ w = fd.wrev + off;
-      const int end = tl.p0 + tl.len;
-#pragma unroll 4
-      for (int p = tl.p0 + lane; p < end; p += 64) {
-        int q = p + o;
-        q -= (q >= Rn) ? Rn : 0;
-        const Rec64 h = ring[p];
-        const double2 wt = w[q];
-        acc.v.x = fma(wt.x, h.v.x, acc.v.x);
-        acc.v.y = fma(wt.x, h.v.y, acc.v.y);
-        acc.g.x = fma(wt.y, h.g.x, acc.g.x);
-        acc.g.y = fma(wt.y, h.g.y, acc.g.y);
+  for (int task = blockIdx.x; task < ntasks; task += gridDim.x) {
+    const ConvTask tk = tasks[task];
+    const int nt = tk.t1 - tk.t0;
+    const FaultDev& fd = faults[tiles[tk.t0].fault];
+    const int err = *fd.err;
+    const long long step = *fd.step;
+    for (int k = wave; k < nt; k += wpb) {
+      const Tile tl = tiles[tk.t0 + k];
+      Rec64 acc;
+      acc.v = d2(0, 0);
+      acc.g = d2(0, 0);
+      if (err == 0) {
+        const int Rn = tl.Rn;
+        const int o = ring_phase(step, Rn);
+        const Rec64* __restrict__ ring = (const Rec64*)fd.ring + tl.ring_off;
+        const double2* __restrict__ w = fd.wrev + tl.ring_off;
+        const int end = tl.p0 + tl.len;
+        Rec64 h[U];
+        double2 wt[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int p = tl.p0 + lane + 64 * u;
+          int q = p + o;
+          q -= (q >= Rn) ? Rn : 0;
+          if (p < end) {
+            h[u] = ring[p];
+            wt[u] = w[q];
+          } else {
+            h[u].v = d2(0, 0);
+            h[u].g = d2(0, 0);
+            wt[u] = d2(0, 0);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          acc.v.x = fma(wt[u].x, h[u].v.x, acc.v.x);
+          acc.v.y = fma(wt[u].x, h[u].v.y, acc.v.y);
+          acc.g.x = fma(wt[u].y, h[u].g.x, acc.g.x);
+          acc.g.y = fma(wt[u].y, h[u].g.y, acc.g.y);
+        }
+      }
+      acc = wave_reduce_r64(acc);
+      if (lane == 0) {
+        L.part[k] = make_double4(acc.v.x, acc.v.y, acc.g.x, acc.g.y);
+        L.id[k] = tl.part;
       }
     }
-    acc = wave_reduce_r64(acc);
-    if (lane == 0) partials[t] = acc;
+    __syncthreads();
+    finish_task(fd, L, nt);
+    __syncthreads();
   }
 }
 
@@ -236,89 +347,83 @@ k_conv64(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles, in
 // table coordinate (2j + 1) theta_n / h is formed in FP64 so that the phase
 // keeps full accuracy at T ~ 200.
 __global__ void __launch_bounds__(kConvThreads)
-k_conv32(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles, int ntiles,
-         float4* __restrict__ partials, const float4* __restrict__ table, int table_len) {
+k_conv32(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
+         const ConvTask* __restrict__ tasks, int ntasks, const float4* __restrict__ table,
+         int table_len) {
+  constexpr int U = kTileSlots32 / 64;
   extern __shared__ float4 tab[];
+  __shared__ TaskLds L;
   for (int i = threadIdx.x; i < table_len; i += kConvThreads) tab[i] = table[i];
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wpb = kConvThreads / 64;
-  for (int t = blockIdx.x * wpb + wave; t < ntiles; t += gridDim.x * wpb) {
-    const Tile tl = tiles[t];
-    const FaultDev& fd = faults[tl.fault];
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (*fd.err == 0) {
-      const int Rn = fd.Rn[tl.mode];
-      const long long off = fd.ring_off[tl.mode];
-      const long long b = *fd.step - 1;
-      const int o = (int)posmod(-b, Rn);
-      const double th = fd.theta_h[tl.mode];
-      const float4* __restrict__ ring = (const float4*)fd.ring + off;
-      const int end = tl.p0 + tl.len;
-#pragma unroll 4
-      for (int p = tl.p0 + lane; p < end; p += 64) {
-        int q = p + o;
-        q -= (q >= Rn) ? Rn : 0;
-        const float4 h = ring[p];
-        const int j = Rn - q + 1;                       // lag (q = 0: skipped slot)
-        const double u = (double)(2 * j + 1) * th;
-        const int i = min((int)u, table_len - 2);
-        const float f = (float)(u - (double)i);
-        const float4 n0 = tab[i], n1 = tab[i + 1];
-        const float f2 = f * f, f3 = f2 * f;
-        const float h00 = 2.f * f3 - 3.f * f2 + 1.f;
-        const float h10 = f3 - 2.f * f2 + f;
-        const float h01 = 3.f * f2 - 2.f * f3;
-        const float h11 = f3 - f2;
-        float wT = h00 * n0.x + h10 * n0.y + h01 * n1.x + h11 * n1.y;
-        float wN = h00 * n0.z + h10 * n0.w + h01 * n1.z + h11 * n1.w;
-        wT = (q == 0) ? 0.f : wT;
-        wN = (q == 0) ? 0.f : wN;
-        acc.x = fmaf(wT, h.x, acc.x);
-        acc.y = fmaf(wT, h.y, acc.y);
-        acc.z = fmaf(wN, h.z, acc.z);
-        acc.w = fmaf(wN, h.w, acc.w);
+  for (int task = blockIdx.x; task < ntasks; task += gridDim.x) {
+    const ConvTask tk = tasks[task];
+    const int nt = tk.t1 - tk.t0;
+    const FaultDev& fd = faults[tiles[tk.t0].fault];
+    const int err = *fd.err;
+    const long long step = *fd.step;
+    for (int k = wave; k < nt; k += wpb) {
+      const Tile tl = tiles[tk.t0 + k];
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (err == 0) {
+        const int Rn = tl.Rn;
+        const int o = ring_phase(step, Rn);
+        const double th = tl.th;
+        const float4* __restrict__ ring = (const float4*)fd.ring + tl.ring_off;
+        const int end = tl.p0 + tl.len;
+        float4 h[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int p = tl.p0 + lane + 64 * u;
+          h[u] = p < end ? ring[p] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int p = tl.p0 + lane + 64 * u;
+          int q = p + o;
+          q -= (q >= Rn) ? Rn : 0;
+          const int j = Rn - q + 1;                       // lag (q = 0: skipped slot)
+          const double x = (double)(2 * j + 1) * th;
+          const int i = min((int)x, table_len - 2);
+          const float f = (float)(x - (double)i);
+          const float4 n0 = tab[i], n1 = tab[i + 1];
+          const float f2 = f * f, f3 = f2 * f;
+          const float h00 = 2.f * f3 - 3.f * f2 + 1.f;
+          const float h10 = f3 - 2.f * f2 + f;
+          const float h01 = 3.f * f2 - 2.f * f3;
+          const float h11 = f3 - f2;
+          float wT = h00 * n0.x + h10 * n0.y + h01 * n1.x + h11 * n1.y;
+          float wN = h00 * n0.z + h10 * n0.w + h01 * n1.z + h11 * n1.w;
+          const bool use = (q != 0) && (p < end);
+          wT = use ? wT : 0.f;
+          wN = use ? wN : 0.f;
+          acc.x = fmaf(wT, h[u].x, acc.x);
+          acc.y = fmaf(wT, h[u].y, acc.y);
+          acc.z = fmaf(wN, h[u].z, acc.z);
+          acc.w = fmaf(wN, h[u].w, acc.w);
+        }
+      }
+      acc = wave_reduce4(acc);
+      if (lane == 0) {
+        L.part[k] = make_double4(acc.x, acc.y, acc.z, acc.w);
+        L.id[k] = tl.part;
       }
     }
-    acc = wave_reduce4(acc);
-    if (lane == 0) partials[t] = acc;
+    __syncthreads();
+    finish_task(fd, L, nt);
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
 // Spectral kernels (one workgroup per fault, N complex in LDS)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void partial_sum(const float4* partials, int a, int b, double2* T,
-                                            double2* Nn) {
-  double tx = 0, ty = 0, nx = 0, ny = 0;
-  for (int t = a; t < b; ++t) {
-    const float4 v = partials[t];
-    tx += v.x;
-    ty += v.y;
-    nx += v.z;
-    ny += v.w;
-  }
-  *T = d2(tx, ty);
-  *Nn = d2(nx, ny);
-}
-__device__ __forceinline__ void partial_sum(const Rec64* partials, int a, int b, double2* T,
-                                            double2* Nn) {
-  double tx = 0, ty = 0, nx = 0, ny = 0;
-  for (int t = a; t < b; ++t) {
-    const Rec64 v = partials[t];
-    tx += v.v.x;
-    ty += v.v.y;
-    nx += v.g.x;
-    ny += v.g.y;
-  }
-  *T = d2(tx, ty);
-  *Nn = d2(nx, ny);
-}
-
 // Block-wide maxima of two non-negative values (all threads get the result).
 __device__ __forceinline__ void block_max2(double& a, double& b) {
-  __shared__ double red[2][kSpecThreads / 64];
+  constexpr int W = kSpecThreads / 64;
+  __shared__ double red[2][W];
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     a = fmax(a, __shfl_xor(a, off));
@@ -330,11 +435,18 @@ __device__ __forceinline__ void block_max2(double& a, double& b) {
     red[1][wave] = b;
   }
   __syncthreads();
+  double ra[W], rb[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    ra[w] = red[0][w];
+    rb[w] = red[1][w];
+  }
   a = 0.0;
   b = 0.0;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-    a = fmax(a, red[0][w]);
-    b = fmax(b, red[1][w]);
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    a = fmax(a, ra[w]);
+    b = fmax(b, rb[w]);
   }
   __syncthreads();
 }
@@ -348,195 +460,379 @@ __device__ __forceinline__ double pow2_ratio(double x, double y) {
   return ldexp(1.0, ilogb(x) - ilogb(y));
 }
 
-// Load z (a + i b) into LDS with b scaled by the returned power of two.
-template <typename C>
-__device__ double load_balanced(C* buf, int N, const C* __restrict__ z) {
-  double mr = 0.0, mi = 0.0;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    const C v = z[i];
-    buf[i] = v;
-    mr = fmax(mr, fabs((double)v.x));
-    mi = fmax(mi, fabs((double)v.y));
+// LDS layout of the spectral kernels: N complex values (padded), then the
+// quarter-wave twiddle table (N/4 + 1 reals) copied from global memory.
+template <typename R, int MAXPTS>
+__device__ __forceinline__ const R* load_quarter_table(typename Prec<R>::C* buf, const FaultDev& fd) {
+  constexpr int K = (MAXPTS / 4) / kSpecThreads + 1;
+  R* q = reinterpret_cast<R*>(buf + fd.N + (fd.N >> pad_shift<R>(fd.N)));
+  const R* __restrict__ g = (const R*)fd.twiddle;
+  const int Q = fd.N >> 2;
+  R v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = g[min((int)threadIdx.x + k * kSpecThreads, Q)];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = threadIdx.x + k * kSpecThreads;
+    if (i <= Q) q[i] = v[k];
   }
-  block_max2(mr, mi);
-  const double s = pow2_ratio(mr, mi);
-  if (s != 1.0)
-    for (int i = threadIdx.x; i < N; i += blockDim.x) buf[i].y = buf[i].y * s;
-  __syncthreads();
-  return s;
+  return q;
 }
 
-// Traction spectra of mode n (section 3.1 with the current interval's rate
-// spectra vc, gvc and the last committed interval hprev):
-//   tau_hat   = -mu |k| [ (1-r)(u + dt vc) + w0T vc + w1T hprev_v + S_T ]
-//   sigma_hat = -i s_n mu [ (1-r)(g + dt gvc) + w0N gvc + w1N hprev_g + S_N ]
-// Pass 1 uses vc = v_hat0; pass 2 the average of v_hat0 and v_hat1.
-__device__ __forceinline__ void traction_mode(const FaultDev& fd, int n, bool pass2, double2* tau,
-                                              double2* sig) {
-  const int N = fd.N;
-  const double c1 = 1.0 - fd.r;
-  const double dt = fd.dt;
-  double2 vc = fd.v_hat0[n], gvc = fd.gv_hat0[n];
-  if (pass2) {
-    const double2 v1 = fd.v_hat1[n], g1 = fd.gv_hat1[n];
-    vc = d2(0.5 * (vc.x + v1.x), 0.5 * (vc.y + v1.y));
-    gvc = d2(0.5 * (gvc.x + g1.x), 0.5 * (gvc.y + g1.y));
-  }
-  const double2 u = fd.u_hat[n], g = fd.g_hat[n];
-  const double2 hv = fd.hprev_v[n], hg = fd.hprev_g[n];
-  const double2 sT = fd.S_T[n], sN = fd.S_N[n];
-  const double w0T = fd.w0T[n], w0N = fd.w0N[n], w1T = fd.w1T[n], w1N = fd.w1N[n];
-  double2 AT, AN;
-  AT.x = c1 * (u.x + dt * vc.x) + w0T * vc.x + w1T * hv.x + sT.x;
-  AT.y = c1 * (u.y + dt * vc.y) + w0T * vc.y + w1T * hv.y + sT.y;
-  AN.x = c1 * (g.x + dt * gvc.x) + w0N * gvc.x + w1N * hg.x + sN.x;
-  AN.y = c1 * (g.y + dt * gvc.y) + w0N * gvc.y + w1N * hg.y + sN.y;
-  const double mk = -fd.mu * fd.kabs[n];
-  *tau = d2(mk * AT.x, mk * AT.y);
-  const double sn = (n == 0 || 2 * n == N) ? 0.0 : fd.mu;
-  *sig = d2(sn * AN.y, -sn * AN.x);  // -i s mu AN
-}
-
-// Assemble Z = tau_hat + i c sigma_hat (c a balancing power of two), inverse
-// transform in LDS and write tau^el, sigma^el.  The inverse is the forward
-// transform of conj(Z): y = N conj(z).
-template <typename R>
-__device__ void assemble_and_invert(const FaultDev& fd, bool pass2, typename Prec<R>::C* buf) {
+// Copy the FFT input z (the Newton kernel has already scaled its curvature
+// half by fwd_scale) into LDS; all loads of a thread are issued first.
+template <typename R, int MAXPTS>
+__device__ __forceinline__ void load_input(typename Prec<R>::C* buf, int N,
+                                           const typename Prec<R>::C* __restrict__ z, int ps) {
   using C = typename Prec<R>::C;
-  const int N = fd.N, half = fd.nmodes;
-  double mt = 0.0, ms = 0.0;
-  for (int n = threadIdx.x; n <= half; n += blockDim.x) {
-    double2 t, g;
-    traction_mode(fd, n, pass2, &t, &g);
-    mt = fmax(mt, fmax(fabs(t.x), fabs(t.y)));
-    ms = fmax(ms, fmax(fabs(g.x), fabs(g.y)));
+  constexpr int K = MAXPTS / kSpecThreads;
+  C v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = z[min((int)threadIdx.x + k * kSpecThreads, N - 1)];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = threadIdx.x + k * kSpecThreads;
+    if (i < N) buf[lx(i, ps)] = v[k];
   }
-  block_max2(mt, ms);
-  const double c = pow2_ratio(mt, ms);
-  for (int n = threadIdx.x; n <= half; n += blockDim.x) {
-    double2 t, g;
-    traction_mode(fd, n, pass2, &t, &g);
-    g = d2(g.x * c, g.y * c);
-    buf[n] = cmk<C>(t.x - g.y, -(t.y + g.x));
-    if (n > 0 && 2 * n < N) buf[N - n] = cmk<C>(t.x + g.y, -(-t.y + g.x));
+}
+
+// Traction spectra of mode n (section 3.1; current interval rates vc, gvc):
+//   tau_hat = mk (B_T + aT vc),  sigma_hat = -i ms (B_N + aN gvc)
+__device__ __forceinline__ void traction_mode(const ModeCoef& c, double2 BT, double2 BN, double2 vc,
+                                              double2 gvc, double2* tau, double2* sig) {
+  const double ATx = BT.x + c.aT * vc.x, ATy = BT.y + c.aT * vc.y;
+  const double ANx = BN.x + c.aN * gvc.x, ANy = BN.y + c.aN * gvc.y;
+  *tau = d2(c.mk * ATx, c.mk * ATy);
+  *sig = d2(c.ms * ANy, -c.ms * ANx);  // -i ms AN
+}
+
+// Modes one thread owns in the spectral kernels (n = tid + s T).
+template <int MAXPTS>
+struct ModesPerThread {
+  static constexpr int value = (MAXPTS / 2 + kSpecThreads) / kSpecThreads;
+};
+
+constexpr int kInvExpUnset = -100000;
+
+// Exponent bookkeeping of the inverse packing: LDS cells for the block
+// maxima of ilogb|tau_hat| and ilogb|sigma_hat|.
+struct InvScale {
+  int tau_e, sig_e;
+};
+
+// log2 of the balancing factor from the two maxima (0 when either is zero).
+__device__ __forceinline__ int balance_exp(const InvScale* sc) {
+  if (sc->tau_e <= -2000 || sc->sig_e <= -2000) return 0;
+  return min(max(sc->tau_e - sc->sig_e, -256), 256);
+}
+
+__device__ __forceinline__ int ilogb_or_min(double x) {
+  return (x > 0.0 && x <= 1.0e300) ? ilogb(x) : -2000;
+}
+
+// Pack Z = tau_hat + i c sigma_hat (c = 2^e, e from the previous pass or, on
+// the first pass after a reset, from this pass's maxima) as conj(Z), inverse
+// transform in LDS and write tau^el, sigma^el; record this pass's maxima for
+// the next pass.  The inverse of Z is conj(FFT(conj Z))/N.
+template <typename R, int MAXPTS>
+__device__ __forceinline__ void invert_tractions(const FaultDev& fd, typename Prec<R>::C* buf,
+                                                 const R* q, const typename Prec<R>::C* tau,
+                                                 const typename Prec<R>::C* sig, double mt,
+                                                 double ms, InvScale* sc, int e_prev) {
+  using C = typename Prec<R>::C;
+  constexpr int kPer = ModesPerThread<MAXPTS>::value;
+  const int N = fd.N, half = fd.nmodes;
+  const int ps = pad_shift<R>(N);
+  // this pass's maxima: wave reduction, then an LDS atomic per wave
+  int et = ilogb_or_min(mt), es = ilogb_or_min(ms);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    et = max(et, __shfl_xor(et, off));
+    es = max(es, __shfl_xor(es, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&sc->tau_e, et);
+    atomicMax(&sc->sig_e, es);
+  }
+  int e = e_prev;
+  if (e == kInvExpUnset) {  // first pass after a reset: use this pass's maxima
+    __syncthreads();
+    e = balance_exp(sc);
+  }
+  const double c = ldexp(1.0, e);
+#pragma unroll
+  for (int sl = 0; sl < kPer; ++sl) {
+    const int n = threadIdx.x + sl * kSpecThreads;
+    if (n <= half) {
+      const double2 t = d2(tau[sl].x, tau[sl].y);
+      const double2 g = d2((double)sig[sl].x * c, (double)sig[sl].y * c);
+      buf[lx(n, ps)] = cmk<C>(t.x - g.y, -(t.y + g.x));
+      if (n > 0 && 2 * n < N) buf[lx(N - n, ps)] = cmk<C>(t.x + g.y, -(-t.y + g.x));
+    }
   }
   __syncthreads();
-  fft_lds<C, Prec<R>::kMaxPts>(buf, N, fd.log2N, (const C*)fd.twiddle);
+  fft_lds<C, R, MAXPTS>(buf, N, fd.log2N, q, ps);
   const int slot = (int)((*fd.step + 1) & 1);
-  double* __restrict__ tau = fd.tau_el[slot];
-  double* __restrict__ sig = fd.sigma_el[slot];
+  double* __restrict__ to = fd.tau_el[slot];
+  double* __restrict__ so = fd.sigma_el[slot];
   const double inv = 1.0 / N, invc = 1.0 / (c * N);
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    const C z = buf[i];
-    tau[i] = (double)z.x * inv;
-    sig[i] = -(double)z.y * invc;
+    const C z = buf[lx(i, ps)];
+    to[i] = (double)z.x * inv;
+    so[i] = -(double)z.y * invc;
   }
+  // the FFT's barriers have ordered every atomicMax above
+  if (threadIdx.x == 0)
+    *fd.inv_exp = balance_exp(sc);
 }
 
-// Unpack the FFT Z of z = a + i s b (a, b real, s the balancing scale) into
+// Unpack the FFT Z of z = a + i s b (a, b real, s the forward scale) into
 // A_n, B_n, n = 0..N/2.
 template <typename C>
 __device__ __forceinline__ void unpack_mode(const C* buf, int N, int n, double inv_s, double2* A,
-                                            double2* B) {
-  const C zn = buf[n];
-  const C zm = buf[n == 0 ? 0 : N - n];
+                                            double2* B, int ps) {
+  const C zn = buf[lx(n, ps)];
+  const C zm = buf[lx(n == 0 ? 0 : N - n, ps)];
   // A = (Z_n + conj Z_m)/2, B = (Z_n - conj Z_m)/(2i)
   *A = d2(0.5 * ((double)zn.x + (double)zm.x), 0.5 * ((double)zn.y - (double)zm.y));
   const double dx = (double)zn.x - (double)zm.x, dy = (double)zn.y + (double)zm.y;
   *B = d2(0.5 * dy * inv_s, -0.5 * dx * inv_s);
 }
 
-template <typename R>
-__global__ void __launch_bounds__(kSpecThreads)
-k_pass1(const FaultDev* __restrict__ faults, const typename Prec<R>::Rec* __restrict__ partials) {
-  using C = typename Prec<R>::C;
-  extern __shared__ unsigned char smem_raw[];
-  C* buf = reinterpret_cast<C*>(smem_raw);
-  const FaultDev& fd = faults[blockIdx.x];
-  if (*fd.err) return;
-  const int half = fd.nmodes;
-  for (int n = threadIdx.x; n <= half; n += blockDim.x) {
-    double2 sT = d2(0, 0), sN = d2(0, 0);
-    if (n > 0)
-      partial_sum(partials, fd.tile_base + fd.tile_start[n], fd.tile_base + fd.tile_start[n + 1],
-                  &sT, &sN);
-    fd.S_T[n] = sT;
-    fd.S_N[n] = sN;
+__device__ __forceinline__ void init_inv_scale(InvScale* sc) {
+  if (threadIdx.x == 0) {
+    sc->tau_e = -2000;
+    sc->sig_e = -2000;
   }
-  // each thread reads back only the modes it wrote
-  assemble_and_invert<R>(fd, false, buf);
 }
 
-template <typename R>
+template <typename R, int MAXPTS>
+__global__ void __launch_bounds__(kSpecThreads)
+k_pass1(const FaultDev* __restrict__ faults) {
+  using C = typename Prec<R>::C;
+  constexpr int kPer = ModesPerThread<MAXPTS>::value;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ InvScale sc;
+  C* buf = reinterpret_cast<C*>(smem_raw);
+  const FaultDev& fd = faults[blockIdx.x];
+  const int err = *fd.err;
+  const int e_prev = *fd.inv_exp;
+  if (err) return;
+  init_inv_scale(&sc);
+  __syncthreads();  // the maxima cells are set before any wave updates them
+  const R* q = load_quarter_table<R, MAXPTS>(buf, fd);
+  const int half = fd.nmodes;
+  C tau[kPer], sig[kPer];
+  double mt = 0.0, ms = 0.0;
+  // groups of three modes: all loads of a group are issued before its stores
+  constexpr int G = (sizeof(R) == 4 && MAXPTS <= 8192) ? 2 : 1;
+#pragma unroll
+  for (int s0 = 0; s0 < kPer; s0 += G) {
+    double4 S[G];
+    double2 P[G][2], V[G][2];
+    ModeCoef cf[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int n = threadIdx.x + (s0 + k) * kSpecThreads;
+      if (s0 + k < kPer && n <= half) {
+        cf[k] = fd.coef[n];
+        S[k] = fd.parts[n];
+        P[k][0] = fd.P_T[n];
+        P[k][1] = fd.P_N[n];
+        V[k][0] = fd.v_hat0[n];
+        V[k][1] = fd.gv_hat0[n];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int sl = s0 + k;
+      const int n = threadIdx.x + sl * kSpecThreads;
+      if (sl < kPer && n <= half) {
+        const ModeCoef& c = cf[k];
+        double4 h = c.nparts > 0 ? S[k] : make_double4(0.0, 0.0, 0.0, 0.0);
+        for (int j = 1; j < c.nparts; ++j) {  // further pieces of a long window
+          const double4 b = fd.parts[c.part0 + j - 1];
+          h.x += b.x;
+          h.y += b.y;
+          h.z += b.z;
+          h.w += b.w;
+        }
+        const double2 BT = d2(P[k][0].x + h.x, P[k][0].y + h.y);
+        const double2 BN = d2(P[k][1].x + h.z, P[k][1].y + h.w);
+        fd.B_T[n] = BT;
+        fd.B_N[n] = BN;
+        double2 t, g;
+        traction_mode(c, BT, BN, V[k][0], V[k][1], &t, &g);
+        tau[sl] = cmk<C>(t.x, t.y);
+        sig[sl] = cmk<C>(g.x, g.y);
+        mt = fmax(mt, fmax(fabs(t.x), fabs(t.y)));
+        ms = fmax(ms, fmax(fabs(g.x), fabs(g.y)));
+      }
+    }
+  }
+  invert_tractions<R, MAXPTS>(fd, buf, q, tau, sig, mt, ms, &sc, e_prev);
+}
+
+template <typename R, int MAXPTS>
 __global__ void __launch_bounds__(kSpecThreads)
 k_pass2(const FaultDev* __restrict__ faults) {
   using C = typename Prec<R>::C;
+  constexpr int kPer = ModesPerThread<MAXPTS>::value;
   extern __shared__ unsigned char smem_raw[];
+  __shared__ InvScale sc;
   C* buf = reinterpret_cast<C*>(smem_raw);
   const FaultDev& fd = faults[blockIdx.x];
-  if (*fd.err) return;
+  const int err = *fd.err;
+  const int e_prev = *fd.inv_exp;
+  if (err) return;
   const int N = fd.N, half = fd.nmodes;
-  const double s = load_balanced(buf, N, (const C*)fd.zbuf);
-  fft_lds<C, Prec<R>::kMaxPts>(buf, N, fd.log2N, (const C*)fd.twiddle);
-  for (int n = threadIdx.x; n <= half; n += blockDim.x) {
-    double2 A, B;
-    unpack_mode(buf, N, n, 1.0 / s, &A, &B);
-    fd.v_hat1[n] = A;
-    fd.gv_hat1[n] = B;
+  const int ps = pad_shift<R>(N);
+  init_inv_scale(&sc);
+  const R* q = load_quarter_table<R, MAXPTS>(buf, fd);
+  load_input<R, MAXPTS>(buf, N, (const C*)fd.zbuf, ps);
+  __syncthreads();
+  fft_lds<C, R, MAXPTS>(buf, N, fd.log2N, q, ps);
+  const double inv_s = 1.0 / fd.fwd_scale;
+  C tau[kPer], sig[kPer];
+  double mt = 0.0, ms = 0.0;
+  constexpr int G = (sizeof(R) == 4 && MAXPTS <= 8192) ? 2 : 1;
+#pragma unroll
+  for (int s0 = 0; s0 < kPer; s0 += G) {
+    double2 Bv[G][2], V0[G][2];
+    ModeCoef cf[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int n = threadIdx.x + (s0 + k) * kSpecThreads;
+      if (s0 + k < kPer && n <= half) {
+        cf[k] = fd.coef[n];
+        Bv[k][0] = fd.B_T[n];
+        Bv[k][1] = fd.B_N[n];
+        V0[k][0] = fd.v_hat0[n];
+        V0[k][1] = fd.gv_hat0[n];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int sl = s0 + k;
+      const int n = threadIdx.x + sl * kSpecThreads;
+      if (sl < kPer && n <= half) {
+        double2 A, B;
+        unpack_mode(buf, N, n, inv_s, &A, &B, ps);
+        fd.v_hat1[n] = A;
+        fd.gv_hat1[n] = B;
+        const double2 vc = d2(0.5 * (V0[k][0].x + A.x), 0.5 * (V0[k][0].y + A.y));
+        const double2 gvc = d2(0.5 * (V0[k][1].x + B.x), 0.5 * (V0[k][1].y + B.y));
+        double2 t, g;
+        traction_mode(cf[k], Bv[k][0], Bv[k][1], vc, gvc, &t, &g);
+        tau[sl] = cmk<C>(t.x, t.y);
+        sig[sl] = cmk<C>(g.x, g.y);
+        mt = fmax(mt, fmax(fabs(t.x), fabs(t.y)));
+        ms = fmax(ms, fmax(fabs(g.x), fabs(g.y)));
+      }
+    }
   }
-  __syncthreads();  // all LDS reads done before the assembly overwrites buf
-  assemble_and_invert<R>(fd, true, buf);
+  __syncthreads();  // every unpack read of buf is done before the packing overwrites it
+  invert_tractions<R, MAXPTS>(fd, buf, q, tau, sig, mt, ms, &sc, e_prev);
 }
 
-template <typename R>
+template <typename R, int MAXPTS>
 __global__ void __launch_bounds__(kSpecThreads)
 k_commit(const FaultDev* __restrict__ faults) {
   using C = typename Prec<R>::C;
   using Rec = typename Prec<R>::Rec;
+  constexpr int kPer = ModesPerThread<MAXPTS>::value;
   extern __shared__ unsigned char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
   const FaultDev& fd = faults[blockIdx.x];
-  if (*fd.err) return;
-  const int N = fd.N, half = fd.nmodes;
+  const int err = *fd.err;
   const long long l = *fd.step;
-  const double s = load_balanced(buf, N, (const C*)fd.zbuf);
-  fft_lds<C, Prec<R>::kMaxPts>(buf, N, fd.log2N, (const C*)fd.twiddle);
-  const double dt = fd.dt;
-  for (int n = threadIdx.x; n <= half; n += blockDim.x) {
-    double2 A, B;
-    unpack_mode(buf, N, n, 1.0 / s, &A, &B);
-    const double2 a0 = fd.v_hat0[n], b0 = fd.gv_hat0[n];
-    const double2 a1 = fd.v_hat1[n], b1 = fd.gv_hat1[n];
-    const double2 hv = d2(0.5 * (a0.x + a1.x), 0.5 * (a0.y + a1.y));
-    const double2 hg = d2(0.5 * (b0.x + b1.x), 0.5 * (b0.y + b1.y));
-    const int Rn = fd.Rn[n];
-    if (n > 0 && Rn > 0) {
-      const long long slot = fd.ring_off[n] + (l % Rn);
-      Rec rec;
-      if constexpr (sizeof(R) == 4) {
-        rec = make_float4((float)hv.x, (float)hv.y, (float)hg.x, (float)hg.y);
-      } else {
-        rec.v = hv;
-        rec.g = hg;
+  if (err) return;
+  const int N = fd.N, half = fd.nmodes;
+  const int ps = pad_shift<R>(N);
+  const R* q = load_quarter_table<R, MAXPTS>(buf, fd);
+  load_input<R, MAXPTS>(buf, N, (const C*)fd.zbuf, ps);
+  __syncthreads();
+  fft_lds<C, R, MAXPTS>(buf, N, fd.log2N, q, ps);
+  const double dt = fd.dt, c1 = 1.0 - fd.r;
+  const double inv_s = 1.0 / fd.fwd_scale;
+  constexpr int G = (sizeof(R) == 4 && MAXPTS <= 8192) ? 2 : 1;
+#pragma unroll
+  for (int s0 = 0; s0 < kPer; s0 += G) {
+    double2 V0[G][2], V1[G][2], U[G][2];
+    double w1[G][2];
+    int Rn[G];
+    long long off[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int n = threadIdx.x + (s0 + k) * kSpecThreads;
+      if (s0 + k < kPer && n <= half) {
+        V0[k][0] = fd.v_hat0[n];
+        V0[k][1] = fd.gv_hat0[n];
+        V1[k][0] = fd.v_hat1[n];
+        V1[k][1] = fd.gv_hat1[n];
+        U[k][0] = fd.u_hat[n];
+        U[k][1] = fd.g_hat[n];
+        w1[k][0] = fd.coef[n].w1T;
+        w1[k][1] = fd.coef[n].w1N;
+        Rn[k] = fd.Rn[n];
+        off[k] = fd.ring_off[n];
       }
-      ((Rec*)fd.ring)[slot] = rec;
     }
-    fd.hprev_v[n] = hv;
-    fd.hprev_g[n] = hg;
-    const double2 u = fd.u_hat[n], g = fd.g_hat[n];
-    fd.u_hat[n] = d2(u.x + dt * hv.x, u.y + dt * hv.y);
-    fd.g_hat[n] = d2(g.x + dt * hg.x, g.y + dt * hg.y);
-    fd.v_hat0[n] = A;
-    fd.gv_hat0[n] = B;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int n = threadIdx.x + (s0 + k) * kSpecThreads;
+      if (s0 + k < kPer && n <= half) {
+        double2 A, B;
+        unpack_mode(buf, N, n, inv_s, &A, &B, ps);
+        // rate of the interval [t, t + dt] in pass 2: (V_0 + V_1)/2
+        const double2 hv = d2(0.5 * (V0[k][0].x + V1[k][0].x), 0.5 * (V0[k][0].y + V1[k][0].y));
+        const double2 hg = d2(0.5 * (V0[k][1].x + V1[k][1].x), 0.5 * (V0[k][1].y + V1[k][1].y));
+        if (n > 0 && Rn[k] > 0) {
+          const long long slot = off[k] + (l % Rn[k]);
+          Rec rec;
+          if constexpr (sizeof(R) == 4) {
+            rec = make_float4((float)hv.x, (float)hv.y, (float)hg.x, (float)hg.y);
+          } else {
+            rec.v = hv;
+            rec.g = hg;
+          }
+          ((Rec*)fd.ring)[slot] = rec;
+        }
+        const double2 u = d2(U[k][0].x + dt * hv.x, U[k][0].y + dt * hv.y);
+        const double2 g = d2(U[k][1].x + dt * hg.x, U[k][1].y + dt * hg.y);
+        fd.hprev_v[n] = hv;
+        fd.hprev_g[n] = hg;
+        fd.u_hat[n] = u;
+        fd.g_hat[n] = g;
+        fd.P_T[n] = d2(c1 * u.x + w1[k][0] * hv.x, c1 * u.y + w1[k][0] * hv.y);
+        fd.P_N[n] = d2(c1 * g.x + w1[k][1] * hg.x, c1 * g.y + w1[k][1] * hg.y);
+        fd.v_hat0[n] = A;
+        fd.gv_hat0[n] = B;
+      }
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) *fd.step = l + 1;
 }
 
+// P = (1-r) u_hat + w1 hprev for every mode of one fault; the inverse
+// packing scale is marked unset (the next pass measures it).
+__global__ void k_prepare(const FaultDev* __restrict__ fdp) {
+  const FaultDev& fd = *fdp;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n == 0) *fd.inv_exp = kInvExpUnset;
+  if (n > fd.nmodes) return;
+  const double c1 = 1.0 - fd.r;
+  const double2 u = fd.u_hat[n], g = fd.g_hat[n], hv = fd.hprev_v[n], hg = fd.hprev_g[n];
+  const ModeCoef c = fd.coef[n];
+  fd.P_T[n] = d2(c1 * u.x + c.w1T * hv.x, c1 * u.y + c.w1T * hv.y);
+  fd.P_N[n] = d2(c1 * g.x + c.w1N * hg.x, c1 * g.y + c.w1N * hg.y);
+}
+
 // Forward spectra of count real signal pairs (a, kappa*a or b) -> A, B
 // (n = 0..N/2).  Block c handles signal c; inputs are FP64 and are balanced
-// before rounding to the transform precision.
-template <typename R>
+// by their block maxima before rounding to the transform precision.
+template <typename R, int MAXPTS>
 __global__ void __launch_bounds__(kSpecThreads)
 k_spectra(const FaultDev* __restrict__ fdp, const double* __restrict__ a,
           const double* __restrict__ b, int b_is_kappa_a, double2* __restrict__ A,
@@ -546,6 +842,8 @@ k_spectra(const FaultDev* __restrict__ fdp, const double* __restrict__ a,
   C* buf = reinterpret_cast<C*>(smem_raw);
   const FaultDev& fd = *fdp;
   const int N = fd.N;
+  const int ps = pad_shift<R>(N);
+  const R* q = load_quarter_table<R, MAXPTS>(buf, fd);
   const double* ac = a + stride_in * blockIdx.x;
   const double* bc = b ? b + stride_in * blockIdx.x : nullptr;
   double ma = 0.0, mb = 0.0;
@@ -560,15 +858,15 @@ k_spectra(const FaultDev* __restrict__ fdp, const double* __restrict__ a,
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     const double av = ac[i];
     const double bv = b_is_kappa_a ? fd.kappa[i] * av : (bc ? bc[i] : 0.0);
-    buf[i] = cmk<C>(av, bv * s);
+    buf[lx(i, ps)] = cmk<C>(av, bv * s);
   }
   __syncthreads();
-  fft_lds<C, Prec<R>::kMaxPts>(buf, N, fd.log2N, (const C*)fd.twiddle);
+  fft_lds<C, R, MAXPTS>(buf, N, fd.log2N, q, ps);
   double2* Ao = A + stride_out * blockIdx.x;
   double2* Bo = B + stride_out * blockIdx.x;
   for (int n = threadIdx.x; n <= fd.nmodes; n += blockDim.x) {
     double2 x, y;
-    unpack_mode(buf, N, n, 1.0 / s, &x, &y);
+    unpack_mode(buf, N, n, 1.0 / s, &x, &y, ps);
     Ao[n] = x;
     Bo[n] = y;
   }
@@ -623,7 +921,7 @@ __global__ void k_rates(const double* __restrict__ hist, double* __restrict__ ra
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int solve_rate(double tau, double sig, double theta, double a, double b,
                                           const FaultDev& fd, double Vguess, double* Vout) {
-  const double lnVref = log(fd.V_ref);
+  const double lnVref = fd.ln_V_ref;
   const double psi = fd.f0 + b * log(theta * fd.V_ref / fd.Dc);
   const double x_rs = lnVref + (tau / sig - psi) / a;
   const double x_0 = lnVref - psi / a;
@@ -667,19 +965,26 @@ k_newton(const FaultDev* __restrict__ faults, const int2* __restrict__ map, int 
   const int2 m = map[blockIdx.x];
   const FaultDev& fd = faults[m.x];
   const int i = m.y + threadIdx.x;
-  if (i >= fd.N) return;
-  if (*fd.err) return;
+  const int ii = min(i, fd.N - 1);
+  // every load is issued before the first branch
+  const int err = *fd.err;
   const long long l = *fd.step;
   const int cur = (int)(l & 1), nxt = cur ^ 1;
+  const double V0 = fd.V[cur][ii], thd0 = fd.thd[cur][ii], th0 = fd.theta[cur][ii];
+  const double slip0 = fd.slip[cur][ii];
+  const double V1 = fd.V1[ii], thd1 = fd.thd1[ii];
+  const double tl = fd.tau_load[ii], sl = fd.sigma_load[ii];
+  const double te = fd.tau_el[nxt][ii], se = fd.sigma_el[nxt][ii];
+  const double a = fd.a[ii], b = fd.b[ii], kap = fd.kappa[ii];
+  if (i >= fd.N || err) return;
   const double dt = fd.dt;
-  const double V0 = fd.V[cur][i], thd0 = fd.thd[cur][i], th0 = fd.theta[cur][i];
   double Vc, thdc;
   if (pass == 1) {
     Vc = V0;
     thdc = thd0;
   } else {
-    Vc = 0.5 * (V0 + fd.V1[i]);
-    thdc = 0.5 * (thd0 + fd.thd1[i]);
+    Vc = 0.5 * (V0 + V1);
+    thdc = 0.5 * (thd0 + thd1);
   }
   double theta_p;
   if (fd.theta_mode == SBIEM_THETA_EXP) {
@@ -689,8 +994,8 @@ k_newton(const FaultDev* __restrict__ faults, const int2* __restrict__ map, int 
     theta_p = th0 + dt * thdc;
   }
   const double t_new = fd.t0 + (double)(l + 1) * dt;
-  const double tau = fd.tau_load[i] + fd.tau_rate * t_new + fd.tau_el[nxt][i];
-  const double sig = fd.sigma_load[i] + fd.sigma_el[nxt][i];
+  const double tau = tl + fd.tau_rate * t_new + te;
+  const double sig = sl + se;
   double Vp = Vc;
   if (!(sig > 0.0)) {
     report(fd, SBIEM_EOPEN, i);
@@ -700,7 +1005,7 @@ k_newton(const FaultDev* __restrict__ faults, const int2* __restrict__ map, int 
     report(fd, SBIEM_ESTATE, i);
     return;
   }
-  if (solve_rate(tau, sig, theta_p, fd.a[i], fd.b[i], fd, Vc, &Vp) != 0 || !isfinite(Vp)) {
+  if (solve_rate(tau, sig, theta_p, a, b, fd, Vc, &Vp) != 0 || !isfinite(Vp)) {
     report(fd, SBIEM_ENEWTON, i);
     return;
   }
@@ -709,47 +1014,72 @@ k_newton(const FaultDev* __restrict__ faults, const int2* __restrict__ map, int 
     fd.V1[i] = Vp;
     fd.thd1[i] = thdp;
   } else {
-    fd.slip[nxt][i] = fd.slip[cur][i] + dt * Vc;
+    fd.slip[nxt][i] = slip0 + dt * Vc;
     fd.V[nxt][i] = Vp;
     fd.theta[nxt][i] = theta_p;
     fd.thd[nxt][i] = thdp;
   }
   const double dv = Vp - fd.V_pl;
-  ((C*)fd.zbuf)[i] = cmk<C>(dv, fd.kappa[i] * dv);
+  ((C*)fd.zbuf)[i] = cmk<C>(dv, fd.fwd_scale * kap * dv);
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static size_t spec_lds(int precision, int maxN) {
-  return (size_t)maxN * (precision == SBIEM_FP32CONV ? sizeof(float2) : sizeof(double2));
+  if (precision == SBIEM_FP32CONV) return spec_lds_bytes<float>(maxN, pad_shift<float>(maxN));
+  return spec_lds_bytes<double>(maxN, pad_shift<double>(maxN));
+}
+
+// The spectral kernels are instantiated per largest transform size so that
+// each thread's per-mode arrays stay in registers.
+template <typename R, int M>
+struct SpecTag {
+  using type = R;
+  static constexpr int pts = M;
+};
+
+template <typename F>
+static hipError_t with_spec_size(int precision, int maxN, F&& f) {
+  if (precision == SBIEM_FP32CONV) {
+    if (maxN <= 2048) return f(SpecTag<float, 2048>{});
+    if (maxN <= 8192) return f(SpecTag<float, 8192>{});
+    return f(SpecTag<float, 16384>{});
+  }
+  if (maxN <= 2048) return f(SpecTag<double, 2048>{});
+  return f(SpecTag<double, 8192>{});
+}
+
+template <typename T>
+static hipError_t set_spec_attributes(T) {
+  using R = typename T::type;
+  constexpr int M = T::pts;
+  const int bytes = kMaxDynLds;
+  const hipFuncAttribute a = hipFuncAttributeMaxDynamicSharedMemorySize;
+  hipError_t e = hipFuncSetAttribute((const void*)k_pass1<R, M>, a, bytes);
+  if (!e) e = hipFuncSetAttribute((const void*)k_pass2<R, M>, a, bytes);
+  if (!e) e = hipFuncSetAttribute((const void*)k_commit<R, M>, a, bytes);
+  if (!e) e = hipFuncSetAttribute((const void*)k_spectra<R, M>, a, bytes);
+  return e;
 }
 
 hipError_t setup_kernel_attributes(int precision) {
   static bool done[2] = {false, false};
   const int idx = precision == SBIEM_FP32CONV ? 1 : 0;
   if (done[idx]) return hipSuccess;
-  const int bytes = kMaxDynLds;
   hipError_t e = hipSuccess;
-  if (idx) {
-    e = hipFuncSetAttribute((const void*)k_pass1<float>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (!e) e = hipFuncSetAttribute((const void*)k_pass2<float>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (!e) e = hipFuncSetAttribute((const void*)k_commit<float>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (!e) e = hipFuncSetAttribute((const void*)k_spectra<float>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (!e) e = hipFuncSetAttribute((const void*)k_conv32, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  } else {
-    e = hipFuncSetAttribute((const void*)k_pass1<double>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (!e) e = hipFuncSetAttribute((const void*)k_pass2<double>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (!e) e = hipFuncSetAttribute((const void*)k_commit<double>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (!e) e = hipFuncSetAttribute((const void*)k_spectra<double>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  for (int maxN : {2048, 8192, 16384}) {
+    if (!e) e = with_spec_size(precision, maxN, [](auto t) { return set_spec_attributes(t); });
   }
+  if (!e && idx)
+    e = hipFuncSetAttribute((const void*)k_conv32, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kMaxDynLds);
   if (!e) done[idx] = true;
   return e;
 }
 
-int conv_grid_size(int precision, int ntiles, int table_len) {
-  const int wpb = kConvThreads / 64;
-  int need = (ntiles + wpb - 1) / wpb;
+int conv_grid_size(int precision, int ntasks, int table_len) {
+  int need = ntasks;
   if (precision == SBIEM_FP32CONV) {
     // persistent: a few workgroups per CU amortise the LDS table load
     const int per_cu = (int)(kMaxLdsBytes / ((size_t)table_len * sizeof(float4) + 1024));
@@ -760,27 +1090,25 @@ int conv_grid_size(int precision, int ntiles, int table_len) {
 }
 
 hipError_t launch_conv(const Exec& ex, hipStream_t s) {
-  if (ex.ntiles == 0) return hipSuccess;
+  if (ex.ntasks == 0) return hipSuccess;
   if (ex.precision == SBIEM_FP32CONV) {
     const size_t lds = (size_t)ex.table_len * sizeof(float4);
     hipLaunchKernelGGL(k_conv32, dim3(ex.conv_grid), dim3(kConvThreads), lds, s, ex.d_faults,
-                       ex.d_tiles, ex.ntiles, (float4*)ex.d_partials, ex.table, ex.table_len);
+                       ex.d_tiles, ex.d_tasks, ex.ntasks, ex.table, ex.table_len);
   } else {
     hipLaunchKernelGGL(k_conv64, dim3(ex.conv_grid), dim3(kConvThreads), 0, s, ex.d_faults,
-                       ex.d_tiles, ex.ntiles, (Rec64*)ex.d_partials);
+                       ex.d_tiles, ex.d_tasks, ex.ntasks);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_pass1(const Exec& ex, hipStream_t s) {
   const size_t lds = spec_lds(ex.precision, ex.max_N);
-  if (ex.precision == SBIEM_FP32CONV)
-    hipLaunchKernelGGL(k_pass1<float>, dim3(ex.nfaults), dim3(kSpecThreads), lds, s, ex.d_faults,
-                       (const float4*)ex.d_partials);
-  else
-    hipLaunchKernelGGL(k_pass1<double>, dim3(ex.nfaults), dim3(kSpecThreads), lds, s, ex.d_faults,
-                       (const Rec64*)ex.d_partials);
-  return hipGetLastError();
+  return with_spec_size(ex.precision, ex.max_N, [&](auto t) {
+    using T = decltype(t);
+    k_pass1<typename T::type, T::pts><<<dim3(ex.nfaults), dim3(kSpecThreads), lds, s>>>(ex.d_faults);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_newton(const Exec& ex, int pass, hipStream_t s) {
@@ -795,20 +1123,20 @@ hipError_t launch_newton(const Exec& ex, int pass, hipStream_t s) {
 
 hipError_t launch_pass2(const Exec& ex, hipStream_t s) {
   const size_t lds = spec_lds(ex.precision, ex.max_N);
-  if (ex.precision == SBIEM_FP32CONV)
-    hipLaunchKernelGGL(k_pass2<float>, dim3(ex.nfaults), dim3(kSpecThreads), lds, s, ex.d_faults);
-  else
-    hipLaunchKernelGGL(k_pass2<double>, dim3(ex.nfaults), dim3(kSpecThreads), lds, s, ex.d_faults);
-  return hipGetLastError();
+  return with_spec_size(ex.precision, ex.max_N, [&](auto t) {
+    using T = decltype(t);
+    k_pass2<typename T::type, T::pts><<<dim3(ex.nfaults), dim3(kSpecThreads), lds, s>>>(ex.d_faults);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_commit(const Exec& ex, hipStream_t s) {
   const size_t lds = spec_lds(ex.precision, ex.max_N);
-  if (ex.precision == SBIEM_FP32CONV)
-    hipLaunchKernelGGL(k_commit<float>, dim3(ex.nfaults), dim3(kSpecThreads), lds, s, ex.d_faults);
-  else
-    hipLaunchKernelGGL(k_commit<double>, dim3(ex.nfaults), dim3(kSpecThreads), lds, s, ex.d_faults);
-  return hipGetLastError();
+  return with_spec_size(ex.precision, ex.max_N, [&](auto t) {
+    using T = decltype(t);
+    k_commit<typename T::type, T::pts><<<dim3(ex.nfaults), dim3(kSpecThreads), lds, s>>>(ex.d_faults);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_step(const Exec& ex, hipStream_t s, bool profile, hipEvent_t e0, hipEvent_t e1) {
@@ -828,12 +1156,17 @@ hipError_t launch_spectra(const FaultDev* d_fault, int precision, int max_N, con
                           int count, long long stride_in, long long stride_out, hipStream_t s) {
   const size_t lds = spec_lds(precision, max_N);
   const int kap = scale_b_by_kappa != 0.0 ? 1 : 0;
-  if (precision == SBIEM_FP32CONV)
-    hipLaunchKernelGGL(k_spectra<float>, dim3(count), dim3(kSpecThreads), lds, s, d_fault, a, b,
-                       kap, A, B, stride_in, stride_out);
-  else
-    hipLaunchKernelGGL(k_spectra<double>, dim3(count), dim3(kSpecThreads), lds, s, d_fault, a, b,
-                       kap, A, B, stride_in, stride_out);
+  return with_spec_size(precision, max_N, [&](auto t) {
+    using T = decltype(t);
+    k_spectra<typename T::type, T::pts><<<dim3(count), dim3(kSpecThreads), lds, s>>>(
+        d_fault, a, b, kap, A, B, stride_in, stride_out);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_prepare(const FaultDev* d_fault, int nmodes, hipStream_t s) {
+  const int blocks = (nmodes + 1 + 255) / 256;
+  hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, s, d_fault);
   return hipGetLastError();
 }
 

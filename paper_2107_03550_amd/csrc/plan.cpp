@@ -155,49 +155,90 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
     slots += d->Rn[n];
   }
   d->ring_slots = slots;
-  // conv tiles
+  // conv tiles (one wavefront each) and tasks (one workgroup each): a task
+  // holds whole modes up to kTaskTiles tiles, a longer mode is cut into
+  // pieces of kTaskTiles tiles
   const int tile = p->precision == SBIEM_FP32CONV ? kTileSlots32 : kTileSlots64;
-  d->tile_start.assign(half + 2, 0);
-  for (int n = 0; n <= half; ++n) {
-    d->tile_start[n] = (int)d->tiles.size();
-    if (n == 0) continue;
-    for (int p0 = 0; p0 < d->Rn[n]; p0 += tile)
-      d->tiles.push_back(Tile{0, n, p0, std::min(tile, d->Rn[n] - p0)});
+  const long double th_unit = 3.141592653589793238462643383279502884L * (long double)p->cs *
+                              (long double)dt / (long double)p->L / (long double)kTableStep;
+  d->part0.assign(half + 1, 0);
+  d->nparts.assign(half + 1, 0);
+  // conv partials: the first piece of mode n is parts[n]; further pieces of a
+  // mode longer than one task follow from index N/2 + 1 on
+  int extra = half + 1;
+  int cur_tiles = 0;
+  auto open_task = [&]() {
+    d->tasks.push_back(ConvTask{(int)d->tiles.size(), (int)d->tiles.size()});
+    cur_tiles = 0;
+  };
+  for (int n = 1; n <= half; ++n) {
+    const int count = (d->Rn[n] + tile - 1) / tile;
+    if (count == 0) continue;
+    if (d->tasks.empty() || cur_tiles + std::min(count, kTaskTiles) > kTaskTiles) open_task();
+    const int extra0 = extra;
+    int part = n;
+    for (int k = 0; k < count; ++k) {
+      if (cur_tiles == kTaskTiles) {  // a long mode continues in a new task
+        open_task();
+        part = extra++;
+      }
+      Tile t;
+      t.fault = 0;
+      t.mode = n;
+      t.p0 = k * tile;
+      t.len = std::min(tile, d->Rn[n] - k * tile);
+      t.Rn = d->Rn[n];
+      t.part = part;
+      t.pad0 = t.pad1 = 0;
+      t.ring_off = d->ring_off[n];
+      t.th = (double)(th_unit * n);
+      d->tiles.push_back(t);
+      d->tasks.back().t1 = (int)d->tiles.size();
+      ++cur_tiles;
+    }
+    d->part0[n] = extra0;
+    d->nparts[n] = 1 + (extra - extra0);
   }
-  d->tile_start[half + 1] = (int)d->tiles.size();
-
+  const int parts = extra;
   // per-mode constants
   const long double cs = p->cs, cp = p->cp;
   const long double theta_unit = kPiL * cs * (long double)dt / (long double)p->L;  // c_s k_1 dt / 2
-  std::vector<double> kabs(half + 1), w0T(half + 1), w0N(half + 1), w1T(half + 1), w1N(half + 1),
-      th(half + 1);
+  std::vector<ModeCoef> coef(half + 1);
+  std::vector<double> th(half + 1);
+  const double c1 = 1.0 - p->r;
   for (int n = 0; n <= half; ++n) {
-    kabs[n] = 2.0 * M_PI * (double)n / p->L;
+    const double kabs = 2.0 * M_PI * (double)n / p->L;
     const long double theta = theta_unit * n;  // c_s |k_n| dt / 2
     long double CT, CN;
     kernel_values(theta, cs, cp, &CT, &CN, nullptr, nullptr);
-    w0T[n] = (double)(dt * CT);
-    w0N[n] = (double)(dt * CN);
+    ModeCoef& c = coef[n];
+    c.mk = -p->mu * kabs;
+    c.ms = (n == 0 || 2 * n == N) ? 0.0 : p->mu;
+    c.aT = c1 * dt + (double)(dt * CT);
+    c.aN = c1 * dt + (double)(dt * CN);
     if (d->M[n] >= 2) {
       kernel_values(3.0L * theta, cs, cp, &CT, &CN, nullptr, nullptr);
-      w1T[n] = (double)(dt * CT);
-      w1N[n] = (double)(dt * CN);
+      c.w1T = (double)(dt * CT);
+      c.w1N = (double)(dt * CN);
     } else {
-      w1T[n] = w1N[n] = 0.0;
+      c.w1T = c.w1N = 0.0;
     }
+    c.part0 = d->part0[n];
+    c.nparts = d->nparts[n];
     th[n] = (double)(theta / (long double)kTableStep);
   }
   hipError_t e = hipSuccess;
   hipStream_t s = p->stream;
-  d->kabs = upload(d->mem, kabs, s, &e);
-  if (!e) d->w0T = upload(d->mem, w0T, s, &e);
-  if (!e) d->w0N = upload(d->mem, w0N, s, &e);
-  if (!e) d->w1T = upload(d->mem, w1T, s, &e);
-  if (!e) d->w1N = upload(d->mem, w1N, s, &e);
+  d->coef = upload(d->mem, coef, s, &e);
   if (!e) d->theta_h = upload(d->mem, th, s, &e);
   if (!e) d->d_Rn = upload(d->mem, d->Rn, s, &e);
   if (!e) d->d_ring_off = upload(d->mem, d->ring_off, s, &e);
-  if (!e) d->d_tile_start = upload(d->mem, d->tile_start, s, &e);
+  if (!e) {
+    d->parts = (double4*)d->mem.get(sizeof(double4) * std::max(1, parts));
+    if (!d->parts) e = hipErrorOutOfMemory;
+    else e = hipMemsetAsync(d->parts, 0, sizeof(double4) * std::max(1, parts), s);
+  }
+
   const size_t rec = p->precision == SBIEM_FP32CONV ? 16 : 32;
   if (!e) {
     d->ring = d->mem.get((size_t)std::max<long long>(slots, 1) * rec);
@@ -283,12 +324,15 @@ int build_dyn_data(sbiem_plan* p, DynData** out) {
   sp(&d->gv_hat1);
   sp(&d->hprev_v);
   sp(&d->hprev_g);
-  sp(&d->S_T);
-  sp(&d->S_N);
+  sp(&d->B_T);
+  sp(&d->B_N);
+  sp(&d->P_T);
+  sp(&d->P_N);
   d->zbuf = d->mem.get(N * sizeof(double2));
   d->step = (long long*)d->mem.get(sizeof(long long) * 2);
   d->err = (int*)d->mem.get(sizeof(int) * 4);
-  ok = ok && d->zbuf && d->step && d->err;
+  d->inv_exp = (int*)d->mem.get(sizeof(int) * 2);
+  ok = ok && d->zbuf && d->step && d->err && d->inv_exp;
   if (!ok) {
     delete d;
     return fail(p, SBIEM_ENOMEM, "device allocation of the state buffers failed");
@@ -302,8 +346,8 @@ int build_dyn_data(sbiem_plan* p, DynData** out) {
     e = hipMemsetAsync(d->tau_el[k], 0, N * sizeof(double), s);
     if (!e) e = hipMemsetAsync(d->sigma_el[k], 0, N * sizeof(double), s);
   }
-  double2* spec[] = {d->u_hat, d->g_hat, d->v_hat0, d->gv_hat0, d->v_hat1,
-                     d->gv_hat1, d->hprev_v, d->hprev_g, d->S_T, d->S_N};
+  double2* spec[] = {d->u_hat, d->g_hat, d->v_hat0, d->gv_hat0, d->v_hat1, d->gv_hat1,
+                     d->hprev_v, d->hprev_g, d->B_T, d->B_N, d->P_T, d->P_N};
   for (double2* q : spec)
     if (!e) e = hipMemsetAsync(q, 0, M * sizeof(double2), s);
   if (!e) e = hipMemsetAsync(d->step, 0, sizeof(long long) * 2, s);
@@ -318,8 +362,7 @@ int build_dyn_data(sbiem_plan* p, DynData** out) {
   return SBIEM_OK;
 }
 
-FaultDev make_fault_desc(sbiem_plan* p, DtData* dtd, DynData* dyn, double V_pl, double t0,
-                         int tile_base) {
+FaultDev make_fault_desc(sbiem_plan* p, DtData* dtd, DynData* dyn, double V_pl, double t0) {
   FaultDev f;
   std::memset(&f, 0, sizeof(f));
   f.N = (int)p->N;
@@ -338,6 +381,7 @@ FaultDev make_fault_desc(sbiem_plan* p, DtData* dtd, DynData* dyn, double V_pl, 
   f.f0 = p->f0;
   f.tau_rate = p->tau_rate;
   f.t0 = t0;
+  f.ln_V_ref = p->V_ref > 0 ? std::log(p->V_ref) : 0.0;
   f.a = p->a;
   f.b = p->b;
   f.sigma_load = p->sigma_load;
@@ -361,22 +405,21 @@ FaultDev make_fault_desc(sbiem_plan* p, DtData* dtd, DynData* dyn, double V_pl, 
   f.gv_hat1 = dyn->gv_hat1;
   f.hprev_v = dyn->hprev_v;
   f.hprev_g = dyn->hprev_g;
-  f.S_T = dyn->S_T;
-  f.S_N = dyn->S_N;
+  f.B_T = dyn->B_T;
+  f.B_N = dyn->B_N;
+  f.P_T = dyn->P_T;
+  f.P_N = dyn->P_N;
+  f.inv_exp = dyn->inv_exp;
+  f.fwd_scale = p->fwd_scale;
   if (dtd) {
-    f.kabs = dtd->kabs;
-    f.w0T = dtd->w0T;
-    f.w0N = dtd->w0N;
-    f.w1T = dtd->w1T;
-    f.w1N = dtd->w1N;
+    f.coef = dtd->coef;
     f.Rn = dtd->d_Rn;
     f.ring_off = dtd->d_ring_off;
     f.theta_h = dtd->theta_h;
-    f.tile_start = dtd->d_tile_start;
+    f.parts = dtd->parts;
     f.ring = dtd->ring;
     f.wrev = dtd->wrev;
   }
-  f.tile_base = tile_base;
   f.zbuf = dyn->zbuf;
   f.twiddle = p->twiddle;
   f.step = dyn->step;
@@ -413,23 +456,20 @@ int ensure_device(sbiem_plan* p) {
   return SBIEM_OK;
 }
 
+// Quarter-wave table cos(2 pi t / N), t = 0..N/4, in the convolution precision.
 int upload_twiddles(sbiem_plan* p) {
-  const int64_t N = p->N;
-  std::vector<double2> t64(N);
-  std::vector<float2> t32(N);
-  for (int64_t t = 0; t < N; ++t) {
-    long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)t / (long double)N;
-    t64[t] = make_double2((double)cosl(ang), (double)sinl(ang));
-    t32[t] = make_float2((float)cosl(ang), (float)sinl(ang));
+  const int64_t N = p->N, Q = N / 4;
+  std::vector<double> t64(Q + 1);
+  std::vector<float> t32(Q + 1);
+  for (int64_t t = 0; t <= Q; ++t) {
+    long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)t / (long double)N;
+    long double c = (t == Q) ? 0.0L : cosl(ang);
+    t64[t] = (double)c;
+    t32[t] = (float)c;
   }
   hipError_t e = hipSuccess;
-  if (!p->twiddle64) p->twiddle64 = upload(p->mem, t64, p->stream, &e);
-  if (e) return hip_fail(p, e, "uploading twiddles");
-  if (p->precision == SBIEM_FP32CONV) {
-    p->twiddle = upload(p->mem, t32, p->stream, &e);
-  } else {
-    p->twiddle = p->twiddle64;
-  }
+  if (p->precision == SBIEM_FP32CONV) p->twiddle = upload(p->mem, t32, p->stream, &e);
+  else p->twiddle = upload(p->mem, t64, p->stream, &e);
   if (!e) e = hipStreamSynchronize(p->stream);
   if (e) return hip_fail(p, e, "uploading twiddles");
   return SBIEM_OK;
@@ -533,6 +573,11 @@ int sbiem_plan_create(sbiem_plan** out, int64_t N, double L, double mu, double n
   p->cp = cp;
   p->r = (cs * cs) / (cp * cp);
   p->kappa_host = curvature_host(h, N, L);
+  {
+    double kmax = 0.0;
+    for (double k : p->kappa_host) kmax = std::max(kmax, std::fabs(k));
+    p->fwd_scale = kmax > 0.0 ? std::ldexp(1.0, -std::ilogb(kmax)) : 1.0;
+  }
   const size_t bytes = (size_t)N * sizeof(double);
   p->kappa = (double*)p->mem.get(bytes);
   p->a = (double*)p->mem.get(bytes);
