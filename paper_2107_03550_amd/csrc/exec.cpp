@@ -13,7 +13,12 @@ namespace {
 constexpr int kGraphSteps = 16;  // steps captured in one replayable graph
 }
 
-Exec::~Exec() { drop_graph(); }
+Exec::~Exec() {
+  drop_graph();
+  if (aux) (void)hipStreamDestroy(aux);
+  if (fork) (void)hipEventDestroy(fork);
+  if (join) (void)hipEventDestroy(join);
+}
 
 hipError_t EventPool::ensure(size_t n) {
   while (ev.size() < n) {
@@ -40,15 +45,15 @@ void Exec::drop_graph() {
 int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>& dts,
                const std::vector<DynData*>& dyns, const std::vector<FaultDev>& descs,
                int precision, Exec** out, std::string* err) {
-  (void)dyns;
   *out = nullptr;
   Exec* ex = new Exec();
+  ex->dyns = dyns;
   ex->precision = precision;
   ex->nfaults = (int)plans.size();
   ex->host_faults = descs;
   std::vector<Tile> tiles;
   std::vector<ConvTask> tasks;
-  std::vector<int2> nmap;
+  std::vector<int2> mmap, emap;
   double bytes = 0.0;
   const double rec = precision == SBIEM_FP32CONV ? 16.0 : 32.0;
   for (int f = 0; f < ex->nfaults; ++f) {
@@ -63,9 +68,11 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
     // (2 complex FP64) written per mode
     for (size_t n = 1; n < d->Rn.size(); ++n)
       if (d->Rn[n] > 1) bytes += rec * (d->Rn[n] - 1) + 32.0;
-    const int N = (int)plans[f]->N;
-    ex->max_N = std::max(ex->max_N, N);
-    for (int i = 0; i < N; i += kNewtonThreads) nmap.push_back(make_int2(f, i));
+    const FaultDev& fd = descs[f];
+    for (int g = 0; g < fd.ngroups; ++g) mmap.push_back(make_int2(f, g));
+    for (int b = 0; b < fd.Q; b += fd.ncls) emap.push_back(make_int2(f, b));
+    ex->mode_lds = std::max(ex->mode_lds, mode_lds_bytes(precision, fd.log2Q));
+    ex->elem_lds = std::max(ex->elem_lds, elem_lds_bytes(precision, fd.log2P, fd.ncls));
     if (precision == SBIEM_FP32CONV) {
       if (d->table_len > ex->table_len) {
         ex->table_len = d->table_len;
@@ -87,14 +94,16 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
   }
   ex->ntiles = (int)tiles.size();
   ex->ntasks = (int)tasks.size();
-  ex->newton_blocks = (int)nmap.size();
+  ex->mode_blocks = (int)mmap.size();
+  ex->elem_blocks = (int)emap.size();
   ex->conv_bytes = bytes;
   ex->conv_grid = conv_grid_size(precision, ex->ntasks, ex->table_len);
   ex->d_faults = (FaultDev*)ex->mem.get(sizeof(FaultDev) * ex->nfaults);
   ex->d_tiles = (Tile*)ex->mem.get(sizeof(Tile) * std::max(1, ex->ntiles));
   ex->d_tasks = (ConvTask*)ex->mem.get(sizeof(ConvTask) * std::max(1, ex->ntasks));
-  ex->d_newton_map = (int2*)ex->mem.get(sizeof(int2) * std::max(1, ex->newton_blocks));
-  if (!ex->d_faults || !ex->d_tiles || !ex->d_tasks || !ex->d_newton_map) {
+  ex->d_mode_map = (int2*)ex->mem.get(sizeof(int2) * std::max(1, ex->mode_blocks));
+  ex->d_elem_map = (int2*)ex->mem.get(sizeof(int2) * std::max(1, ex->elem_blocks));
+  if (!ex->d_faults || !ex->d_tiles || !ex->d_tasks || !ex->d_mode_map || !ex->d_elem_map) {
     *err = "device allocation of the execution context failed";
     delete ex;
     return SBIEM_ENOMEM;
@@ -106,8 +115,13 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
   if (!e && ex->ntasks)
     e = hipMemcpy(ex->d_tasks, tasks.data(), sizeof(ConvTask) * ex->ntasks, hipMemcpyHostToDevice);
   if (!e)
-    e = hipMemcpy(ex->d_newton_map, nmap.data(), sizeof(int2) * ex->newton_blocks, hipMemcpyHostToDevice);
+    e = hipMemcpy(ex->d_mode_map, mmap.data(), sizeof(int2) * ex->mode_blocks, hipMemcpyHostToDevice);
+  if (!e)
+    e = hipMemcpy(ex->d_elem_map, emap.data(), sizeof(int2) * ex->elem_blocks, hipMemcpyHostToDevice);
   if (!e) e = setup_kernel_attributes(precision);
+  if (!e) e = hipStreamCreateWithFlags(&ex->aux, hipStreamNonBlocking);
+  if (!e) e = hipEventCreateWithFlags(&ex->fork, hipEventDisableTiming);
+  if (!e) e = hipEventCreateWithFlags(&ex->join, hipEventDisableTiming);
   if (e) {
     *err = std::string("building the execution context: ") + hipGetErrorString(e);
     delete ex;
@@ -154,6 +168,8 @@ int reset_history(sbiem_plan* p) {
   if (!e) e = hipMemcpyAsync(d->err, init, sizeof(init), hipMemcpyHostToDevice, s);
   if (!e) e = hipMemsetAsync(d->hprev_v, 0, M * sizeof(double2), s);
   if (!e) e = hipMemsetAsync(d->hprev_g, 0, M * sizeof(double2), s);
+  if (!e) e = hipMemsetAsync(d->cells, 0, sizeof(int) * 8, s);
+  d->primed = false;
   if (!e && p->dtd) {
     const size_t rec = p->precision == SBIEM_FP32CONV ? 16 : 32;
     e = hipMemsetAsync(p->dtd->ring, 0, (size_t)std::max<long long>(p->dtd->ring_slots, 1) * rec, s);
@@ -187,26 +203,34 @@ int rebase_state(sbiem_plan* p) {
 }
 
 // u_hat = F[slip - V_pl t], g_hat = F[kappa (slip - V_pl t)],
-// v_hat0 = F[V - V_pl], gv_hat0 = F[kappa (V - V_pl)] from host arrays.
+// v_hat0 = F[V - V_pl], gv_hat0 = F[kappa (V - V_pl)] from host arrays
+// (natural element order).
 int spectral_state_from_host(sbiem_plan* p, const double* slip, const double* V, double t) {
   const int64_t N = p->N;
-  std::vector<double> x(N), y(N);
+  std::vector<double> x(2 * N);
   for (int64_t i = 0; i < N; ++i) {
     x[i] = slip[i] - p->V_pl * t;
-    y[i] = V[i] - p->V_pl;
+    x[N + i] = V[i] - p->V_pl;
   }
   DynData* d = p->dyn;
   hipStream_t s = p->stream;
-  const size_t bytes = (size_t)N * sizeof(double);
-  hipError_t e = hipMemcpyAsync(d->V1, x.data(), bytes, hipMemcpyHostToDevice, s);
-  if (!e) e = hipMemcpyAsync(d->thd1, y.data(), bytes, hipMemcpyHostToDevice, s);
+  DevArena tmp;
+  double* dx = (double*)tmp.get((size_t)2 * N * sizeof(double));
+  void* gF = tmp.get((size_t)2 * N * sizeof(double2));
+  double2* A = (double2*)tmp.get((size_t)2 * (N / 2 + 1) * sizeof(double2));
+  double2* B = (double2*)tmp.get((size_t)2 * (N / 2 + 1) * sizeof(double2));
+  if (!dx || !gF || !A || !B) return fail(p, SBIEM_ENOMEM, "spectral state: device allocation failed");
+  const size_t M = (size_t)(N / 2 + 1);
+  FaultDev h = make_fault_desc(p, p->dtd, d, p->V_pl, p->t0);
+  hipError_t e = hipMemcpyAsync(dx, x.data(), 2 * N * sizeof(double), hipMemcpyHostToDevice, s);
   if (!e) e = setup_kernel_attributes(p->precision);
-  if (!e) e = launch_spectra(p->d_desc, p->precision, (int)N, d->V1, nullptr, 1.0, d->u_hat, d->g_hat,
-                             1, 0, 0, s);
-  if (!e) e = launch_spectra(p->d_desc, p->precision, (int)N, d->thd1, nullptr, 1.0, d->v_hat0,
-                             d->gv_hat0, 1, 0, 0, s);
-  if (!e && p->dtd) e = launch_prepare(p->d_desc, (int)(N / 2), s);
+  if (!e) e = launch_forward(p->d_desc, h, p->precision, dx, A, B, 2, (long long)M, gF, s);
+  if (!e) e = hipMemcpyAsync(d->u_hat, A, M * sizeof(double2), hipMemcpyDeviceToDevice, s);
+  if (!e) e = hipMemcpyAsync(d->g_hat, B, M * sizeof(double2), hipMemcpyDeviceToDevice, s);
+  if (!e) e = hipMemcpyAsync(d->v_hat0, A + M, M * sizeof(double2), hipMemcpyDeviceToDevice, s);
+  if (!e) e = hipMemcpyAsync(d->gv_hat0, B + M, M * sizeof(double2), hipMemcpyDeviceToDevice, s);
   if (!e) e = hipStreamSynchronize(s);
+  d->primed = false;
   if (e) return hip_fail(p, e, "computing the spectral state");
   return SBIEM_OK;
 }
@@ -233,6 +257,7 @@ int check_failure(sbiem_plan* p) {
   }
   p->last_fail_count = h[1];
   p->last_fail_index = h[2];
+  d->primed = false;
   const int init[3] = {0, 0, 0x7fffffff};
   e = hipMemcpy(d->err, init, sizeof(init), hipMemcpyHostToDevice);
   if (e) return hip_fail(p, e, "clearing the failure flag");
@@ -252,15 +277,54 @@ int ready(sbiem_plan* p, double dt) {
   return SBIEM_OK;
 }
 
+// One step in steady state: the next step's history sums on the second
+// stream beside the element/mode stages of this step, joined before the
+// commit launch that consumes them.
+hipError_t launch_step(Exec& ex, hipStream_t s, hipStream_t aux, bool profile, hipEvent_t e0,
+                       hipEvent_t e1) {
+  hipError_t e = hipEventRecord(ex.fork, s);
+  if (!e) e = hipStreamWaitEvent(aux, ex.fork, 0);
+  if (!e && profile) e = hipEventRecord(e0, aux);
+  if (!e) e = launch_conv(ex, 1, aux);
+  if (!e && profile) e = hipEventRecord(e1, aux);
+  if (!e) e = hipEventRecord(ex.join, aux);
+  if (!e) e = launch_elems(ex, 1, s);
+  if (!e) e = launch_modes(ex, 1, 0, s);
+  if (!e) e = launch_elems(ex, 2, s);
+  if (!e) e = hipStreamWaitEvent(s, ex.join, 0);
+  if (!e) e = launch_modes(ex, 2, 0, s);
+  return e;
+}
+
+// Pass-1 spectra of the pending step from the stored state (after a reset,
+// a new dt or a failed step): history sums for this step, the balance
+// maxima, then the assembly.
+hipError_t prologue(Exec& ex, hipStream_t s) {
+  bool need = false;
+  for (DynData* d : ex.dyns) need = need || !d->primed;
+  if (!need) return hipSuccess;
+  const int init[8] = {-2000, -2000, -2000, -2000, 0, 0, 0, 0};
+  hipError_t e = hipSuccess;
+  for (DynData* d : ex.dyns)
+    if (!e) e = hipMemcpyAsync(d->cells, init, sizeof(init), hipMemcpyHostToDevice, s);
+  if (!e) e = launch_conv(ex, 0, s);
+  if (!e) e = launch_modes(ex, 0, 1, s);
+  if (!e) e = launch_modes(ex, 0, 0, s);
+  if (!e) e = hipStreamSynchronize(s);  // init lives on the host stack
+  if (!e)
+    for (DynData* d : ex.dyns) d->primed = true;
+  return e;
+}
+
 hipError_t ensure_graph(Exec* ex, hipStream_t s) {
   if (ex->graph && ex->graph_stream == s) return hipSuccess;
   ex->drop_graph();
-  hipStream_t cap = nullptr;
+  hipStream_t cap = nullptr, cap2 = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-  if (e) return e;
-  e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (!e) e = hipStreamCreateWithFlags(&cap2, hipStreamNonBlocking);
+  if (!e) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (!e) {
-    for (int k = 0; k < kGraphSteps && !e; ++k) e = launch_step(*ex, cap, false, nullptr, nullptr);
+    for (int k = 0; k < kGraphSteps && !e; ++k) e = launch_step(*ex, cap, cap2, false, nullptr, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(cap, &g);
     if (!e) e = e2;
@@ -271,7 +335,8 @@ hipError_t ensure_graph(Exec* ex, hipStream_t s) {
       (void)hipGraphDestroy(g);
     }
   }
-  (void)hipStreamDestroy(cap);
+  if (cap2) (void)hipStreamDestroy(cap2);
+  if (cap) (void)hipStreamDestroy(cap);
   if (!e) {
     ex->graph_steps = kGraphSteps;
     ex->graph_stream = s;
@@ -287,15 +352,17 @@ hipError_t ensure_graph(Exec* ex, hipStream_t s) {
 // once the run has finished.
 hipError_t run_steps(Exec* ex, int64_t nsteps, hipStream_t s, bool profile, EventPool* pool,
                      double* prof_ms, int64_t* prof_launches) {
-  hipError_t e = hipSuccess;
+  if (nsteps <= 0) return hipSuccess;
+  hipError_t e = prologue(*ex, s);
+  if (e) return e;
   if (profile) {
     const int64_t chunk = 4096;
     for (int64_t done = 0; done < nsteps && !e; done += chunk) {
       const int64_t n = std::min(chunk, nsteps - done);
       e = pool->ensure((size_t)(2 * n));
       for (int64_t k = 0; k < n && !e; ++k)
-        e = launch_step(*ex, s, true, pool->ev[2 * k], pool->ev[2 * k + 1]);
-      if (!e) e = hipEventSynchronize(pool->ev[2 * n - 1]);
+        e = launch_step(*ex, s, ex->aux, true, pool->ev[2 * k], pool->ev[2 * k + 1]);
+      if (!e) e = hipStreamSynchronize(s);
       for (int64_t k = 0; k < n && !e; ++k) {
         float ms = 0.f;
         e = hipEventElapsedTime(&ms, pool->ev[2 * k], pool->ev[2 * k + 1]);
@@ -316,7 +383,7 @@ hipError_t run_steps(Exec* ex, int64_t nsteps, hipStream_t s, bool profile, Even
       left -= kGraphSteps;
     }
   }
-  for (int64_t k = 0; k < left && !e; ++k) e = launch_step(*ex, s, false, nullptr, nullptr);
+  for (int64_t k = 0; k < left && !e; ++k) e = launch_step(*ex, s, ex->aux, false, nullptr, nullptr);
   return e;
 }
 
@@ -414,11 +481,13 @@ int sbiem_stress(sbiem_plan* p, const double* slip_hist, int64_t nt, double dt, 
   DevArena tmp;
   const int M = (int)(N / 2 + 1);
   const int64_t nint = nt;
+  const int64_t nsig = std::max<int64_t>(nint, 1);
   double* d_hist = (double*)tmp.get((size_t)(nt + 1) * N * sizeof(double));
-  double* d_rates = (double*)tmp.get((size_t)std::max<int64_t>(nint, 1) * N * sizeof(double));
-  double2* RV = (double2*)tmp.get((size_t)std::max<int64_t>(nint, 1) * M * sizeof(double2));
-  double2* RG = (double2*)tmp.get((size_t)std::max<int64_t>(nint, 1) * M * sizeof(double2));
-  if (!d_hist || !d_rates || !RV || !RG) {
+  double* d_rates = (double*)tmp.get((size_t)nsig * N * sizeof(double));
+  double2* RV = (double2*)tmp.get((size_t)nsig * M * sizeof(double2));
+  double2* RG = (double2*)tmp.get((size_t)nsig * M * sizeof(double2));
+  void* gF = tmp.get((size_t)nsig * N * sizeof(double2));
+  if (!d_hist || !d_rates || !RV || !RG || !gF) {
     delete ex;
     delete dyn;
     delete dtd;
@@ -429,26 +498,26 @@ int sbiem_stress(sbiem_plan* p, const double* slip_hist, int64_t nt, double dt, 
   if (!e && nint > 0) e = launch_rates(d_hist, d_rates, (long long)nint * N, N, dt, s);
   const FaultDev* dfd = ex->d_faults;
   if (!e && nint > 0)
-    e = launch_spectra(dfd, p->precision, (int)N, d_rates, nullptr, 1.0, RV, RG, (int)nint, N, M, s);
+    e = launch_forward(dfd, f, p->precision, d_rates, RV, RG, (int)nint, M, gF, s);
   // static part on snapshot nt-1 (its slip plus dt times the last rate is snapshot nt)
   const int64_t base = nint > 0 ? nt - 1 : 0;
   if (!e)
-    e = launch_spectra(dfd, p->precision, (int)N, d_hist + base * N, nullptr, 1.0, dyn->u_hat,
-                       dyn->g_hat, 1, 0, 0, s);
+    e = launch_forward(dfd, f, p->precision, d_hist + base * N, dyn->u_hat, dyn->g_hat, 1, M, gF, s);
   if (!e && nint > 0) {
     e = hipMemcpyAsync(dyn->v_hat0, RV + (nint - 1) * M, M * sizeof(double2), hipMemcpyDeviceToDevice, s);
     if (!e) e = hipMemcpyAsync(dyn->gv_hat0, RG + (nint - 1) * M, M * sizeof(double2), hipMemcpyDeviceToDevice, s);
   }
   if (!e) e = launch_fill_ring(dfd, p->precision, M - 1, RV, RG, (int)nint, s);
-  if (!e) e = launch_prepare(dfd, M - 1, s);
   const long long step = nint > 0 ? nint - 1 : 0;
   if (!e) e = hipMemcpyAsync(dyn->step, &step, sizeof(step), hipMemcpyHostToDevice, s);
-  if (!e) e = launch_conv(*ex, s);
-  if (!e) e = launch_pass1(*ex, s);
+  if (!e) e = hipStreamSynchronize(s);  // step lives on the host stack
+  dyn->primed = false;
+  if (!e) e = prologue(*ex, s);
+  if (!e) e = launch_elems(*ex, 0, s);
   if (!e) e = hipStreamSynchronize(s);
   const int slot = (int)((step + 1) & 1);
-  if (!e) e = hipMemcpy(tau_out, dyn->tau_el[slot], N * sizeof(double), hipMemcpyDeviceToHost);
-  if (!e) e = hipMemcpy(sigma_out, dyn->sigma_el[slot], N * sizeof(double), hipMemcpyDeviceToHost);
+  if (!e) e = download_elems(p, dyn->tau_el[slot], tau_out);
+  if (!e) e = download_elems(p, dyn->sigma_el[slot], sigma_out);
   delete ex;
   delete dyn;
   delete dtd;

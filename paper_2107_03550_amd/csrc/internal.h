@@ -18,49 +18,73 @@ namespace sbiem {
 // aX = (1-r) dt + w0X (the predicted slip dt vc plus the current interval).
 struct ModeCoef {
   double mk, ms, aT, aN, w1T, w1N;
-  int part0;    // second conv partial of the mode (the first is parts[n])
-  int nparts;   // number of partials (0: no history records)
+  long long ring_off;  // first ring record of the mode
+  int Rn;              // ring capacity M_n - 1 (0: no history records)
+  int part0;           // index of the mode's second conv partial (the first is
+                       // at the mode's own position)
+  int nparts;          // number of partials (0: no history records)
+  int pad;
 };
+
+// ---------------------------------------------------------------------------
+// Index maps of the four-step transforms.  N = P Q (powers of two, P <= Q).
+// Element i belongs to class b = i mod Q (P elements i = b + Q a); spectral
+// index n in [0, N) belongs to class c = n mod P (Q entries n = c + P d).
+// Per-element arrays are stored class-major (position b P + a), so one
+// element workgroup reads a contiguous block; per-mode arrays (modes
+// 0..N/2) are stored at mode_pos(n) = (n mod P) Q/2 + n div P for n < N/2
+// and N/2 for the Nyquist mode, so the modes of one class are contiguous.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int elem_pos(int i, int log2P, int log2Q) {
+  return ((i & ((1 << log2Q) - 1)) << log2P) + (i >> log2Q);
+}
+__host__ __device__ inline int mode_pos(int n, int log2P, int log2Q) {
+  const int half = 1 << (log2P + log2Q - 1);
+  if (n >= half) return half;
+  return ((n & ((1 << log2P) - 1)) << (log2Q - 1)) + (n >> log2P);
+}
 
 // ---------------------------------------------------------------------------
 // Device-visible description of one fault at one time step.  One array of
 // these per execution context (a plan, a batch, a stress evaluation); the
-// kernels index it by fault number.  Mode index n runs over 0..N/2 in every
-// per-mode array (mode 0 carries no elastic term).
+// kernels index it by fault number.
 // ---------------------------------------------------------------------------
 struct FaultDev {
   int N, log2N, nmodes;     // nmodes = N/2
+  int P, Q, log2P, log2Q;   // N = P Q (see the index maps above)
+  int ngroups;              // mode workgroups: classes {g, P-g} (g = 0: {0, P/2})
+  int ncls;                 // element classes per element workgroup
   int theta_mode;
   double L, mu, r, cs, dt, eta_rad;
   double V_pl, Dc, V_ref, f0, tau_rate, t0, ln_V_ref;
 
-  // per element (FP64, length N)
+  // per element (FP64, length N, class-major positions)
   const double *a, *b, *sigma_load, *tau_load, *kappa;
   double *slip[2], *V[2], *theta[2], *thd[2];  // committed state at [step & 1]
   double *V1, *thd1;                           // pass-1 solution
   double *tau_el[2], *sigma_el[2];             // last pass of the step at [(step+1) & 1]
 
-  // spectral state (FP64 complex, length N/2+1)
+  // spectral state (FP64 complex, modes 0..N/2 at mode_pos)
   double2 *u_hat, *g_hat;       // F[slip - V_pl t], F[kappa (slip - V_pl t)]
   double2 *v_hat0, *gv_hat0;    // F[V - V_pl], F[kappa (V - V_pl)] at step start
   double2 *v_hat1, *gv_hat1;    // same for the pass-1 solution
   double2 *hprev_v, *hprev_g;   // rate spectra of the last committed interval
-  double2 *P_T, *P_N;           // (1-r) u_hat + w1 hprev, set at commit
-  double2 *B_T, *B_N;           // P + history sum S, set by pass 1 for pass 2
-  int* inv_exp;                 // log2 balancing scale of the inverse packing
+  double2 *B_T, *B_N;           // (1-r) u_hat + w1 hprev + S, pass 1 -> pass 2
   double fwd_scale;             // power of two ~ 1/max|kappa| for the forward packing
 
-  // per mode (length N/2+1)
+  // transform exchange buffers (N complex, convolution precision)
+  void* gI;                     // inverse transform after the mode stage: [b][c]
+  void* gF;                     // forward transform after the element stage: [c][b]
+  int* cells;                   // [0..1] log2 maxima (tau, sigma) of pass 1,
+                                // [2..3] of pass 2, [4] balance exponent in use
+  int* done;                    // mode workgroups finished in the commit launch
+
+  // per mode (modes 0..N/2 at mode_pos)
   const ModeCoef* coef;
-  const int* Rn;                // ring capacity M_n - 1 (0 for mode 0)
-  const long long* ring_off;    // first ring record of mode n
-  const double* theta_h;        // FP32 weights: c_s |k_n| dt / 2 / table spacing
   double4* parts;               // conv partials: (S_T re, im, S_N re, im)
 
   void* ring;                   // history records: float4 or 2 x double2 per slot
   const double2* wrev;          // FP64 weights per ring slot (see conv kernel)
-
-  void* zbuf;                   // N complex in convolution precision (FFT input)
   const void* twiddle;          // N/4+1 values cos(2 pi t / N), convolution precision
 
   long long* step;              // committed steps since state/dt were set
@@ -92,8 +116,8 @@ constexpr int kTaskTiles = 16;  // at most this many tiles per task
 constexpr int kTileSlots32 = 512;   // FP32 records per wavefront tile
 constexpr int kTileSlots64 = 256;   // FP64 records per wavefront tile
 constexpr int kConvThreads = 512;   // 8 wavefronts
-constexpr int kSpecThreads = 1024;  // spectral (FFT) kernels
-constexpr int kNewtonThreads = 64;
+constexpr int kModeThreads = 256;   // mode-stage workgroups
+constexpr int kElemThreads = 256;   // element-stage workgroups
 constexpr double kTableStep = 1.0 / 16.0;  // spacing of the FP32 kernel table in T
 constexpr int kMaxLdsBytes = 160 * 1024;
 constexpr int kMaxDynLds = kMaxLdsBytes - 4096;  // room for static LDS (reductions)
@@ -135,10 +159,7 @@ struct DtData {
   std::vector<int> part0, nparts;
   int table_len = 0;             // FP32 table nodes
   DevArena mem;
-  ModeCoef* coef = nullptr;
-  double* theta_h = nullptr;
-  int* d_Rn = nullptr;
-  long long* d_ring_off = nullptr;
+  ModeCoef* coef = nullptr;      // at mode_pos
   double4* parts = nullptr;
   void* ring = nullptr;
   double2* wrev = nullptr;
@@ -150,11 +171,14 @@ struct DynData {
   DevArena mem;
   double *slip[2], *V[2], *theta[2], *thd[2], *V1, *thd1, *tau_el[2], *sigma_el[2];
   double2 *u_hat, *g_hat, *v_hat0, *gv_hat0, *v_hat1, *gv_hat1, *hprev_v, *hprev_g, *B_T,
-      *B_N, *P_T, *P_N;
-  int* inv_exp;
-  void* zbuf;
+      *B_N;
+  void *gI, *gF;
+  int *cells, *done;
   long long* step;
   int *err, *err_count, *err_index;
+  // the pass-1 spectra of the next step are in gI/B (set by a step's last
+  // launch; cleared whenever the state, dt or frame changes)
+  bool primed = false;
 };
 
 // Events bracketing conv launches while profiling (two per step, reused).
@@ -174,9 +198,12 @@ struct Exec {
   int ntiles = 0;
   ConvTask* d_tasks = nullptr;
   int ntasks = 0;
-  int2* d_newton_map = nullptr;  // per Newton block: fault, first element
-  int newton_blocks = 0;
-  int max_N = 0;
+  int2* d_mode_map = nullptr;    // per mode workgroup: fault, group
+  int mode_blocks = 0;
+  int2* d_elem_map = nullptr;    // per element workgroup: fault, first class
+  int elem_blocks = 0;
+  size_t mode_lds = 0, elem_lds = 0;
+  std::vector<DynData*> dyns;
   const float4* table = nullptr;  // FP32 kernel table (shared by all faults)
   int table_len = 0;
   int conv_grid = 0;
@@ -186,6 +213,8 @@ struct Exec {
   hipGraph_t graph_def = nullptr;
   int graph_steps = 0;
   hipStream_t graph_stream = nullptr;
+  hipStream_t aux = nullptr;     // second stream: the next step's convolution
+  hipEvent_t fork = nullptr, join = nullptr;
   ~Exec();
   void drop_graph();
 };
@@ -198,7 +227,7 @@ struct sbiem_plan {
   std::string last_error;
 
   int64_t N = 0;
-  int log2N = 0;
+  int log2N = 0, log2P = 0, log2Q = 0, ncls = 1;
   double L = 0, mu = 0, nu = 0, cs = 0, cp = 0, r = 0;
   int precision = SBIEM_FP64;
   int theta_mode = SBIEM_THETA_PAPER;
@@ -244,6 +273,10 @@ int fail(sbiem_plan* p, int status, const std::string& msg);
 int fail_global(int status, const std::string& msg);
 int hip_fail(sbiem_plan* p, hipError_t e, const char* what);
 
+// Natural element order (host) <-> class-major device order.
+std::vector<double> to_elem_order(const sbiem_plan* p, const double* x);
+hipError_t download_elems(const sbiem_plan* p, const double* dev, double* host);
+
 // Build the descriptor of a fault for an execution context.
 FaultDev make_fault_desc(sbiem_plan* p, DtData* dtd, DynData* dyn, double V_pl, double t0);
 // Allocate tables/ring for dt (host side computations + uploads).
@@ -256,25 +289,29 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
                int precision, Exec** out, std::string* err);
 
 // kernels.hip launchers
-hipError_t launch_conv(const Exec& ex, hipStream_t s);
-hipError_t launch_pass1(const Exec& ex, hipStream_t s);
-hipError_t launch_newton(const Exec& ex, int pass, hipStream_t s);
-hipError_t launch_pass2(const Exec& ex, hipStream_t s);
-hipError_t launch_commit(const Exec& ex, hipStream_t s);
-hipError_t launch_step(const Exec& ex, hipStream_t s, bool profile, hipEvent_t e0, hipEvent_t e1);
-// one fault: forward FFT of two real FP64 signals packed as z = a + i b
-// (a, b device arrays of length N), unpacked spectra n = 0..N/2 into A, B
-hipError_t launch_spectra(const FaultDev* d_fault, int precision, int max_N, const double* a,
-                          const double* b, double scale_b_by_kappa, double2* A, double2* B,
-                          int count, long long stride_in, long long stride_out, hipStream_t s);
+// ahead = 0: sums for the pending step; 1: for the step after it (launched
+// beside the pending step's passes, which it does not conflict with)
+hipError_t launch_conv(const Exec& ex, int ahead, hipStream_t s);
+// mode stage: kind 0 = pass-1 assembly from the stored state (measure != 0:
+// only the balance maxima), 1 = pass 2, 2 = commit and next pass 1
+hipError_t launch_modes(const Exec& ex, int kind, int measure, hipStream_t s);
+// element stage: kind 0 = tractions only, 1 = pass 1, 2 = pass 2
+hipError_t launch_elems(const Exec& ex, int kind, hipStream_t s);
+// one fault: spectra A (of a) and B (of kappa a) at mode_pos for count real
+// signals a (natural element order, stride N); gF holds count * N complex
+hipError_t launch_forward(const FaultDev* d_fault, const FaultDev& h_fault, int precision,
+                          const double* a, double2* A, double2* B, int count, long long stride_out,
+                          void* gF, hipStream_t s);
 // stress-only path: fill the ring of a fault from interval spectra
 hipError_t launch_fill_ring(const FaultDev* d_fault, int precision, int nmodes,
                             const double2* RV, const double2* RG, int nint, hipStream_t s);
-// P = (1-r) u_hat + w1 hprev for every mode and an unset inverse scale
-hipError_t launch_prepare(const FaultDev* d_fault, int nmodes, hipStream_t s);
 hipError_t launch_rates(const double* hist, double* rates, long long count, long long N, double dt,
                         hipStream_t s);
 int conv_grid_size(int precision, int ntasks, int table_len);
 hipError_t setup_kernel_attributes(int precision);
+size_t mode_lds_bytes(int precision, int log2Q);
+size_t elem_lds_bytes(int precision, int log2P, int ncls);
+// N = P Q with P = 2^floor(log2 N / 2); classes per element workgroup
+void split_sizes(int log2N, int* log2P, int* log2Q, int* ncls);
 
 }  // namespace sbiem

@@ -1,18 +1,19 @@
 // HIP kernels of the sBIEM time step for gfx950 (CDNA4, wave64).
 //
-// One step (section 3.3) is five launches over every fault of a context:
-//   k_conv    history sums over lags >= 2 of every mode (HBM-bound stream of
-//             the wavenumber-major ring; one wavefront per tile of records)
-//   k_pass1   per fault, one workgroup: reduce the conv partials, assemble
-//             the traction spectra of pass 1 (section 3.1 + current interval
-//             + last interval), inverse FFT in LDS -> tau^el(x), sigma^el(x)
-//   k_newton  per element: predictor, momentum balance (Newton on ln V),
-//             aging law; writes the FFT input (V_p - V_pl) + i kappa (V_p - V_pl)
-//   k_pass2   per fault: forward FFT of the pass-1 rates, pass-2 assembly
-//             with V_c = (V_0 + V_1)/2, inverse FFT
-//   k_newton  pass 2 (writes the next state)
-//   k_commit  per fault: forward FFT of V_2, push (V_0 + V_1)/2 into the ring,
-//             advance the spectral slip and the step counter
+// One step (section 3.3) runs over every fault of a context as
+//   k_conv     history sums over lags >= 2 of every mode for the NEXT step
+//              (HBM-bound stream of the wavenumber-major ring), on a second
+//              stream beside the three launches below
+//   k_elems<1> inverse-transform finish -> tau^el, sigma^el; pass-1 momentum
+//              balance per element (Newton on ln V); forward-transform start
+//   k_modes<1> forward-transform finish -> rate spectra of pass 1; pass-2
+//              traction assembly; inverse-transform start
+//   k_elems<2> the same for pass 2 (writes the next state)
+//   k_modes<2> forward-transform finish of V_2; commit (ring push of the
+//              interval rate, spectral slip, step counter) and the pass-1
+//              assembly of the next step with the sums k_conv produced
+// The transforms are four-step FFTs split between element and mode
+// workgroups (see the index maps in internal.h).
 #include "internal.h"
 
 #include <hip/hip_runtime.h>
@@ -47,12 +48,8 @@ __device__ __forceinline__ double2 d2add(double2 a, double2 b) { return d2(a.x +
 __device__ __forceinline__ double2 d2scale(double2 a, double s) { return d2(a.x * s, a.y * s); }
 
 // ---------------------------------------------------------------------------
-// LDS-resident radix-8/4/2 Stockham FFT (forward, exp(-2 pi i n k / N)).
-// Pass with radix RD after sub-transforms of length p: butterfly i takes
-// x[i + r N/RD], twiddles by exp(-2 pi i r k / (p RD)) with k = i mod p, and
-// writes the RD outputs to (i - k) RD + k + s p.  Every thread first loads
-// all inputs of its butterflies, then (after a barrier) writes the outputs,
-// so one LDS buffer suffices.
+// Radix-8/4/2 butterflies and twiddles for LDS Stockham FFTs (forward,
+// exp(-2 pi i n k / M)).
 // ---------------------------------------------------------------------------
 template <typename C> __device__ __forceinline__ void dft2(C* x) {
   C a = x[0], b = x[1];
@@ -111,75 +108,10 @@ __device__ __forceinline__ C twiddle_half(const R* __restrict__ q, int m, int N)
 // spreads the power-of-two strides of the Stockham passes over all banks.
 __device__ __forceinline__ int lx(int x, int ps) { return x + (x >> ps); }
 
-template <typename C, typename R, int LR, int MAXPTS>
-__device__ __forceinline__ void fft_pass(C* buf, int N, int p, const R* __restrict__ q, int ps) {
-  constexpr int RD = 1 << LR;
-  constexpr int MAXB = ((MAXPTS >> LR) + kSpecThreads - 1) / kSpecThreads;
-  const int nb = N >> LR;
-  C x[MAXB][RD];
-#pragma unroll
-  for (int b = 0; b < MAXB; ++b) {
-    const int i = threadIdx.x + b * kSpecThreads;
-    if (i < nb) {
-#pragma unroll
-      for (int r = 0; r < RD; ++r) x[b][r] = buf[lx(i + r * nb, ps)];
-    }
-  }
-  __syncthreads();
-  const int tws = N / (p * RD);
-#pragma unroll
-  for (int b = 0; b < MAXB; ++b) {
-    const int i = threadIdx.x + b * kSpecThreads;
-    if (i < nb) {
-      const int k = i & (p - 1);
-      if (p > 1) {
-        // w^r = exp(-2 pi i r k / (p RD)) from one lookup and products
-        const C w1 = twiddle_half<C, R>(q, k * tws, N);
-        x[b][1] = cmul(x[b][1], w1);
-        if (RD >= 4) {
-          const C w2 = cmul(w1, w1);
-          const C w3 = cmul(w2, w1);
-          x[b][2] = cmul(x[b][2], w2);
-          x[b][3] = cmul(x[b][3], w3);
-          if (RD == 8) {
-            const C w4 = cmul(w2, w2);
-            x[b][4] = cmul(x[b][4], w4);
-            x[b][5] = cmul(x[b][5], cmul(w4, w1));
-            x[b][6] = cmul(x[b][6], cmul(w4, w2));
-            x[b][7] = cmul(x[b][7], cmul(w4, w3));
-          }
-        }
-      }
-      if (RD == 8) dft8(x[b]);
-      else if (RD == 4) dft4(x[b][0], x[b][1], x[b][2], x[b][3]);
-      else dft2(x[b]);
-      const int base = (i - k) * RD + k;
-#pragma unroll
-      for (int s = 0; s < RD; ++s) buf[lx(base + s * p, ps)] = x[b][s];
-    }
-  }
-  __syncthreads();
-}
-
-// Forward FFT of buf[0..N) in LDS (q: quarter-wave table in LDS); the caller
-// has synchronised after filling both.
-template <typename C, typename R, int MAXPTS>
-__device__ __forceinline__ void fft_lds(C* buf, int N, int log2N, const R* __restrict__ q, int ps) {
-  int p = 1, rem = log2N;
-  while (rem >= 3) {
-    fft_pass<C, R, 3, MAXPTS>(buf, N, p, q, ps);
-    p <<= 3;
-    rem -= 3;
-  }
-  if (rem == 2) fft_pass<C, R, 2, MAXPTS>(buf, N, p, q, ps);
-  else if (rem == 1) fft_pass<C, R, 1, MAXPTS>(buf, N, p, q, ps);
-}
-
 template <typename R> struct Prec;
 template <> struct Prec<float> {
   using C = float2;
   using Rec = float4;  // (v_re, v_im, g_re, g_im)
-  static constexpr int kMaxPts = 16384;
   static constexpr int kTile = kTileSlots32;
 };
 struct Rec64 {
@@ -188,29 +120,20 @@ struct Rec64 {
 template <> struct Prec<double> {
   using C = double2;
   using Rec = Rec64;
-  static constexpr int kMaxPts = 8192;
   static constexpr int kTile = kTileSlots64;
 };
 
-// LDS bytes of a spectral kernel for N points: padded data + quarter table.
-template <typename R>
-__host__ __device__ inline size_t spec_lds_bytes(int N, int ps) {
-  return (size_t)(N + (N >> ps)) * sizeof(typename Prec<R>::C) + (size_t)(N / 4 + 1) * sizeof(R);
-}
-// Pad one element in 8 when it fits, else one in 16.
-template <typename R>
-__host__ __device__ inline int pad_shift(int N) {
-  return spec_lds_bytes<R>(N, 3) <= (size_t)kMaxDynLds ? 3 : 4;
-}
-
 // ---------------------------------------------------------------------------
-// History convolution.  Slot p of mode n's ring holds interval
-// I(p) = b - ((b - p) mod R_n) with b = step - 1 the last committed interval;
-// its lag at this step is j = 1 + ((b - p) mod R_n).  The slot of lag 1
-// (p = b mod R_n) is skipped here (the spectral kernels add it from hprev),
-// which also makes this launch independent of the step's own commit.
-// The weight of slot p is at q = (p - b) mod R_n = (p + o) mod R_n with
-// o = (-b) mod R_n: q = 0 is the skipped slot, lag j = R_n - q + 1 otherwise.
+// History convolution for step s (s = the committed-step counter, plus one
+// when the launch computes the sums a step ahead).  Slot p of mode n's ring
+// holds interval I(p) = b - ((b - p) mod R_n) with b = s - 1 the last
+// interval committed before step s; its lag at step s is
+// j = 1 + ((b - p) mod R_n).  The slot of lag 1 (p = b mod R_n) is skipped
+// here (the mode stage adds it from h_prev): it is the slot that step s - 1
+// commits into, so the sums for step s can run while step s - 1 is still in
+// its passes.  The weight of slot p is at q = (p - b) mod R_n = (p + o) mod R_n
+// with o = (-b) mod R_n: q = 0 is the skipped slot, lag j = R_n - q + 1
+// otherwise.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float4 wave_reduce4(float4 v) {
 #pragma unroll
@@ -282,7 +205,7 @@ __device__ __forceinline__ void finish_task(const FaultDev& fd, const TaskLds& L
 
 __global__ void __launch_bounds__(kConvThreads)
 k_conv64(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
-         const ConvTask* __restrict__ tasks, int ntasks) {
+         const ConvTask* __restrict__ tasks, int ntasks, int ahead) {
   constexpr int U = kTileSlots64 / 64;
   __shared__ TaskLds L;
   const int lane = threadIdx.x & 63;
@@ -293,7 +216,7 @@ k_conv64(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
     const int nt = tk.t1 - tk.t0;
     const FaultDev& fd = faults[tiles[tk.t0].fault];
     const int err = *fd.err;
-    const long long step = *fd.step;
+    const long long step = *fd.step + ahead;
     for (int k = wave; k < nt; k += wpb) {
       const Tile tl = tiles[tk.t0 + k];
       Rec64 acc;
@@ -349,7 +272,7 @@ k_conv64(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
 __global__ void __launch_bounds__(kConvThreads)
 k_conv32(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
          const ConvTask* __restrict__ tasks, int ntasks, const float4* __restrict__ table,
-         int table_len) {
+         int table_len, int ahead) {
   constexpr int U = kTileSlots32 / 64;
   extern __shared__ float4 tab[];
   __shared__ TaskLds L;
@@ -363,7 +286,7 @@ k_conv32(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
     const int nt = tk.t1 - tk.t0;
     const FaultDev& fd = faults[tiles[tk.t0].fault];
     const int err = *fd.err;
-    const long long step = *fd.step;
+    const long long step = *fd.step + ahead;
     for (int k = wave; k < nt; k += wpb) {
       const Tile tl = tiles[tk.t0 + k];
       float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -418,82 +341,125 @@ k_conv32(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
 }
 
 // ---------------------------------------------------------------------------
-// Spectral kernels (one workgroup per fault, N complex in LDS)
+// Four-step transforms across workgroups.  N = P Q; element i = b + Q a
+// (class b), spectral index n = c + P d (class c).
+//
+// Forward, X_n = sum_i x_i w_N^{i n} (w_M = exp(-2 pi i / M)):
+//   element stage, class b:  Y_b[c] = w_N^{b c} sum_a x_{b+Qa} w_P^{a c}
+//                            -> gF[c Q + b]
+//   mode stage, class c:     X_{c+Pd} = sum_b Y_b[c] w_Q^{b d}
+// Inverse of a Hermitian-packed spectrum Z, computed as conj(FFT(conj Z))/N:
+//   mode stage, class c:     W_c[b] = w_N^{c b} sum_d conj(Z_{c+Pd}) w_Q^{d b}
+//                            -> gI[b P + c]
+//   element stage, class b:  N conj(x_{b+Qa}) = sum_c W_c[b] w_P^{c a}
+// The element stage of the inverse leaves element b + Q a where the forward
+// element stage wants it, so the friction solve between them needs no
+// exchange; a mode workgroup owns the classes {c, P - c}, which hold every
+// index n together with its mirror N - n, so packing and unpacking the two
+// real signals of a transform stay inside the workgroup.
 // ---------------------------------------------------------------------------
-// Block-wide maxima of two non-negative values (all threads get the result).
-__device__ __forceinline__ void block_max2(double& a, double& b) {
-  constexpr int W = kSpecThreads / 64;
-  __shared__ double red[2][W];
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    a = fmax(a, __shfl_xor(a, off));
-    b = fmax(b, __shfl_xor(b, off));
+
+// exp(-2 pi i m / N) for m in [0, N) from the global quarter-wave table.
+template <typename C, typename R>
+__device__ __forceinline__ C twiddle_full(const R* __restrict__ q, int m, int N) {
+  const int h = N >> 1;
+  C w = twiddle_half<C, R>(q, m & (h - 1), N);
+  if (m >= h) {
+    w.x = -w.x;
+    w.y = -w.y;
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) {
-    red[0][wave] = a;
-    red[1][wave] = b;
-  }
-  __syncthreads();
-  double ra[W], rb[W];
+  return w;
+}
+
+// Vector stride (complex elements) of an M-point vector with one pad per 8.
+__host__ __device__ inline int vstride(int M) { return M + (M >> 3); }
+
+// One Stockham pass with radix 2^LR after sub-transforms of length p, over
+// nvec vectors of M = 2^lm points: butterfly j takes x[j + r M/RD], applies
+// exp(-2 pi i r k / (p RD)) with k = j mod p and writes the RD outputs to
+// (j - k) RD + k + s p.  Out of place (src -> dst), then a barrier.
+template <typename C, typename R, int LR>
+__device__ __forceinline__ void fft_pass_b(const C* __restrict__ src, C* __restrict__ dst, int nvec,
+                                           int lm, int p, const R* __restrict__ q) {
+  constexpr int RD = 1 << LR;
+  const int M = 1 << lm;
+  const int nb = M >> LR;
+  const int total = nvec << (lm - LR);
+  const int vs = vstride(M);
+  const int tws = M / (p * RD);
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int v = t >> (lm - LR);
+    const int j = t & (nb - 1);
+    const C* s = src + v * vs;
+    C x[RD];
 #pragma unroll
-  for (int w = 0; w < W; ++w) {
-    ra[w] = red[0][w];
-    rb[w] = red[1][w];
-  }
-  a = 0.0;
-  b = 0.0;
+    for (int r = 0; r < RD; ++r) x[r] = s[lx(j + r * nb, 3)];
+    const int k = j & (p - 1);
+    if (p > 1) {
+      const C w1 = twiddle_half<C, R>(q, k * tws, M);
+      x[1] = cmul(x[1], w1);
+      if (RD >= 4) {
+        const C w2 = cmul(w1, w1);
+        const C w3 = cmul(w2, w1);
+        x[2] = cmul(x[2], w2);
+        x[3] = cmul(x[3], w3);
+        if (RD == 8) {
+          const C w4 = cmul(w2, w2);
+          x[4] = cmul(x[4], w4);
+          x[5] = cmul(x[5], cmul(w4, w1));
+          x[6] = cmul(x[6], cmul(w4, w2));
+          x[7] = cmul(x[7], cmul(w4, w3));
+        }
+      }
+    }
+    if (RD == 8) dft8(x);
+    else if (RD == 4) dft4(x[0], x[1], x[2], x[3]);
+    else dft2(x);
+    C* d = dst + v * vs;
+    const int base = (j - k) * RD + k;
 #pragma unroll
-  for (int w = 0; w < W; ++w) {
-    a = fmax(a, ra[w]);
-    b = fmax(b, rb[w]);
+    for (int r = 0; r < RD; ++r) d[lx(base + r * p, 3)] = x[r];
   }
   __syncthreads();
 }
 
-// Power of two closest to x/y (1 when either is zero or not finite).  Two
-// real signals packed into one complex transform share its rounding error;
-// scaling the smaller one up by an exact power of two keeps each at its own
-// relative accuracy.
-__device__ __forceinline__ double pow2_ratio(double x, double y) {
-  if (!(x > 0.0) || !(y > 0.0) || !isfinite(x) || !isfinite(y)) return 1.0;
-  return ldexp(1.0, ilogb(x) - ilogb(y));
+// Forward FFT of nvec vectors of 2^lm points held in a (natural order,
+// padded); b is scratch of the same size; q is the LDS table cos(2 pi r / M),
+// r = 0..M/4.  The caller has synchronised after filling a and q.  Returns
+// the buffer that holds the transforms (natural order).
+template <typename C, typename R>
+__device__ __forceinline__ C* fft_batch(C* a, C* b, int nvec, int lm, const R* __restrict__ q) {
+  int p = 1, rem = lm;
+  C* src = a;
+  C* dst = b;
+  while (rem > 0) {
+    if (rem >= 3) {
+      fft_pass_b<C, R, 3>(src, dst, nvec, lm, p, q);
+      p <<= 3;
+      rem -= 3;
+    } else if (rem == 2) {
+      fft_pass_b<C, R, 2>(src, dst, nvec, lm, p, q);
+      p <<= 2;
+      rem -= 2;
+    } else {
+      fft_pass_b<C, R, 1>(src, dst, nvec, lm, p, q);
+      p <<= 1;
+      rem -= 1;
+    }
+    C* t = src;
+    src = dst;
+    dst = t;
+  }
+  return src;
 }
 
-// LDS layout of the spectral kernels: N complex values (padded), then the
-// quarter-wave twiddle table (N/4 + 1 reals) copied from global memory.
-template <typename R, int MAXPTS>
-__device__ __forceinline__ const R* load_quarter_table(typename Prec<R>::C* buf, const FaultDev& fd) {
-  constexpr int K = (MAXPTS / 4) / kSpecThreads + 1;
-  R* q = reinterpret_cast<R*>(buf + fd.N + (fd.N >> pad_shift<R>(fd.N)));
+// LDS table cos(2 pi r / M), r = 0..M/4, from the fault's N-point table.
+template <typename R>
+__device__ __forceinline__ void load_sub_table(R* q, const FaultDev& fd, int lm) {
   const R* __restrict__ g = (const R*)fd.twiddle;
-  const int Q = fd.N >> 2;
-  R v[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = g[min((int)threadIdx.x + k * kSpecThreads, Q)];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = threadIdx.x + k * kSpecThreads;
-    if (i <= Q) q[i] = v[k];
-  }
-  return q;
-}
-
-// Copy the FFT input z (the Newton kernel has already scaled its curvature
-// half by fwd_scale) into LDS; all loads of a thread are issued first.
-template <typename R, int MAXPTS>
-__device__ __forceinline__ void load_input(typename Prec<R>::C* buf, int N,
-                                           const typename Prec<R>::C* __restrict__ z, int ps) {
-  using C = typename Prec<R>::C;
-  constexpr int K = MAXPTS / kSpecThreads;
-  C v[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = z[min((int)threadIdx.x + k * kSpecThreads, N - 1)];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = threadIdx.x + k * kSpecThreads;
-    if (i < N) buf[lx(i, ps)] = v[k];
-  }
+  const int M4 = (1 << lm) >> 2;
+  const int stride = fd.N >> lm;
+  for (int r = threadIdx.x; r <= M4; r += blockDim.x) q[r] = g[r * stride];
 }
 
 // Traction spectra of mode n (section 3.1; current interval rates vc, gvc):
@@ -506,44 +472,37 @@ __device__ __forceinline__ void traction_mode(const ModeCoef& c, double2 BT, dou
   *sig = d2(c.ms * ANy, -c.ms * ANx);  // -i ms AN
 }
 
-// Modes one thread owns in the spectral kernels (n = tid + s T).
-template <int MAXPTS>
-struct ModesPerThread {
-  static constexpr int value = (MAXPTS / 2 + kSpecThreads) / kSpecThreads;
-};
-
-constexpr int kInvExpUnset = -100000;
-
-// Exponent bookkeeping of the inverse packing: LDS cells for the block
-// maxima of ilogb|tau_hat| and ilogb|sigma_hat|.
-struct InvScale {
-  int tau_e, sig_e;
-};
-
-// log2 of the balancing factor from the two maxima (0 when either is zero).
-__device__ __forceinline__ int balance_exp(const InvScale* sc) {
-  if (sc->tau_e <= -2000 || sc->sig_e <= -2000) return 0;
-  return min(max(sc->tau_e - sc->sig_e, -256), 256);
+// History sum S of a mode: its first conv partial plus any further pieces.
+__device__ __forceinline__ double4 history_sum(const FaultDev& fd, const ModeCoef& c, int pm) {
+  double4 h = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (c.nparts > 0) h = fd.parts[pm];
+  for (int j = 1; j < c.nparts; ++j) {
+    const double4 b = fd.parts[c.part0 + j - 1];
+    h.x += b.x;
+    h.y += b.y;
+    h.z += b.z;
+    h.w += b.w;
+  }
+  return h;
 }
+
+constexpr int kNoExp = -2000;  // "no maximum yet" in the balance cells
 
 __device__ __forceinline__ int ilogb_or_min(double x) {
-  return (x > 0.0 && x <= 1.0e300) ? ilogb(x) : -2000;
+  return (x > 0.0 && x <= 1.0e300) ? ilogb(x) : kNoExp;
 }
 
-// Pack Z = tau_hat + i c sigma_hat (c = 2^e, e from the previous pass or, on
-// the first pass after a reset, from this pass's maxima) as conj(Z), inverse
-// transform in LDS and write tau^el, sigma^el; record this pass's maxima for
-// the next pass.  The inverse of Z is conj(FFT(conj Z))/N.
-template <typename R, int MAXPTS>
-__device__ __forceinline__ void invert_tractions(const FaultDev& fd, typename Prec<R>::C* buf,
-                                                 const R* q, const typename Prec<R>::C* tau,
-                                                 const typename Prec<R>::C* sig, double mt,
-                                                 double ms, InvScale* sc, int e_prev) {
-  using C = typename Prec<R>::C;
-  constexpr int kPer = ModesPerThread<MAXPTS>::value;
-  const int N = fd.N, half = fd.nmodes;
-  const int ps = pad_shift<R>(N);
-  // this pass's maxima: wave reduction, then an LDS atomic per wave
+// log2 of the balance factor c in Z = tau_hat + i c sigma_hat from the two
+// maxima (0 when either is missing).
+__device__ __forceinline__ int balance_exp(int te, int se) {
+  if (te <= kNoExp || se <= kNoExp) return 0;
+  return min(max(te - se, -256), 256);
+}
+
+// Workgroup maximum of ilogb(mt), ilogb(ms) folded into two global cells
+// (LDS cells red[0..1] were set to kNoExp before the workgroup's first
+// barrier; ends with a barrier).
+__device__ __forceinline__ void fold_maxima(double mt, double ms, int* red, int* cell) {
   int et = ilogb_or_min(mt), es = ilogb_or_min(ms);
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
@@ -551,399 +510,379 @@ __device__ __forceinline__ void invert_tractions(const FaultDev& fd, typename Pr
     es = max(es, __shfl_xor(es, off));
   }
   if ((threadIdx.x & 63) == 0) {
-    atomicMax(&sc->tau_e, et);
-    atomicMax(&sc->sig_e, es);
-  }
-  int e = e_prev;
-  if (e == kInvExpUnset) {  // first pass after a reset: use this pass's maxima
-    __syncthreads();
-    e = balance_exp(sc);
-  }
-  const double c = ldexp(1.0, e);
-#pragma unroll
-  for (int sl = 0; sl < kPer; ++sl) {
-    const int n = threadIdx.x + sl * kSpecThreads;
-    if (n <= half) {
-      const double2 t = d2(tau[sl].x, tau[sl].y);
-      const double2 g = d2((double)sig[sl].x * c, (double)sig[sl].y * c);
-      buf[lx(n, ps)] = cmk<C>(t.x - g.y, -(t.y + g.x));
-      if (n > 0 && 2 * n < N) buf[lx(N - n, ps)] = cmk<C>(t.x + g.y, -(-t.y + g.x));
-    }
+    atomicMax(&red[0], et);
+    atomicMax(&red[1], es);
   }
   __syncthreads();
-  fft_lds<C, R, MAXPTS>(buf, N, fd.log2N, q, ps);
-  const int slot = (int)((*fd.step + 1) & 1);
-  double* __restrict__ to = fd.tau_el[slot];
-  double* __restrict__ so = fd.sigma_el[slot];
-  const double inv = 1.0 / N, invc = 1.0 / (c * N);
-  for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    const C z = buf[lx(i, ps)];
-    to[i] = (double)z.x * inv;
-    so[i] = -(double)z.y * invc;
-  }
-  // the FFT's barriers have ordered every atomicMax above
-  if (threadIdx.x == 0)
-    *fd.inv_exp = balance_exp(sc);
-}
-
-// Unpack the FFT Z of z = a + i s b (a, b real, s the forward scale) into
-// A_n, B_n, n = 0..N/2.
-template <typename C>
-__device__ __forceinline__ void unpack_mode(const C* buf, int N, int n, double inv_s, double2* A,
-                                            double2* B, int ps) {
-  const C zn = buf[lx(n, ps)];
-  const C zm = buf[lx(n == 0 ? 0 : N - n, ps)];
-  // A = (Z_n + conj Z_m)/2, B = (Z_n - conj Z_m)/(2i)
-  *A = d2(0.5 * ((double)zn.x + (double)zm.x), 0.5 * ((double)zn.y - (double)zm.y));
-  const double dx = (double)zn.x - (double)zm.x, dy = (double)zn.y + (double)zm.y;
-  *B = d2(0.5 * dy * inv_s, -0.5 * dx * inv_s);
-}
-
-__device__ __forceinline__ void init_inv_scale(InvScale* sc) {
   if (threadIdx.x == 0) {
-    sc->tau_e = -2000;
-    sc->sig_e = -2000;
+    if (red[0] > kNoExp) atomicMax(&cell[0], red[0]);
+    if (red[1] > kNoExp) atomicMax(&cell[1], red[1]);
   }
 }
 
-template <typename R, int MAXPTS>
-__global__ void __launch_bounds__(kSpecThreads)
-k_pass1(const FaultDev* __restrict__ faults) {
-  using C = typename Prec<R>::C;
-  constexpr int kPer = ModesPerThread<MAXPTS>::value;
-  extern __shared__ unsigned char smem_raw[];
-  __shared__ InvScale sc;
-  C* buf = reinterpret_cast<C*>(smem_raw);
-  const FaultDev& fd = faults[blockIdx.x];
-  const int err = *fd.err;
-  const int e_prev = *fd.inv_exp;
-  if (err) return;
-  init_inv_scale(&sc);
-  __syncthreads();  // the maxima cells are set before any wave updates them
-  const R* q = load_quarter_table<R, MAXPTS>(buf, fd);
-  const int half = fd.nmodes;
-  C tau[kPer], sig[kPer];
-  double mt = 0.0, ms = 0.0;
-  // groups of three modes: all loads of a group are issued before its stores
-  constexpr int G = (sizeof(R) == 4 && MAXPTS <= 8192) ? 2 : 1;
-#pragma unroll
-  for (int s0 = 0; s0 < kPer; s0 += G) {
-    double4 S[G];
-    double2 P[G][2], V[G][2];
-    ModeCoef cf[G];
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const int n = threadIdx.x + (s0 + k) * kSpecThreads;
-      if (s0 + k < kPer && n <= half) {
-        cf[k] = fd.coef[n];
-        S[k] = fd.parts[n];
-        P[k][0] = fd.P_T[n];
-        P[k][1] = fd.P_N[n];
-        V[k][0] = fd.v_hat0[n];
-        V[k][1] = fd.gv_hat0[n];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const int sl = s0 + k;
-      const int n = threadIdx.x + sl * kSpecThreads;
-      if (sl < kPer && n <= half) {
-        const ModeCoef& c = cf[k];
-        double4 h = c.nparts > 0 ? S[k] : make_double4(0.0, 0.0, 0.0, 0.0);
-        for (int j = 1; j < c.nparts; ++j) {  // further pieces of a long window
-          const double4 b = fd.parts[c.part0 + j - 1];
-          h.x += b.x;
-          h.y += b.y;
-          h.z += b.z;
-          h.w += b.w;
-        }
-        const double2 BT = d2(P[k][0].x + h.x, P[k][0].y + h.y);
-        const double2 BN = d2(P[k][1].x + h.z, P[k][1].y + h.w);
-        fd.B_T[n] = BT;
-        fd.B_N[n] = BN;
-        double2 t, g;
-        traction_mode(c, BT, BN, V[k][0], V[k][1], &t, &g);
-        tau[sl] = cmk<C>(t.x, t.y);
-        sig[sl] = cmk<C>(g.x, g.y);
-        mt = fmax(mt, fmax(fabs(t.x), fabs(t.y)));
-        ms = fmax(ms, fmax(fabs(g.x), fabs(g.y)));
-      }
-    }
-  }
-  invert_tractions<R, MAXPTS>(fd, buf, q, tau, sig, mt, ms, &sc, e_prev);
+// Mode workgroup (fault, group g) of a launch: map, or group = block index.
+__device__ __forceinline__ int2 work_item(const int2* __restrict__ map) {
+  return map ? map[blockIdx.x] : make_int2(0, (int)blockIdx.x);
 }
 
-template <typename R, int MAXPTS>
-__global__ void __launch_bounds__(kSpecThreads)
-k_pass2(const FaultDev* __restrict__ faults) {
-  using C = typename Prec<R>::C;
-  constexpr int kPer = ModesPerThread<MAXPTS>::value;
-  extern __shared__ unsigned char smem_raw[];
-  __shared__ InvScale sc;
-  C* buf = reinterpret_cast<C*>(smem_raw);
-  const FaultDev& fd = faults[blockIdx.x];
-  const int err = *fd.err;
-  const int e_prev = *fd.inv_exp;
-  if (err) return;
-  const int N = fd.N, half = fd.nmodes;
-  const int ps = pad_shift<R>(N);
-  init_inv_scale(&sc);
-  const R* q = load_quarter_table<R, MAXPTS>(buf, fd);
-  load_input<R, MAXPTS>(buf, N, (const C*)fd.zbuf, ps);
-  __syncthreads();
-  fft_lds<C, R, MAXPTS>(buf, N, fd.log2N, q, ps);
-  const double inv_s = 1.0 / fd.fwd_scale;
-  C tau[kPer], sig[kPer];
-  double mt = 0.0, ms = 0.0;
-  constexpr int G = (sizeof(R) == 4 && MAXPTS <= 8192) ? 2 : 1;
-#pragma unroll
-  for (int s0 = 0; s0 < kPer; s0 += G) {
-    double2 Bv[G][2], V0[G][2];
-    ModeCoef cf[G];
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const int n = threadIdx.x + (s0 + k) * kSpecThreads;
-      if (s0 + k < kPer && n <= half) {
-        cf[k] = fd.coef[n];
-        Bv[k][0] = fd.B_T[n];
-        Bv[k][1] = fd.B_N[n];
-        V0[k][0] = fd.v_hat0[n];
-        V0[k][1] = fd.gv_hat0[n];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const int sl = s0 + k;
-      const int n = threadIdx.x + sl * kSpecThreads;
-      if (sl < kPer && n <= half) {
-        double2 A, B;
-        unpack_mode(buf, N, n, inv_s, &A, &B, ps);
-        fd.v_hat1[n] = A;
-        fd.gv_hat1[n] = B;
-        const double2 vc = d2(0.5 * (V0[k][0].x + A.x), 0.5 * (V0[k][0].y + A.y));
-        const double2 gvc = d2(0.5 * (V0[k][1].x + B.x), 0.5 * (V0[k][1].y + B.y));
-        double2 t, g;
-        traction_mode(cf[k], Bv[k][0], Bv[k][1], vc, gvc, &t, &g);
-        tau[sl] = cmk<C>(t.x, t.y);
-        sig[sl] = cmk<C>(g.x, g.y);
-        mt = fmax(mt, fmax(fabs(t.x), fabs(t.y)));
-        ms = fmax(ms, fmax(fabs(g.x), fabs(g.y)));
-      }
-    }
-  }
-  __syncthreads();  // every unpack read of buf is done before the packing overwrites it
-  invert_tractions<R, MAXPTS>(fd, buf, q, tau, sig, mt, ms, &sc, e_prev);
+// ---------------------------------------------------------------------------
+// Mode stage.  KIND 0: pass-1 assembly from the stored state (prologue and
+// stress path); KIND 1: forward-transform finish of the pass-1 rates, pass-2
+// assembly; KIND 2: forward-transform finish of the pass-2 rates, commit
+// (ring push of (V_0 + V_1)/2, spectral slip, h_prev, V_0 <- V_2) and the
+// pass-1 assembly of the next step; KIND 3: forward-transform finish only,
+// spectra to (outA, outB).  Kinds 0-2 end with the first half of the
+// inverse transform into gI.
+// LDS: buffers A and B (two Q-point vectors each), then the Q-point table.
+// Every global load a thread needs for its first slot is issued at the top,
+// so the launch waits for memory once.
+// ---------------------------------------------------------------------------
+struct ModeIn {
+  ModeCoef cf;
+  double2 v0, gv0, v1, gv1, u, gg, hv, hg, BT, BN;
+  double4 S0;  // first conv partial
+};
+
+// Per-mode arrays of a fault (read from the descriptor once per launch).
+struct ModePtrs {
+  const ModeCoef* coef;
+  double4* parts;
+  double2 *u, *g, *v0, *gv0, *v1, *gv1, *hv, *hg, *BT, *BN;
+};
+
+__device__ __forceinline__ ModePtrs mode_ptrs(const FaultDev& fd) {
+  ModePtrs m;
+  m.coef = fd.coef;
+  m.parts = fd.parts;
+  m.u = fd.u_hat;
+  m.g = fd.g_hat;
+  m.v0 = fd.v_hat0;
+  m.gv0 = fd.gv_hat0;
+  m.v1 = fd.v_hat1;
+  m.gv1 = fd.gv_hat1;
+  m.hv = fd.hprev_v;
+  m.hg = fd.hprev_g;
+  m.BT = fd.B_T;
+  m.BN = fd.B_N;
+  return m;
 }
 
-template <typename R, int MAXPTS>
-__global__ void __launch_bounds__(kSpecThreads)
-k_commit(const FaultDev* __restrict__ faults) {
+template <int KIND>
+__device__ __forceinline__ void load_mode_in(const ModePtrs& f, int pm, ModeIn& m) {
+  m.cf = f.coef[pm];
+  m.v0 = f.v0[pm];
+  m.gv0 = f.gv0[pm];
+  if (KIND == 0 || KIND == 2) {
+    m.u = f.u[pm];
+    m.gg = f.g[pm];
+    m.S0 = f.parts[pm];
+  }
+  if (KIND == 0) {
+    m.hv = f.hv[pm];
+    m.hg = f.hg[pm];
+  }
+  if (KIND == 1) {
+    m.BT = f.BT[pm];
+    m.BN = f.BN[pm];
+  }
+  if (KIND == 2) {
+    m.v1 = f.v1[pm];
+    m.gv1 = f.gv1[pm];
+  }
+}
+
+// Slot t of a mode workgroup: vector v (class cls), entry d, index n.
+struct ModeSlot {
+  int v, d, cls, n, sn, sm, pm;
+  bool mode;  // n <= N/2: the slot's thread handles mode n and its mirror
+};
+
+__device__ __forceinline__ ModeSlot mode_slot(int t, int N, int lP, int lQ, int cls0, int cls1, int vs) {
+  ModeSlot s;
+  const int P = 1 << lP, Q = 1 << lQ;
+  s.v = t >> lQ;
+  s.d = t & (Q - 1);
+  s.cls = s.v ? cls1 : cls0;
+  s.n = s.cls + (s.d << lP);
+  s.mode = s.n <= (N >> 1);
+  const int cm = (P - s.cls) & (P - 1);
+  const int dm = ((N - s.n) >> lP) & (Q - 1);
+  const int vm = (cm == cls0) ? 0 : 1;
+  s.sn = s.v * vs + lx(s.d, 3);
+  s.sm = vm * vs + lx(dm, 3);
+  s.pm = mode_pos(s.mode ? s.n : 0, lP, lQ);
+  return s;
+}
+
+template <typename R, int KIND>
+__global__ void __launch_bounds__(kModeThreads)
+k_modes(const FaultDev* __restrict__ faults, const int2* __restrict__ map, int measure,
+        const void* __restrict__ gF_in, double2* __restrict__ outA, double2* __restrict__ outB,
+        long long stride_out) {
   using C = typename Prec<R>::C;
   using Rec = typename Prec<R>::Rec;
-  constexpr int kPer = ModesPerThread<MAXPTS>::value;
   extern __shared__ unsigned char smem_raw[];
-  C* buf = reinterpret_cast<C*>(smem_raw);
-  const FaultDev& fd = faults[blockIdx.x];
-  const int err = *fd.err;
-  const long long l = *fd.step;
-  if (err) return;
-  const int N = fd.N, half = fd.nmodes;
-  const int ps = pad_shift<R>(N);
-  const R* q = load_quarter_table<R, MAXPTS>(buf, fd);
-  load_input<R, MAXPTS>(buf, N, (const C*)fd.zbuf, ps);
-  __syncthreads();
-  fft_lds<C, R, MAXPTS>(buf, N, fd.log2N, q, ps);
+  __shared__ int red[2];
+  const int2 w = work_item(map);
+  const FaultDev& fd = faults[w.x];
+  const int g = w.y;
+  // ---- every descriptor field the launch uses, read once up front
+  const int N = fd.N, P = fd.P, Q = fd.Q, lP = fd.log2P, lQ = fd.log2Q;
+  const R* __restrict__ tq = (const R*)fd.twiddle;
+  const ModePtrs mp = mode_ptrs(fd);
+  const C* __restrict__ src = (const C*)(KIND == 3 ? gF_in : fd.gF);
+  C* __restrict__ gI = (C*)fd.gI;
+  Rec* __restrict__ ring = (Rec*)fd.ring;
+  int* cells = fd.cells;
+  int* done = fd.done;
+  long long* stepp = fd.step;
+  const int ngroups = fd.ngroups;
+  const double inv_s = 1.0 / fd.fwd_scale;
   const double dt = fd.dt, c1 = 1.0 - fd.r;
-  const double inv_s = 1.0 / fd.fwd_scale;
-  constexpr int G = (sizeof(R) == 4 && MAXPTS <= 8192) ? 2 : 1;
-#pragma unroll
-  for (int s0 = 0; s0 < kPer; s0 += G) {
-    double2 V0[G][2], V1[G][2], U[G][2];
-    double w1[G][2];
-    int Rn[G];
-    long long off[G];
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const int n = threadIdx.x + (s0 + k) * kSpecThreads;
-      if (s0 + k < kPer && n <= half) {
-        V0[k][0] = fd.v_hat0[n];
-        V0[k][1] = fd.gv_hat0[n];
-        V1[k][0] = fd.v_hat1[n];
-        V1[k][1] = fd.gv_hat1[n];
-        U[k][0] = fd.u_hat[n];
-        U[k][1] = fd.g_hat[n];
-        w1[k][0] = fd.coef[n].w1T;
-        w1[k][1] = fd.coef[n].w1N;
-        Rn[k] = fd.Rn[n];
-        off[k] = fd.ring_off[n];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const int n = threadIdx.x + (s0 + k) * kSpecThreads;
-      if (s0 + k < kPer && n <= half) {
-        double2 A, B;
-        unpack_mode(buf, N, n, inv_s, &A, &B, ps);
-        // rate of the interval [t, t + dt] in pass 2: (V_0 + V_1)/2
-        const double2 hv = d2(0.5 * (V0[k][0].x + V1[k][0].x), 0.5 * (V0[k][0].y + V1[k][0].y));
-        const double2 hg = d2(0.5 * (V0[k][1].x + V1[k][1].x), 0.5 * (V0[k][1].y + V1[k][1].y));
-        if (n > 0 && Rn[k] > 0) {
-          const long long slot = off[k] + (l % Rn[k]);
-          Rec rec;
-          if constexpr (sizeof(R) == 4) {
-            rec = make_float4((float)hv.x, (float)hv.y, (float)hg.x, (float)hg.y);
-          } else {
-            rec.v = hv;
-            rec.g = hg;
-          }
-          ((Rec*)fd.ring)[slot] = rec;
-        }
-        const double2 u = d2(U[k][0].x + dt * hv.x, U[k][0].y + dt * hv.y);
-        const double2 g = d2(U[k][1].x + dt * hg.x, U[k][1].y + dt * hg.y);
-        fd.hprev_v[n] = hv;
-        fd.hprev_g[n] = hg;
-        fd.u_hat[n] = u;
-        fd.g_hat[n] = g;
-        fd.P_T[n] = d2(c1 * u.x + w1[k][0] * hv.x, c1 * u.y + w1[k][0] * hv.y);
-        fd.P_N[n] = d2(c1 * g.x + w1[k][1] * hg.x, c1 * g.y + w1[k][1] * hg.y);
-        fd.v_hat0[n] = A;
-        fd.gv_hat0[n] = B;
-      }
+  int err = 0;
+  long long l = 0;
+  int e_in = 0;
+  if (KIND != 3) {
+    err = *fd.err;
+    if (KIND == 2) l = *stepp;
+    e_in = (KIND == 1) ? balance_exp(cells[0], cells[1]) : balance_exp(cells[2], cells[3]);
+  }
+
+  const int vs = vstride(Q);
+  const int nslot = 2 * Q;
+  C* bufA = reinterpret_cast<C*>(smem_raw);
+  C* bufB = bufA + 2 * vs;
+  R* q = reinterpret_cast<R*>(bufB + 2 * vs);
+  const int cls0 = g == 0 ? 0 : g;
+  const int cls1 = g == 0 ? (P >> 1) : P - g;
+
+  // ---- loads of the first slot, the transform input and the tables
+  const int t0 = threadIdx.x;
+  const ModeSlot s0 = mode_slot(t0 < nslot ? t0 : 0, N, lP, lQ, cls0, cls1, vs);
+  ModeIn in0;
+  if (KIND != 3 && t0 < nslot && s0.mode) load_mode_in<KIND>(mp, s0.pm, in0);
+  C tw0 = cmk<C>(1.0, 0.0);
+  if (KIND != 3 && t0 < nslot) tw0 = twiddle_full<C, R>(tq, s0.cls * s0.d, N);
+  if (KIND != 0) {
+    const C* __restrict__ sp = src + (KIND == 3 ? (size_t)blockIdx.y * N : 0);
+    for (int t = threadIdx.x; t < nslot; t += blockDim.x) {
+      const int v = t >> lQ, b = t & (Q - 1);
+      bufA[v * vs + lx(b, 3)] = sp[(size_t)(v ? cls1 : cls0) * Q + b];
     }
   }
-  __syncthreads();
-  if (threadIdx.x == 0) *fd.step = l + 1;
-}
-
-// P = (1-r) u_hat + w1 hprev for every mode of one fault; the inverse
-// packing scale is marked unset (the next pass measures it).
-__global__ void k_prepare(const FaultDev* __restrict__ fdp) {
-  const FaultDev& fd = *fdp;
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n == 0) *fd.inv_exp = kInvExpUnset;
-  if (n > fd.nmodes) return;
-  const double c1 = 1.0 - fd.r;
-  const double2 u = fd.u_hat[n], g = fd.g_hat[n], hv = fd.hprev_v[n], hg = fd.hprev_g[n];
-  const ModeCoef c = fd.coef[n];
-  fd.P_T[n] = d2(c1 * u.x + c.w1T * hv.x, c1 * u.y + c.w1T * hv.y);
-  fd.P_N[n] = d2(c1 * g.x + c.w1N * hg.x, c1 * g.y + c.w1N * hg.y);
-}
-
-// Forward spectra of count real signal pairs (a, kappa*a or b) -> A, B
-// (n = 0..N/2).  Block c handles signal c; inputs are FP64 and are balanced
-// by their block maxima before rounding to the transform precision.
-template <typename R, int MAXPTS>
-__global__ void __launch_bounds__(kSpecThreads)
-k_spectra(const FaultDev* __restrict__ fdp, const double* __restrict__ a,
-          const double* __restrict__ b, int b_is_kappa_a, double2* __restrict__ A,
-          double2* __restrict__ B, long long stride_in, long long stride_out) {
-  using C = typename Prec<R>::C;
-  extern __shared__ unsigned char smem_raw[];
-  C* buf = reinterpret_cast<C*>(smem_raw);
-  const FaultDev& fd = *fdp;
-  const int N = fd.N;
-  const int ps = pad_shift<R>(N);
-  const R* q = load_quarter_table<R, MAXPTS>(buf, fd);
-  const double* ac = a + stride_in * blockIdx.x;
-  const double* bc = b ? b + stride_in * blockIdx.x : nullptr;
-  double ma = 0.0, mb = 0.0;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    const double av = ac[i];
-    const double bv = b_is_kappa_a ? fd.kappa[i] * av : (bc ? bc[i] : 0.0);
-    ma = fmax(ma, fabs(av));
-    mb = fmax(mb, fabs(bv));
-  }
-  block_max2(ma, mb);
-  const double s = pow2_ratio(ma, mb);
-  for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    const double av = ac[i];
-    const double bv = b_is_kappa_a ? fd.kappa[i] * av : (bc ? bc[i] : 0.0);
-    buf[lx(i, ps)] = cmk<C>(av, bv * s);
-  }
-  __syncthreads();
-  fft_lds<C, R, MAXPTS>(buf, N, fd.log2N, q, ps);
-  double2* Ao = A + stride_out * blockIdx.x;
-  double2* Bo = B + stride_out * blockIdx.x;
-  for (int n = threadIdx.x; n <= fd.nmodes; n += blockDim.x) {
-    double2 x, y;
-    unpack_mode(buf, N, n, 1.0 / s, &x, &y, ps);
-    Ao[n] = x;
-    Bo[n] = y;
-  }
-}
-
-// Stress path: ring slot p of mode n receives the latest interval
-// l <= nint - 2 with l = p (mod R_n) (zero if none); hprev = interval nint-2.
-template <typename R>
-__global__ void k_fill_ring(const FaultDev* __restrict__ fdp, const double2* __restrict__ RV,
-                            const double2* __restrict__ RG, int nint) {
-  using Rec = typename Prec<R>::Rec;
-  const FaultDev& fd = *fdp;
-  const int n = blockIdx.x;  // mode
-  const int stride = fd.nmodes + 1;
-  const long long last = (long long)nint - 2;
+  load_sub_table<R>(q, fd, lQ);
   if (threadIdx.x == 0) {
-    fd.hprev_v[n] = last >= 0 ? RV[last * stride + n] : d2(0, 0);
-    fd.hprev_g[n] = last >= 0 ? RG[last * stride + n] : d2(0, 0);
+    red[0] = kNoExp;
+    red[1] = kNoExp;
   }
-  const int Rn = fd.Rn[n];
-  if (n == 0 || Rn == 0) return;
-  for (int p = threadIdx.x; p < Rn; p += blockDim.x) {
-    double2 v = d2(0, 0), g = d2(0, 0);
-    if (last >= 0) {
-      const long long l = last - posmod(last - p, Rn);
-      if (l >= 0) {
-        v = RV[l * stride + n];
-        g = RG[l * stride + n];
+  if (err) return;
+  __syncthreads();
+  C* X = bufA;
+  if (KIND != 0) X = fft_batch<C, R>(bufA, bufB, 2, lQ, q);
+
+  const double c = ldexp(1.0, e_in);
+  double mt = 0.0, ms = 0.0;
+  auto slot_work = [&](const ModeSlot& sl, const ModeIn& in) {
+    const int pm = sl.pm;
+    double2 A = d2(0, 0), Bv = d2(0, 0);
+    if (KIND != 0) {
+      const C zn = X[sl.sn], zm = X[sl.sm];
+      // A = (Z_n + conj Z_m)/2, B = (Z_n - conj Z_m)/(2i), B rescaled
+      A = d2(0.5 * ((double)zn.x + (double)zm.x), 0.5 * ((double)zn.y - (double)zm.y));
+      Bv = d2(0.5 * ((double)zn.y + (double)zm.y) * inv_s,
+              -0.5 * ((double)zn.x - (double)zm.x) * inv_s);
+    }
+    if (KIND == 3) {
+      outA[(size_t)blockIdx.y * stride_out + pm] = A;
+      outB[(size_t)blockIdx.y * stride_out + pm] = Bv;
+      return;
+    }
+    const ModeCoef& cf = in.cf;
+    double4 S = in.S0;
+    if (KIND != 1) {
+      if (cf.nparts == 0) S = make_double4(0.0, 0.0, 0.0, 0.0);
+      for (int j = 1; j < cf.nparts; ++j) {  // further pieces of a long window
+        const double4 b = mp.parts[cf.part0 + j - 1];
+        S.x += b.x;
+        S.y += b.y;
+        S.z += b.z;
+        S.w += b.w;
       }
     }
-    Rec rec;
-    if constexpr (sizeof(R) == 4) {
-      rec = make_float4((float)v.x, (float)v.y, (float)g.x, (float)g.y);
-    } else {
-      rec.v = v;
-      rec.g = g;
+    double2 tau, sig, BT, BN;
+    if (KIND == 0) {
+      BT = d2(c1 * in.u.x + cf.w1T * in.hv.x + S.x, c1 * in.u.y + cf.w1T * in.hv.y + S.y);
+      BN = d2(c1 * in.gg.x + cf.w1N * in.hg.x + S.z, c1 * in.gg.y + cf.w1N * in.hg.y + S.w);
+      traction_mode(cf, BT, BN, in.v0, in.gv0, &tau, &sig);
+    } else if (KIND == 1) {
+      BT = in.BT;
+      BN = in.BN;
+      mp.v1[pm] = A;
+      mp.gv1[pm] = Bv;
+      const double2 vc = d2(0.5 * (in.v0.x + A.x), 0.5 * (in.v0.y + A.y));
+      const double2 gvc = d2(0.5 * (in.gv0.x + Bv.x), 0.5 * (in.gv0.y + Bv.y));
+      traction_mode(cf, BT, BN, vc, gvc, &tau, &sig);
+    } else {  // KIND 2
+      // rate of the committed interval: (V_0 + V_1)/2
+      const double2 hv = d2(0.5 * (in.v0.x + in.v1.x), 0.5 * (in.v0.y + in.v1.y));
+      const double2 hg = d2(0.5 * (in.gv0.x + in.gv1.x), 0.5 * (in.gv0.y + in.gv1.y));
+      if (sl.n > 0 && cf.Rn > 0) {
+        Rec rec;
+        if constexpr (sizeof(R) == 4) {
+          rec = make_float4((float)hv.x, (float)hv.y, (float)hg.x, (float)hg.y);
+        } else {
+          rec.v = hv;
+          rec.g = hg;
+        }
+        ring[cf.ring_off + mod_pos(l, cf.Rn)] = rec;
+      }
+      const double2 un = d2(in.u.x + dt * hv.x, in.u.y + dt * hv.y);
+      const double2 gn = d2(in.gg.x + dt * hg.x, in.gg.y + dt * hg.y);
+      mp.u[pm] = un;
+      mp.g[pm] = gn;
+      mp.hv[pm] = hv;
+      mp.hg[pm] = hg;
+      mp.v0[pm] = A;
+      mp.gv0[pm] = Bv;
+      BT = d2(c1 * un.x + cf.w1T * hv.x + S.x, c1 * un.y + cf.w1T * hv.y + S.y);
+      BN = d2(c1 * gn.x + cf.w1N * hg.x + S.z, c1 * gn.y + cf.w1N * hg.y + S.w);
+      traction_mode(cf, BT, BN, A, Bv, &tau, &sig);
     }
-    ((Rec*)fd.ring)[fd.ring_off[n] + p] = rec;
+    mt = fmax(mt, fmax(fabs(tau.x), fabs(tau.y)));
+    ms = fmax(ms, fmax(fabs(sig.x), fabs(sig.y)));
+    if (KIND == 0 && measure) return;
+    if (KIND != 1) {
+      mp.BT[pm] = BT;
+      mp.BN[pm] = BN;
+    }
+    // conj(Z) at n and at N - n with Z = tau_hat + i c sigma_hat (the two
+    // spectra are Hermitian, so Z_{N-n} = conj(tau_hat) + i c conj(sigma_hat))
+    const double gx = c * sig.x, gy = c * sig.y;
+    X[sl.sn] = cmk<C>(tau.x - gy, -(tau.y + gx));
+    if (sl.sm != sl.sn) X[sl.sm] = cmk<C>(tau.x + gy, -(-tau.y + gx));
+  };
+  // one mode per slot (v, d) with n = cls_v + P d <= N/2; the slot of its
+  // mirror N - n is handled by the same thread
+  if (t0 < nslot && s0.mode) slot_work(s0, in0);
+  for (int t = t0 + blockDim.x; t < nslot; t += blockDim.x) {
+    const ModeSlot sl = mode_slot(t, N, lP, lQ, cls0, cls1, vs);
+    if (!sl.mode) continue;
+    ModeIn in;
+    if (KIND != 3) load_mode_in<KIND>(mp, sl.pm, in);
+    slot_work(sl, in);
+  }
+  if (KIND == 3) return;
+  __syncthreads();  // X complete; the LDS maxima cells were set before the first barrier
+  fold_maxima(mt, ms, red, (KIND == 1 || (KIND == 0 && measure)) ? cells + 2 : cells);
+  if (KIND == 0 && measure) return;
+  if (g == 0 && threadIdx.x == 0) cells[4] = e_in;
+  C* Xo = (X == bufA) ? bufB : bufA;
+  C* W = fft_batch<C, R>(X, Xo, 2, lQ, q);
+  for (int t = threadIdx.x; t < nslot; t += blockDim.x) {
+    const int v = t >> lQ, b = t & (Q - 1);
+    const int cls = v ? cls1 : cls0;
+    const C tw = (t == t0) ? tw0 : twiddle_full<C, R>(tq, cls * b, N);
+    gI[(size_t)b * P + cls] = cmul(W[v * vs + lx(b, 3)], tw);
+  }
+  if (KIND == 2) {
+    // the last workgroup of the fault to finish advances the step counter
+    // (every workgroup has read it above, before its own increment)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int prev = atomicAdd(done, 1);
+      if (prev == ngroups - 1) {
+        atomicExch(done, 0);
+        *stepp = l + 1;
+      }
+    }
   }
 }
 
-// rates[l*N + i] = (hist[(l+1)*N + i] - hist[l*N + i]) / dt
-__global__ void k_rates(const double* __restrict__ hist, double* __restrict__ rates, long long count,
-                        long long N, double inv_dt) {
-  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < count;
-       k += (long long)gridDim.x * blockDim.x)
-    rates[k] = (hist[k + N] - hist[k]) * inv_dt;
-}
+// ---------------------------------------------------------------------------
+// Momentum balance per element (section 3.3, with radiation damping):
+//   tau - eta V = sigma (f0 + a ln(V/V_ref) + b ln(theta V_ref/Dc)),
+// eta = mu/(2 c_s), solved for x = ln V.  With K = tau - sigma (psi - a ln V_ref)
+// the residual g(x) = K - eta e^x - sigma a x is strictly decreasing, so the
+// root is unique; [lo, hi] brackets it:
+//   hi = x_rs (where the friction term alone balances tau), lowered to
+//        max(ln(tau/eta), x_0) when tau > 0 (x_0: zero friction coefficient),
+//   lo = x_rs - eta e^hi / (sigma a).
+// A single-precision Newton phase (hardware exp/log, bisection whenever a
+// step leaves the bracket) brings x near the root; FP64 Newton steps then
+// finish: a Newton step shorter than 1e-9 (|x| >= 1) ends the iteration,
+// since the error left after it is below the FP64 resolution of x
+// (quadratic convergence, curvature factor <= 1/2).  The single-precision
+// bounds carry margins that keep the bracket valid.
+// ---------------------------------------------------------------------------
+// Constants of the friction update of one fault, read once per launch.
+struct FrictionConst {
+  double lnVref, eta, f0, Vref_Dc, Dc, dt, t_new_load, V_pl, s;
+  int theta_mode;
+};
 
-// ---------------------------------------------------------------------------
-// Momentum balance per element (section 3.3 step (3), with radiation damping)
-// ---------------------------------------------------------------------------
 __device__ __forceinline__ int solve_rate(double tau, double sig, double theta, double a, double b,
-                                          const FaultDev& fd, double Vguess, double* Vout) {
-  const double lnVref = fd.ln_V_ref;
-  const double psi = fd.f0 + b * log(theta * fd.V_ref / fd.Dc);
+                                          const FrictionConst& k, double Vguess, double* Vout) {
+  const double lnVref = k.lnVref, eta = k.eta;
+  const double psi = k.f0 + b * log(theta * k.Vref_Dc);
+  const double sa = sig * a;
   const double x_rs = lnVref + (tau / sig - psi) / a;
   const double x_0 = lnVref - psi / a;
   double hi = x_rs;
-  if (tau > 0.0) hi = fmin(hi, fmax(log(tau / fd.eta_rad), x_0));
+  if (tau > 0.0) {
+    const float lt = __logf((float)(tau / eta));
+    const double ub = (double)lt + 1e-5 * fmax(1.0, fabs((double)lt));
+    hi = fmin(hi, fmax(ub, x_0));
+  }
   hi = fmin(hi, 700.0);
-  double lo = x_rs - fd.eta_rad * exp(hi) / (sig * a);
+  const double ehi = hi < 80.0 ? (double)__expf((float)hi) * (1.0 + 1e-5) : exp(hi);
+  double lo = x_rs - eta * ehi / sa;
   if (!(lo <= hi)) return -1;
-  double x = fmin(fmax(log(Vguess), lo), hi);
+  const double K = tau - sig * (psi - a * lnVref);  // g(x) = K - eta e^x - sa x
+
+  // single-precision phase
+  double x;
+  {
+    const float Kf = (float)K, ef = (float)eta, saf = (float)sa;
+    float flo = (float)lo, fhi = (float)hi;
+    float xf = fminf(fmaxf(__logf((float)Vguess), flo), fhi);
+    if (!(xf == xf)) xf = 0.5f * (flo + fhi);
+    for (int it = 0; it < 40 && xf < 80.f; ++it) {
+      const float ex = __expf(xf);
+      const float g = Kf - ef * ex - saf * xf;
+      const float gp = -ef * ex - saf;
+      if (g > 0.f) flo = xf;
+      else fhi = xf;
+      float xn = xf - __fdividef(g, gp);
+      if (!(xn > flo && xn < fhi)) xn = 0.5f * (flo + fhi);
+      const float st = fabsf(xn - xf);
+      xf = xn;
+      if (st <= 1e-6f * fmaxf(1.f, fabsf(xf))) break;
+    }
+    x = fmin(fmax((double)xf, lo), hi);
+  }
+
+  // double-precision phase
   for (int it = 0; it < 100; ++it) {
     const double ex = exp(x);
-    const double g = tau - fd.eta_rad * ex - sig * (psi + a * (x - lnVref));
+    const double g = K - eta * ex - sa * x;
     if (g == 0.0) {
       *Vout = ex;
       return 0;
     }
-    const double gp = -fd.eta_rad * ex - sig * a;
+    const double gp = -eta * ex - sa;
     if (g > 0.0) lo = x;
     else hi = x;
-    double xn = x - g / gp;
+    const double d = g / gp;
+    const double scale = fmax(1.0, fabs(x));
+    double xn = x - d;
+    // a short Newton step is accepted even where it touches the bracket: the
+    // root is then within |d| (times a factor near 1) of x
+    if (fabs(d) <= 1e-9 * scale) {
+      *Vout = exp(xn);
+      return 0;
+    }
     if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-    if (fabs(xn - x) <= 4e-16 * fmax(1.0, fabs(x))) {
+    if (fabs(xn - x) <= 4e-16 * scale) {
       *Vout = exp(xn);
       return 0;
     }
@@ -958,108 +897,323 @@ __device__ __forceinline__ void report(const FaultDev& fd, int code, int i) {
   atomicMin(fd.err_index, i);
 }
 
-template <typename R>
-__global__ void __launch_bounds__(kNewtonThreads)
-k_newton(const FaultDev* __restrict__ faults, const int2* __restrict__ map, int pass) {
-  using C = typename Prec<R>::C;
-  const int2 m = map[blockIdx.x];
-  const FaultDev& fd = faults[m.x];
-  const int i = m.y + threadIdx.x;
-  const int ii = min(i, fd.N - 1);
-  // every load is issued before the first branch
-  const int err = *fd.err;
-  const long long l = *fd.step;
-  const int cur = (int)(l & 1), nxt = cur ^ 1;
-  const double V0 = fd.V[cur][ii], thd0 = fd.thd[cur][ii], th0 = fd.theta[cur][ii];
-  const double slip0 = fd.slip[cur][ii];
-  const double V1 = fd.V1[ii], thd1 = fd.thd1[ii];
-  const double tl = fd.tau_load[ii], sl = fd.sigma_load[ii];
-  const double te = fd.tau_el[nxt][ii], se = fd.sigma_el[nxt][ii];
-  const double a = fd.a[ii], b = fd.b[ii], kap = fd.kappa[ii];
-  if (i >= fd.N || err) return;
-  const double dt = fd.dt;
-  double Vc, thdc;
-  if (pass == 1) {
+// Per-element inputs of a pass (loaded at the top of the element stage).
+// The committed state is double-buffered by step parity; both buffers are
+// loaded so that no address waits for the step counter.
+struct ElemIn {
+  double V[2], thd[2], th[2], slip[2];
+  double V1, thd1;  // pass-1 solution (pass 2 only)
+  double tl, sl, a, b, kap;
+};
+
+template <int PASS>
+__device__ __forceinline__ void load_elem_in(const FaultDev& fd, int pe, ElemIn& e) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    e.V[k] = fd.V[k][pe];
+    e.thd[k] = fd.thd[k][pe];
+    e.th[k] = fd.theta[k][pe];
+    e.slip[k] = PASS == 2 ? fd.slip[k][pe] : 0.0;
+  }
+  e.V1 = PASS == 2 ? fd.V1[pe] : 0.0;
+  e.thd1 = PASS == 2 ? fd.thd1[pe] : 0.0;
+  e.tl = fd.tau_load[pe];
+  e.sl = fd.sigma_load[pe];
+  e.a = fd.a[pe];
+  e.b = fd.b[pe];
+  e.kap = fd.kappa[pe];
+}
+
+// Output pointers of a pass (read once per launch).
+struct ElemOut {
+  double *V1, *thd1;                     // pass 1
+  double *slip, *V, *theta, *thd;        // pass 2: buffer of the next state
+  double *tau_el, *sigma_el;
+};
+
+// Predictor, momentum balance and aging law of one element (position pe,
+// natural index i) in pass PASS; returns V_p - V_pl (0 on failure).
+template <int PASS>
+__device__ __forceinline__ double friction_element(const FaultDev& fd, const FrictionConst& k,
+                                                   const ElemOut& o, int cur, int pe, int i,
+                                                   const ElemIn& in, double te, double se) {
+  // committed state of this step; the other buffer holds the step before
+  // (selects, not indexing: a run-time index would put the arrays in scratch)
+  const double V0 = cur ? in.V[1] : in.V[0], Vb = cur ? in.V[0] : in.V[1];
+  const double thd0 = cur ? in.thd[1] : in.thd[0], th0 = cur ? in.th[1] : in.th[0];
+  const double dt = k.dt;
+  double Vc, thdc, guess;
+  if (PASS == 1) {
     Vc = V0;
     thdc = thd0;
+    // guess: geometric extrapolation from the last two committed rates
+    const double r = V0 / Vb;
+    guess = (r > 1e-3 && r < 1e3) ? V0 * r : V0;
   } else {
-    Vc = 0.5 * (V0 + V1);
-    thdc = 0.5 * (thd0 + thd1);
+    Vc = 0.5 * (V0 + in.V1);
+    thdc = 0.5 * (thd0 + in.thd1);
+    guess = in.V1;
   }
   double theta_p;
-  if (fd.theta_mode == SBIEM_THETA_EXP) {
-    const double ss = fd.Dc / Vc;
-    theta_p = ss + (th0 - ss) * exp(-Vc * dt / fd.Dc);
+  if (k.theta_mode == SBIEM_THETA_EXP) {
+    const double ss = k.Dc / Vc;
+    theta_p = ss + (th0 - ss) * exp(-Vc * dt / k.Dc);
   } else {
     theta_p = th0 + dt * thdc;
   }
-  const double t_new = fd.t0 + (double)(l + 1) * dt;
-  const double tau = tl + fd.tau_rate * t_new + te;
-  const double sig = sl + se;
+  const double tau = in.tl + k.t_new_load + te;
+  const double sig = in.sl + se;
   double Vp = Vc;
   if (!(sig > 0.0)) {
     report(fd, SBIEM_EOPEN, i);
-    return;
+    return 0.0;
   }
   if (!(theta_p > 0.0) || !isfinite(theta_p)) {
     report(fd, SBIEM_ESTATE, i);
-    return;
+    return 0.0;
   }
-  if (solve_rate(tau, sig, theta_p, a, b, fd, Vc, &Vp) != 0 || !isfinite(Vp)) {
+  if (solve_rate(tau, sig, theta_p, in.a, in.b, k, guess, &Vp) != 0 || !isfinite(Vp)) {
     report(fd, SBIEM_ENEWTON, i);
-    return;
+    return 0.0;
   }
-  const double thdp = 1.0 - theta_p * Vp / fd.Dc;
-  if (pass == 1) {
-    fd.V1[i] = Vp;
-    fd.thd1[i] = thdp;
+  const double thdp = 1.0 - theta_p * Vp / k.Dc;
+  if (PASS == 1) {
+    o.V1[pe] = Vp;
+    o.thd1[pe] = thdp;
   } else {
-    fd.slip[nxt][i] = slip0 + dt * Vc;
-    fd.V[nxt][i] = Vp;
-    fd.theta[nxt][i] = theta_p;
-    fd.thd[nxt][i] = thdp;
+    o.slip[pe] = (cur ? in.slip[1] : in.slip[0]) + dt * Vc;
+    o.V[pe] = Vp;
+    o.theta[pe] = theta_p;
+    o.thd[pe] = thdp;
   }
-  const double dv = Vp - fd.V_pl;
-  ((C*)fd.zbuf)[i] = cmk<C>(dv, fd.fwd_scale * kap * dv);
+  return Vp - k.V_pl;
+}
+
+// ---------------------------------------------------------------------------
+// Element stage.  A workgroup owns classes b0 .. b0 + ncls - 1 (ncls P
+// elements, contiguous at positions b P + a).  KIND 0: second half of the
+// inverse transform -> tau^el, sigma^el; KIND 1/2: the same, then the pass's
+// momentum balance per element and the first half of the forward transform
+// of (V_p - V_pl, s kappa (V_p - V_pl)) into gF; KIND 3: the first half of
+// the forward transform of (a, s kappa a) for a real signal a in natural
+// order (blockIdx.y selects the signal) into gF_out.
+// LDS: buffers A and B (ncls P-point vectors each), then the P-point table.
+// ---------------------------------------------------------------------------
+template <typename R, int KIND>
+__global__ void __launch_bounds__(kElemThreads)
+k_elems(const FaultDev* __restrict__ faults, const int2* __restrict__ map,
+        const double* __restrict__ in, void* __restrict__ gF_out) {
+  using C = typename Prec<R>::C;
+  extern __shared__ unsigned char smem_raw[];
+  const int2 w = map ? map[blockIdx.x] : make_int2(0, (int)blockIdx.x * faults[0].ncls);
+  const FaultDev& fd = faults[w.x];
+  const int b0 = w.y;
+  // ---- every descriptor field the launch uses, read once up front
+  const int N = fd.N, P = fd.P, Q = fd.Q, lP = fd.log2P, lQ = fd.log2Q;
+  const int nv = fd.ncls;
+  const R* __restrict__ tq = (const R*)fd.twiddle;
+  const double s = fd.fwd_scale;
+  const double* __restrict__ kap = fd.kappa;
+  C* __restrict__ gF = (C*)(KIND == 3 ? gF_out : fd.gF);
+  const C* __restrict__ gIrow = (const C*)fd.gI + (size_t)b0 * P;
+  int err = 0, e_used = 0;
+  long long l = 0;
+  if (KIND != 3) {
+    err = *fd.err;
+    l = *fd.step;
+    e_used = fd.cells[4];
+  }
+  FrictionConst k;
+  ElemOut o;
+  const int cur = (int)(l & 1);
+  if (KIND == 1 || KIND == 2) {
+    k.lnVref = fd.ln_V_ref;
+    k.eta = fd.eta_rad;
+    k.f0 = fd.f0;
+    k.Vref_Dc = fd.V_ref / fd.Dc;
+    k.Dc = fd.Dc;
+    k.dt = fd.dt;
+    k.t_new_load = fd.tau_rate * (fd.t0 + (double)(l + 1) * fd.dt);
+    k.V_pl = fd.V_pl;
+    k.s = s;
+    k.theta_mode = fd.theta_mode;
+    o.V1 = fd.V1;
+    o.thd1 = fd.thd1;
+    o.slip = cur ? fd.slip[0] : fd.slip[1];
+    o.V = cur ? fd.V[0] : fd.V[1];
+    o.theta = cur ? fd.theta[0] : fd.theta[1];
+    o.thd = cur ? fd.thd[0] : fd.thd[1];
+  }
+  const int oslot = (int)((l + 1) & 1);
+  o.tau_el = oslot ? fd.tau_el[1] : fd.tau_el[0];
+  o.sigma_el = oslot ? fd.sigma_el[1] : fd.sigma_el[0];
+
+  const int E = nv << lP;
+  const int vs = vstride(P);
+  C* bufA = reinterpret_cast<C*>(smem_raw);
+  C* bufB = bufA + nv * vs;
+  R* q = reinterpret_cast<R*>(bufB + nv * vs);
+
+  // ---- loads of the first element, the transform input and the tables
+  const int t0 = threadIdx.x;
+  const int pe0 = b0 * P + (t0 < E ? t0 : 0);
+  ElemIn in0;
+  if ((KIND == 1 || KIND == 2) && t0 < E) load_elem_in<KIND>(fd, pe0, in0);
+  C tw0 = cmk<C>(1.0, 0.0);
+  if (KIND != 0 && t0 < E) tw0 = twiddle_full<C, R>(tq, (b0 + (t0 >> lP)) * (t0 & (P - 1)), N);
+  if (KIND != 3) {
+    for (int t = threadIdx.x; t < E; t += blockDim.x) {
+      const int v = t >> lP, cc = t & (P - 1);
+      bufA[v * vs + lx(cc, 3)] = gIrow[t];
+    }
+  } else {
+    const double* __restrict__ sig = in + (size_t)blockIdx.y * N;
+    for (int t = threadIdx.x; t < E; t += blockDim.x) {
+      const int v = t >> lP, a = t & (P - 1);
+      const int pe = b0 * P + t;
+      const int i = (b0 + v) + (a << lQ);
+      const double x = sig[i];
+      bufA[v * vs + lx(a, 3)] = cmk<C>(x, s * kap[pe] * x);
+    }
+  }
+  load_sub_table<R>(q, fd, lP);
+  if (err) return;
+  // the balance cells of the pass just read are no longer needed
+  if (b0 == 0 && threadIdx.x == 0) {
+    if (KIND == 1) {
+      fd.cells[2] = kNoExp;
+      fd.cells[3] = kNoExp;
+    } else if (KIND == 2) {
+      fd.cells[0] = kNoExp;
+      fd.cells[1] = kNoExp;
+    }
+  }
+  __syncthreads();
+  C* X = bufA;
+  if (KIND != 3) {
+    X = fft_batch<C, R>(bufA, bufB, nv, lP, q);
+    const double inv = 1.0 / N, invc = inv * ldexp(1.0, -e_used);
+    auto element = [&](int t, const ElemIn& e) {
+      const int v = t >> lP, a = t & (P - 1);
+      const int pe = b0 * P + t;
+      const int i = (b0 + v) + (a << lQ);
+      const int sx = v * vs + lx(a, 3);
+      const C z = X[sx];
+      const double te = (double)z.x * inv, se = -(double)z.y * invc;
+      o.tau_el[pe] = te;
+      o.sigma_el[pe] = se;
+      if (KIND == 1 || KIND == 2) {
+        const double dv = friction_element<KIND>(fd, k, o, cur, pe, i, e, te, se);
+        X[sx] = cmk<C>(dv, s * e.kap * dv);
+      }
+    };
+    if (t0 < E) element(t0, in0);
+    for (int t = t0 + blockDim.x; t < E; t += blockDim.x) {
+      ElemIn e;
+      if (KIND == 1 || KIND == 2) load_elem_in<KIND>(fd, b0 * P + t, e);
+      element(t, e);
+    }
+    if (KIND == 0) return;
+    __syncthreads();
+  }
+  C* Xo = (X == bufA) ? bufB : bufA;
+  C* Y = fft_batch<C, R>(X, Xo, nv, lP, q);
+  if (KIND == 3) gF += (size_t)blockIdx.y * N;
+  for (int t = threadIdx.x; t < E; t += blockDim.x) {
+    const int v = t >> lP, cc = t & (P - 1);
+    const int b = b0 + v;
+    const C tw = (t == t0) ? tw0 : twiddle_full<C, R>(tq, b * cc, N);
+    gF[(size_t)cc * Q + b] = cmul(Y[v * vs + lx(cc, 3)], tw);
+  }
+}
+
+// Stress path: ring slot p of mode n receives the latest interval
+// l <= nint - 2 with l = p (mod R_n) (zero if none); hprev = interval nint-2.
+// RV, RG hold the interval spectra at mode_pos, stride N/2 + 1.
+template <typename R>
+__global__ void k_fill_ring(const FaultDev* __restrict__ fdp, const double2* __restrict__ RV,
+                            const double2* __restrict__ RG, int nint) {
+  using Rec = typename Prec<R>::Rec;
+  const FaultDev& fd = *fdp;
+  const int n = blockIdx.x;  // mode
+  const int pm = mode_pos(n, fd.log2P, fd.log2Q);
+  const int stride = fd.nmodes + 1;
+  const long long last = (long long)nint - 2;
+  if (threadIdx.x == 0) {
+    fd.hprev_v[pm] = last >= 0 ? RV[last * stride + pm] : d2(0, 0);
+    fd.hprev_g[pm] = last >= 0 ? RG[last * stride + pm] : d2(0, 0);
+  }
+  const ModeCoef cf = fd.coef[pm];
+  const int Rn = cf.Rn;
+  if (n == 0 || Rn == 0) return;
+  for (int p = threadIdx.x; p < Rn; p += blockDim.x) {
+    double2 v = d2(0, 0), g = d2(0, 0);
+    if (last >= 0) {
+      const long long ll = last - posmod(last - p, Rn);
+      if (ll >= 0) {
+        v = RV[ll * stride + pm];
+        g = RG[ll * stride + pm];
+      }
+    }
+    Rec rec;
+    if constexpr (sizeof(R) == 4) {
+      rec = make_float4((float)v.x, (float)v.y, (float)g.x, (float)g.y);
+    } else {
+      rec.v = v;
+      rec.g = g;
+    }
+    ((Rec*)fd.ring)[cf.ring_off + p] = rec;
+  }
+}
+
+// rates[l*N + i] = (hist[(l+1)*N + i] - hist[l*N + i]) / dt
+__global__ void k_rates(const double* __restrict__ hist, double* __restrict__ rates, long long count,
+                        long long N, double inv_dt) {
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < count;
+       k += (long long)gridDim.x * blockDim.x)
+    rates[k] = (hist[k + N] - hist[k]) * inv_dt;
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static size_t spec_lds(int precision, int maxN) {
-  if (precision == SBIEM_FP32CONV) return spec_lds_bytes<float>(maxN, pad_shift<float>(maxN));
-  return spec_lds_bytes<double>(maxN, pad_shift<double>(maxN));
+void split_sizes(int log2N, int* log2P, int* log2Q, int* ncls) {
+  const int lp = log2N / 2;
+  *log2P = lp;
+  *log2Q = log2N - lp;
+  const int P = 1 << lp, Q = 1 << (log2N - lp);
+  int n = kElemThreads / P;
+  if (n < 1) n = 1;
+  if (n > Q) n = Q;
+  *ncls = n;
 }
 
-// The spectral kernels are instantiated per largest transform size so that
-// each thread's per-mode arrays stay in registers.
-template <typename R, int M>
-struct SpecTag {
-  using type = R;
-  static constexpr int pts = M;
-};
-
-template <typename F>
-static hipError_t with_spec_size(int precision, int maxN, F&& f) {
-  if (precision == SBIEM_FP32CONV) {
-    if (maxN <= 2048) return f(SpecTag<float, 2048>{});
-    if (maxN <= 8192) return f(SpecTag<float, 8192>{});
-    return f(SpecTag<float, 16384>{});
-  }
-  if (maxN <= 2048) return f(SpecTag<double, 2048>{});
-  return f(SpecTag<double, 8192>{});
+size_t mode_lds_bytes(int precision, int log2Q) {
+  const size_t c = precision == SBIEM_FP32CONV ? sizeof(float2) : sizeof(double2);
+  const size_t r = precision == SBIEM_FP32CONV ? sizeof(float) : sizeof(double);
+  const int Q = 1 << log2Q;
+  return 4 * (size_t)vstride(Q) * c + (size_t)(Q / 4 + 1) * r;
 }
 
-template <typename T>
-static hipError_t set_spec_attributes(T) {
-  using R = typename T::type;
-  constexpr int M = T::pts;
-  const int bytes = kMaxDynLds;
+size_t elem_lds_bytes(int precision, int log2P, int ncls) {
+  const size_t c = precision == SBIEM_FP32CONV ? sizeof(float2) : sizeof(double2);
+  const size_t r = precision == SBIEM_FP32CONV ? sizeof(float) : sizeof(double);
+  const int P = 1 << log2P;
+  return 2 * (size_t)ncls * vstride(P) * c + (size_t)(P / 4 + 1) * r;
+}
+
+template <typename R>
+static hipError_t set_attributes() {
   const hipFuncAttribute a = hipFuncAttributeMaxDynamicSharedMemorySize;
-  hipError_t e = hipFuncSetAttribute((const void*)k_pass1<R, M>, a, bytes);
-  if (!e) e = hipFuncSetAttribute((const void*)k_pass2<R, M>, a, bytes);
-  if (!e) e = hipFuncSetAttribute((const void*)k_commit<R, M>, a, bytes);
-  if (!e) e = hipFuncSetAttribute((const void*)k_spectra<R, M>, a, bytes);
+  const int bytes = kMaxDynLds;
+  hipError_t e = hipFuncSetAttribute((const void*)k_modes<R, 0>, a, bytes);
+  if (!e) e = hipFuncSetAttribute((const void*)k_modes<R, 1>, a, bytes);
+  if (!e) e = hipFuncSetAttribute((const void*)k_modes<R, 2>, a, bytes);
+  if (!e) e = hipFuncSetAttribute((const void*)k_modes<R, 3>, a, bytes);
+  if (!e) e = hipFuncSetAttribute((const void*)k_elems<R, 0>, a, bytes);
+  if (!e) e = hipFuncSetAttribute((const void*)k_elems<R, 1>, a, bytes);
+  if (!e) e = hipFuncSetAttribute((const void*)k_elems<R, 2>, a, bytes);
+  if (!e) e = hipFuncSetAttribute((const void*)k_elems<R, 3>, a, bytes);
   return e;
 }
 
@@ -1067,10 +1221,7 @@ hipError_t setup_kernel_attributes(int precision) {
   static bool done[2] = {false, false};
   const int idx = precision == SBIEM_FP32CONV ? 1 : 0;
   if (done[idx]) return hipSuccess;
-  hipError_t e = hipSuccess;
-  for (int maxN : {2048, 8192, 16384}) {
-    if (!e) e = with_spec_size(precision, maxN, [](auto t) { return set_spec_attributes(t); });
-  }
+  hipError_t e = idx ? set_attributes<float>() : set_attributes<double>();
   if (!e && idx)
     e = hipFuncSetAttribute((const void*)k_conv32, hipFuncAttributeMaxDynamicSharedMemorySize,
                             kMaxDynLds);
@@ -1089,84 +1240,77 @@ int conv_grid_size(int precision, int ntasks, int table_len) {
   return need < 1 ? 1 : need;
 }
 
-hipError_t launch_conv(const Exec& ex, hipStream_t s) {
+hipError_t launch_conv(const Exec& ex, int ahead, hipStream_t s) {
   if (ex.ntasks == 0) return hipSuccess;
   if (ex.precision == SBIEM_FP32CONV) {
     const size_t lds = (size_t)ex.table_len * sizeof(float4);
     hipLaunchKernelGGL(k_conv32, dim3(ex.conv_grid), dim3(kConvThreads), lds, s, ex.d_faults,
-                       ex.d_tiles, ex.d_tasks, ex.ntasks, ex.table, ex.table_len);
+                       ex.d_tiles, ex.d_tasks, ex.ntasks, ex.table, ex.table_len, ahead);
   } else {
     hipLaunchKernelGGL(k_conv64, dim3(ex.conv_grid), dim3(kConvThreads), 0, s, ex.d_faults,
-                       ex.d_tiles, ex.d_tasks, ex.ntasks);
+                       ex.d_tiles, ex.d_tasks, ex.ntasks, ahead);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_pass1(const Exec& ex, hipStream_t s) {
-  const size_t lds = spec_lds(ex.precision, ex.max_N);
-  return with_spec_size(ex.precision, ex.max_N, [&](auto t) {
-    using T = decltype(t);
-    k_pass1<typename T::type, T::pts><<<dim3(ex.nfaults), dim3(kSpecThreads), lds, s>>>(ex.d_faults);
-    return hipGetLastError();
-  });
+template <typename R>
+static void modes_kind(const Exec& ex, int kind, int measure, hipStream_t s) {
+  const dim3 grid(ex.mode_blocks), block(kModeThreads);
+  const size_t lds = ex.mode_lds;
+  const int2* map = ex.nfaults == 1 ? nullptr : ex.d_mode_map;  // one fault: group = block
+  switch (kind) {
+    case 0:
+      k_modes<R, 0><<<grid, block, lds, s>>>(ex.d_faults, map, measure, nullptr, nullptr,
+                                              nullptr, 0);
+      break;
+    case 1:
+      k_modes<R, 1><<<grid, block, lds, s>>>(ex.d_faults, map, 0, nullptr, nullptr,
+                                              nullptr, 0);
+      break;
+    default:
+      k_modes<R, 2><<<grid, block, lds, s>>>(ex.d_faults, map, 0, nullptr, nullptr,
+                                              nullptr, 0);
+      break;
+  }
 }
 
-hipError_t launch_newton(const Exec& ex, int pass, hipStream_t s) {
-  if (ex.precision == SBIEM_FP32CONV)
-    hipLaunchKernelGGL(k_newton<float>, dim3(ex.newton_blocks), dim3(kNewtonThreads), 0, s,
-                       ex.d_faults, ex.d_newton_map, pass);
-  else
-    hipLaunchKernelGGL(k_newton<double>, dim3(ex.newton_blocks), dim3(kNewtonThreads), 0, s,
-                       ex.d_faults, ex.d_newton_map, pass);
+hipError_t launch_modes(const Exec& ex, int kind, int measure, hipStream_t s) {
+  if (ex.precision == SBIEM_FP32CONV) modes_kind<float>(ex, kind, measure, s);
+  else modes_kind<double>(ex, kind, measure, s);
   return hipGetLastError();
 }
 
-hipError_t launch_pass2(const Exec& ex, hipStream_t s) {
-  const size_t lds = spec_lds(ex.precision, ex.max_N);
-  return with_spec_size(ex.precision, ex.max_N, [&](auto t) {
-    using T = decltype(t);
-    k_pass2<typename T::type, T::pts><<<dim3(ex.nfaults), dim3(kSpecThreads), lds, s>>>(ex.d_faults);
-    return hipGetLastError();
-  });
+template <typename R>
+static void elems_kind(const Exec& ex, int kind, hipStream_t s) {
+  const dim3 grid(ex.elem_blocks), block(kElemThreads);
+  const size_t lds = ex.elem_lds;
+  const int2* map = ex.nfaults == 1 ? nullptr : ex.d_elem_map;
+  switch (kind) {
+    case 0: k_elems<R, 0><<<grid, block, lds, s>>>(ex.d_faults, map, nullptr, nullptr); break;
+    case 1: k_elems<R, 1><<<grid, block, lds, s>>>(ex.d_faults, map, nullptr, nullptr); break;
+    default: k_elems<R, 2><<<grid, block, lds, s>>>(ex.d_faults, map, nullptr, nullptr); break;
+  }
 }
 
-hipError_t launch_commit(const Exec& ex, hipStream_t s) {
-  const size_t lds = spec_lds(ex.precision, ex.max_N);
-  return with_spec_size(ex.precision, ex.max_N, [&](auto t) {
-    using T = decltype(t);
-    k_commit<typename T::type, T::pts><<<dim3(ex.nfaults), dim3(kSpecThreads), lds, s>>>(ex.d_faults);
-    return hipGetLastError();
-  });
+hipError_t launch_elems(const Exec& ex, int kind, hipStream_t s) {
+  if (ex.precision == SBIEM_FP32CONV) elems_kind<float>(ex, kind, s);
+  else elems_kind<double>(ex, kind, s);
+  return hipGetLastError();
 }
 
-hipError_t launch_step(const Exec& ex, hipStream_t s, bool profile, hipEvent_t e0, hipEvent_t e1) {
-  hipError_t e;
-  if (profile && (e = hipEventRecord(e0, s))) return e;
-  if ((e = launch_conv(ex, s))) return e;
-  if (profile && (e = hipEventRecord(e1, s))) return e;
-  if ((e = launch_pass1(ex, s))) return e;
-  if ((e = launch_newton(ex, 1, s))) return e;
-  if ((e = launch_pass2(ex, s))) return e;
-  if ((e = launch_newton(ex, 2, s))) return e;
-  return launch_commit(ex, s);
-}
-
-hipError_t launch_spectra(const FaultDev* d_fault, int precision, int max_N, const double* a,
-                          const double* b, double scale_b_by_kappa, double2* A, double2* B,
-                          int count, long long stride_in, long long stride_out, hipStream_t s) {
-  const size_t lds = spec_lds(precision, max_N);
-  const int kap = scale_b_by_kappa != 0.0 ? 1 : 0;
-  return with_spec_size(precision, max_N, [&](auto t) {
-    using T = decltype(t);
-    k_spectra<typename T::type, T::pts><<<dim3(count), dim3(kSpecThreads), lds, s>>>(
-        d_fault, a, b, kap, A, B, stride_in, stride_out);
-    return hipGetLastError();
-  });
-}
-
-hipError_t launch_prepare(const FaultDev* d_fault, int nmodes, hipStream_t s) {
-  const int blocks = (nmodes + 1 + 255) / 256;
-  hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, s, d_fault);
+hipError_t launch_forward(const FaultDev* d_fault, const FaultDev& h, int precision,
+                          const double* a, double2* A, double2* B, int count, long long stride_out,
+                          void* gF, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const dim3 eg((unsigned)(h.Q / h.ncls), (unsigned)count), mg((unsigned)h.ngroups, (unsigned)count);
+  const size_t el = elem_lds_bytes(precision, h.log2P, h.ncls), ml = mode_lds_bytes(precision, h.log2Q);
+  if (precision == SBIEM_FP32CONV) {
+    k_elems<float, 3><<<eg, dim3(kElemThreads), el, s>>>(d_fault, nullptr, a, gF);
+    k_modes<float, 3><<<mg, dim3(kModeThreads), ml, s>>>(d_fault, nullptr, 0, gF, A, B, stride_out);
+  } else {
+    k_elems<double, 3><<<eg, dim3(kElemThreads), el, s>>>(d_fault, nullptr, a, gF);
+    k_modes<double, 3><<<mg, dim3(kModeThreads), ml, s>>>(d_fault, nullptr, 0, gF, A, B, stride_out);
+  }
   return hipGetLastError();
 }
 

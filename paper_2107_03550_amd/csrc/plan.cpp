@@ -109,6 +109,27 @@ std::vector<double> curvature_host(const double* h, int64_t N, double L) {
   return out;
 }
 
+}  // namespace
+
+// Natural element order (host) -> class-major device order and back.
+std::vector<double> to_elem_order(const sbiem_plan* p, const double* x) {
+  const int64_t N = p->N;
+  std::vector<double> y(N);
+  for (int64_t i = 0; i < N; ++i) y[elem_pos((int)i, p->log2P, p->log2Q)] = x[i];
+  return y;
+}
+
+hipError_t download_elems(const sbiem_plan* p, const double* dev, double* host) {
+  const int64_t N = p->N;
+  std::vector<double> y(N);
+  hipError_t e = hipMemcpy(y.data(), dev, (size_t)N * sizeof(double), hipMemcpyDeviceToHost);
+  if (e) return e;
+  for (int64_t i = 0; i < N; ++i) host[i] = y[elem_pos((int)i, p->log2P, p->log2Q)];
+  return hipSuccess;
+}
+
+namespace {
+
 template <typename T>
 T* upload(sbiem::DevArena& mem, const std::vector<T>& v, hipStream_t s, hipError_t* err) {
   T* d = (T*)mem.get(v.size() * sizeof(T));
@@ -163,8 +184,8 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
                               (long double)dt / (long double)p->L / (long double)kTableStep;
   d->part0.assign(half + 1, 0);
   d->nparts.assign(half + 1, 0);
-  // conv partials: the first piece of mode n is parts[n]; further pieces of a
-  // mode longer than one task follow from index N/2 + 1 on
+  // conv partials: the first piece of mode n is parts[mode_pos(n)]; further
+  // pieces of a mode longer than one task follow from index N/2 + 1 on
   int extra = half + 1;
   int cur_tiles = 0;
   auto open_task = [&]() {
@@ -176,7 +197,7 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
     if (count == 0) continue;
     if (d->tasks.empty() || cur_tiles + std::min(count, kTaskTiles) > kTaskTiles) open_task();
     const int extra0 = extra;
-    int part = n;
+    int part = mode_pos(n, p->log2P, p->log2Q);
     for (int k = 0; k < count; ++k) {
       if (cur_tiles == kTaskTiles) {  // a long mode continues in a new task
         open_task();
@@ -204,14 +225,13 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
   const long double cs = p->cs, cp = p->cp;
   const long double theta_unit = kPiL * cs * (long double)dt / (long double)p->L;  // c_s k_1 dt / 2
   std::vector<ModeCoef> coef(half + 1);
-  std::vector<double> th(half + 1);
   const double c1 = 1.0 - p->r;
   for (int n = 0; n <= half; ++n) {
     const double kabs = 2.0 * M_PI * (double)n / p->L;
     const long double theta = theta_unit * n;  // c_s |k_n| dt / 2
     long double CT, CN;
     kernel_values(theta, cs, cp, &CT, &CN, nullptr, nullptr);
-    ModeCoef& c = coef[n];
+    ModeCoef& c = coef[mode_pos(n, p->log2P, p->log2Q)];
     c.mk = -p->mu * kabs;
     c.ms = (n == 0 || 2 * n == N) ? 0.0 : p->mu;
     c.aT = c1 * dt + (double)(dt * CT);
@@ -223,16 +243,15 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
     } else {
       c.w1T = c.w1N = 0.0;
     }
+    c.ring_off = d->ring_off[n];
+    c.Rn = d->Rn[n];
     c.part0 = d->part0[n];
     c.nparts = d->nparts[n];
-    th[n] = (double)(theta / (long double)kTableStep);
+    c.pad = 0;
   }
   hipError_t e = hipSuccess;
   hipStream_t s = p->stream;
   d->coef = upload(d->mem, coef, s, &e);
-  if (!e) d->theta_h = upload(d->mem, th, s, &e);
-  if (!e) d->d_Rn = upload(d->mem, d->Rn, s, &e);
-  if (!e) d->d_ring_off = upload(d->mem, d->ring_off, s, &e);
   if (!e) {
     d->parts = (double4*)d->mem.get(sizeof(double4) * std::max(1, parts));
     if (!d->parts) e = hipErrorOutOfMemory;
@@ -326,13 +345,14 @@ int build_dyn_data(sbiem_plan* p, DynData** out) {
   sp(&d->hprev_g);
   sp(&d->B_T);
   sp(&d->B_N);
-  sp(&d->P_T);
-  sp(&d->P_N);
-  d->zbuf = d->mem.get(N * sizeof(double2));
+  // exchange buffers sized for FP64 complex (FP32 uses the first half)
+  d->gI = d->mem.get(N * sizeof(double2));
+  d->gF = d->mem.get(N * sizeof(double2));
   d->step = (long long*)d->mem.get(sizeof(long long) * 2);
   d->err = (int*)d->mem.get(sizeof(int) * 4);
-  d->inv_exp = (int*)d->mem.get(sizeof(int) * 2);
-  ok = ok && d->zbuf && d->step && d->err && d->inv_exp;
+  d->cells = (int*)d->mem.get(sizeof(int) * 8);
+  d->done = d->cells + 6;
+  ok = ok && d->gI && d->gF && d->step && d->err && d->cells;
   if (!ok) {
     delete d;
     return fail(p, SBIEM_ENOMEM, "device allocation of the state buffers failed");
@@ -347,10 +367,11 @@ int build_dyn_data(sbiem_plan* p, DynData** out) {
     if (!e) e = hipMemsetAsync(d->sigma_el[k], 0, N * sizeof(double), s);
   }
   double2* spec[] = {d->u_hat, d->g_hat, d->v_hat0, d->gv_hat0, d->v_hat1, d->gv_hat1,
-                     d->hprev_v, d->hprev_g, d->B_T, d->B_N, d->P_T, d->P_N};
+                     d->hprev_v, d->hprev_g, d->B_T, d->B_N};
   for (double2* q : spec)
     if (!e) e = hipMemsetAsync(q, 0, M * sizeof(double2), s);
   if (!e) e = hipMemsetAsync(d->step, 0, sizeof(long long) * 2, s);
+  if (!e) e = hipMemsetAsync(d->cells, 0, sizeof(int) * 8, s);
   const int init[4] = {0, 0, 0x7fffffff, 0};
   if (!e) e = hipMemcpyAsync(d->err, init, sizeof(init), hipMemcpyHostToDevice, s);
   if (!e) e = hipStreamSynchronize(s);
@@ -368,6 +389,12 @@ FaultDev make_fault_desc(sbiem_plan* p, DtData* dtd, DynData* dyn, double V_pl, 
   f.N = (int)p->N;
   f.log2N = p->log2N;
   f.nmodes = (int)(p->N / 2);
+  f.log2P = p->log2P;
+  f.log2Q = p->log2Q;
+  f.P = 1 << p->log2P;
+  f.Q = 1 << p->log2Q;
+  f.ngroups = std::max(1, f.P / 2);
+  f.ncls = p->ncls;
   f.theta_mode = p->theta_mode;
   f.L = p->L;
   f.mu = p->mu;
@@ -407,20 +434,17 @@ FaultDev make_fault_desc(sbiem_plan* p, DtData* dtd, DynData* dyn, double V_pl, 
   f.hprev_g = dyn->hprev_g;
   f.B_T = dyn->B_T;
   f.B_N = dyn->B_N;
-  f.P_T = dyn->P_T;
-  f.P_N = dyn->P_N;
-  f.inv_exp = dyn->inv_exp;
   f.fwd_scale = p->fwd_scale;
+  f.gI = dyn->gI;
+  f.gF = dyn->gF;
+  f.cells = dyn->cells;
+  f.done = dyn->done;
   if (dtd) {
     f.coef = dtd->coef;
-    f.Rn = dtd->d_Rn;
-    f.ring_off = dtd->d_ring_off;
-    f.theta_h = dtd->theta_h;
     f.parts = dtd->parts;
     f.ring = dtd->ring;
     f.wrev = dtd->wrev;
   }
-  f.zbuf = dyn->zbuf;
   f.twiddle = p->twiddle;
   f.step = dyn->step;
   f.err = dyn->err;
@@ -437,16 +461,6 @@ namespace {
 
 int check_plan(sbiem_plan* p) {
   if (!p) return fail_global(SBIEM_EINVAL, "NULL plan");
-  return SBIEM_OK;
-}
-
-// The spectral kernels keep one N-point complex transform in LDS.
-int check_fft_fits(sbiem_plan* p) {
-  const int64_t lim = p->precision == SBIEM_FP32CONV ? 16384 : 8192;
-  if (p->N > lim)
-    return fail(p, SBIEM_EINVAL,
-                p->precision == SBIEM_FP64 ? "FP64 transforms hold at most 8192 points: use SBIEM_FP32CONV"
-                                           : "FP32 transforms hold at most 16384 points");
   return SBIEM_OK;
 }
 
@@ -553,9 +567,6 @@ int sbiem_plan_create(sbiem_plan** out, int64_t N, double L, double mu, double n
     return fail_global(SBIEM_EINVAL, m.str());
   }
   if (h && !all_finite(h, N)) return fail_global(SBIEM_EINVAL, "plan_create: h must be finite");
-  const int maxN = 16384;
-  if (N > maxN)
-    return fail_global(SBIEM_EINVAL, "plan_create: N above 16384 needs the multi-workgroup FFT (not built)");
 
   sbiem_plan* p = new sbiem_plan();
   hipError_t e = hipGetDevice(&p->device);
@@ -566,6 +577,7 @@ int sbiem_plan_create(sbiem_plan** out, int64_t N, double L, double mu, double n
   p->N = N;
   p->log2N = 0;
   while ((int64_t(1) << p->log2N) < N) ++p->log2N;
+  split_sizes(p->log2N, &p->log2P, &p->log2Q, &p->ncls);
   p->L = L;
   p->mu = mu;
   p->nu = nu;
@@ -588,7 +600,10 @@ int sbiem_plan_create(sbiem_plan** out, int64_t N, double L, double mu, double n
     delete p;
     return fail_global(SBIEM_ENOMEM, "plan_create: device allocation failed");
   }
-  e = hipMemcpy(p->kappa, p->kappa_host.data(), bytes, hipMemcpyHostToDevice);
+  {
+    std::vector<double> kp = to_elem_order(p, p->kappa_host.data());
+    e = hipMemcpy(p->kappa, kp.data(), bytes, hipMemcpyHostToDevice);
+  }
   if (e) {
     delete p;
     return fail_global(SBIEM_EDEVICE, std::string("plan_create: ") + hipGetErrorString(e));
@@ -659,11 +674,17 @@ int sbiem_set_friction(sbiem_plan* p, const double* a, const double* b, double D
     return fail(p, SBIEM_EINVAL, "set_friction: need Dc, V_ref > 0, V_pl >= 0, finite f0 and rate");
   if (int s = ensure_device(p)) return s;
   const size_t bytes = (size_t)N * sizeof(double);
-  hipError_t e = hipMemcpyAsync(p->a, a, bytes, hipMemcpyHostToDevice, p->stream);
-  if (!e) e = hipMemcpyAsync(p->b, b, bytes, hipMemcpyHostToDevice, p->stream);
-  if (!e) e = hipMemcpyAsync(p->sigma_load, sigma_load, bytes, hipMemcpyHostToDevice, p->stream);
-  if (!e) e = hipMemcpyAsync(p->tau_load, tau_load, bytes, hipMemcpyHostToDevice, p->stream);
-  if (!e) e = hipStreamSynchronize(p->stream);
+  hipError_t e = hipStreamSynchronize(p->stream);
+  {
+    std::vector<double> x = to_elem_order(p, a);
+    if (!e) e = hipMemcpy(p->a, x.data(), bytes, hipMemcpyHostToDevice);
+    x = to_elem_order(p, b);
+    if (!e) e = hipMemcpy(p->b, x.data(), bytes, hipMemcpyHostToDevice);
+    x = to_elem_order(p, sigma_load);
+    if (!e) e = hipMemcpy(p->sigma_load, x.data(), bytes, hipMemcpyHostToDevice);
+    x = to_elem_order(p, tau_load);
+    if (!e) e = hipMemcpy(p->tau_load, x.data(), bytes, hipMemcpyHostToDevice);
+  }
   if (e) return hip_fail(p, e, "set_friction");
   p->Dc = Dc;
   p->V_ref = V_ref;
@@ -681,7 +702,6 @@ int sbiem_set_friction(sbiem_plan* p, const double* a, const double* b, double D
 int sbiem_set_state(sbiem_plan* p, const double* slip, const double* V, const double* theta, double t) {
   if (int s = check_plan(p)) return s;
   if (!p->friction_set) return fail(p, SBIEM_ENOTREADY, "set_state: set_friction first");
-  if (int s = check_fft_fits(p)) return s;
   const int64_t N = p->N;
   if (!slip || !V || !theta) return fail(p, SBIEM_EINVAL, "set_state: NULL array");
   if (!all_finite(slip, N) || !all_finite(V, N) || !all_finite(theta, N) || !std::isfinite(t))
@@ -694,10 +714,18 @@ int sbiem_set_state(sbiem_plan* p, const double* slip, const double* V, const do
   DynData* d = p->dyn;
   const size_t bytes = (size_t)N * sizeof(double);
   hipStream_t s = p->stream;
-  hipError_t e = hipMemcpyAsync(d->slip[0], slip, bytes, hipMemcpyHostToDevice, s);
-  if (!e) e = hipMemcpyAsync(d->V[0], V, bytes, hipMemcpyHostToDevice, s);
-  if (!e) e = hipMemcpyAsync(d->theta[0], theta, bytes, hipMemcpyHostToDevice, s);
-  if (!e) e = hipMemcpyAsync(d->thd[0], thd.data(), bytes, hipMemcpyHostToDevice, s);
+  hipError_t e = hipStreamSynchronize(s);
+  {
+    // both buffers of the double-buffered state get the initial state (the
+    // other buffer stands for the step before the first one)
+    const double* host[4] = {slip, V, theta, thd.data()};
+    double* const* dev[4] = {d->slip, d->V, d->theta, d->thd};
+    for (int k = 0; k < 4 && !e; ++k) {
+      std::vector<double> x = to_elem_order(p, host[k]);
+      e = hipMemcpy(dev[k][0], x.data(), bytes, hipMemcpyHostToDevice);
+      if (!e) e = hipMemcpy(dev[k][1], x.data(), bytes, hipMemcpyHostToDevice);
+    }
+  }
   for (int k = 0; k < 2 && !e; ++k) {
     e = hipMemsetAsync(d->tau_el[k], 0, bytes, s);
     if (!e) e = hipMemsetAsync(d->sigma_el[k], 0, bytes, s);
@@ -723,12 +751,10 @@ int sbiem_get_state(sbiem_plan* p, double* slip, double* V, double* theta, doubl
   if (!e) e = hipMemcpy(&step, d->step, sizeof(step), hipMemcpyDeviceToHost);
   if (e) return hip_fail(p, e, "get_state");
   const int cur = (int)(step & 1);
-  const size_t bytes = (size_t)p->N * sizeof(double);
-  if (!e && slip) e = hipMemcpy(slip, d->slip[cur], bytes, hipMemcpyDeviceToHost);
-  if (!e && V) e = hipMemcpy(V, d->V[cur], bytes, hipMemcpyDeviceToHost);
-  if (!e && theta) e = hipMemcpy(theta, d->theta[cur], bytes, hipMemcpyDeviceToHost);
-  if (!e && tau_el) e = hipMemcpy(tau_el, d->tau_el[cur], bytes, hipMemcpyDeviceToHost);
-  if (!e && sigma_el) e = hipMemcpy(sigma_el, d->sigma_el[cur], bytes, hipMemcpyDeviceToHost);
+  const double* src[5] = {d->slip[cur], d->V[cur], d->theta[cur], d->tau_el[cur], d->sigma_el[cur]};
+  double* dst[5] = {slip, V, theta, tau_el, sigma_el};
+  for (int k = 0; k < 5 && !e; ++k)
+    if (dst[k]) e = download_elems(p, src[k], dst[k]);
   if (e) return hip_fail(p, e, "get_state");
   if (t) *t = p->t0 + (double)step * (p->dtd ? p->dtd->dt : 0.0);
   return SBIEM_OK;
@@ -751,7 +777,6 @@ int sbiem_window_lengths(const sbiem_plan* p, double dt, int64_t* M) {
 
 int sbiem_set_dt(sbiem_plan* p, double dt) {
   if (int s = check_plan(p)) return s;
-  if (int s = check_fft_fits(p)) return s;
   if (!(dt > 0) || !std::isfinite(dt)) return fail(p, SBIEM_EINVAL, "set_dt: need dt > 0");
   if (int s = ensure_device(p)) return s;
   hipError_t e = hipStreamSynchronize(p->stream);
