@@ -2,6 +2,9 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
+NAME is one of rough-N256-fp64, seamount-N8192 (default), ensemble64,
+rough-N65536, ensemble16-N262144 (ensembles run as one batch).
+
 One "step" is the whole two-pass time step (history convolution, FFTs,
 traction assembly, friction solve, commit) of the named workload with its
 inputs resident in HBM.  Prints one JSON line with element-steps/s, the
@@ -27,6 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "element-steps/s (stress+friction) at fixed accuracy; plain vs learned-closure, HBM %"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2107_03550_amd", "csrc", "kernels.hip")
+ENSEMBLES = ("ensemble64", "ensemble16-N262144")
 
 
 def kernel_hash() -> str:
@@ -103,59 +107,80 @@ def main():
 
     import torch
     import paper_2107_03550_amd as pkg
-    from sbiem_inputs import workload
+    from sbiem_inputs import ensemble_members, workload
 
     if not torch.cuda.is_available():
         print("bench.py: no GPU", file=sys.stderr)
         sys.exit(1)
-    w = workload(args.workload)
-    plan, fr = build_plan(w, pkg)
     stream = torch.cuda.current_stream()
-    plan.set_stream(stream.cuda_stream)
+    if args.workload in ENSEMBLES:
+        # an ensemble: one batch of independent faults, stepped together
+        members = ensemble_members(args.workload)
+        plans = []
+        for m in members:
+            p, _ = build_plan(m, pkg)
+            p.set_stream(stream.cuda_stream)
+            plans.append(p)
+        runner = pkg.Batch(plans)
+        w = members[0]
+        n_total = sum(m.N for m in members)
+        run = runner.run
+    else:
+        w = workload(args.workload)
+        runner, fr = build_plan(w, pkg)
+        runner.set_stream(stream.cuda_stream)
+        n_total = w.N
+        members = [w]
+        run = lambda k: runner.run(w.dt, k)  # noqa: E731
 
-    plan.run(w.dt, args.warmup)
+    run(args.warmup)
     torch.cuda.synchronize()
 
     # timed region: K steps; every conv launch bracketed by HIP events on the
-    # plan's stream (the stream the kernels are launched on)
-    plan.set_profiling(True)
+    # stream the conv kernel is launched on
+    runner.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan.run(w.dt, args.steps)
+    run(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    conv_ms, conv_n, conv_bytes = plan.profile()
-    plan.set_profiling(False)
+    conv_ms, conv_n, conv_bytes = runner.profile()
+    runner.set_profiling(False)
     wall = t1 - t0
-    value = w.N * args.steps / wall
+    value = n_total * args.steps / wall
 
     # the same K steps replayed through the captured HIP graph (no events)
     torch.cuda.synchronize()
     g0 = time.perf_counter()
-    plan.run(w.dt, args.steps)
+    run(args.steps)
     torch.cuda.synchronize()
     g1 = time.perf_counter()
-    graph_value = w.N * args.steps / (g1 - g0)
+    graph_value = n_total * args.steps / (g1 - g0)
 
     avg_ms = conv_ms / max(conv_n, 1)
     achieved = conv_bytes / (avg_ms * 1e-3) / 1e9
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(w.name),
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(args.workload),
         "kernel": "k_conv32" if w.precision != "fp64" else "k_conv64",
         "bytes_per_launch": conv_bytes, "avg_launch_us": round(avg_ms * 1e3, 3),
         "launches": conv_n,
     }
-    cpu = None if args.no_cpu else cpu_baseline(w, fr, args.cpu_seconds)
+    cpu = None
+    if not args.no_cpu and args.workload not in ENSEMBLES and w.N <= 16384:
+        cpu = cpu_baseline(w, fr, args.cpu_seconds)
     out = {
         "metric": METRIC, "value": value, "unit": "element-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if w.precision != "fp64" else "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "N": w.N, "L_m": w.L, "dt_s": w.dt,
+        "config": {"workload": args.workload, "N": w.N if len(members) == 1 else
+                   sorted({m.N for m in members}), "elements": n_total,
+                   "L_m": w.L if len(members) == 1 else "10 N m" if args.workload == "ensemble64"
+                   else w.L, "dt_s": w.dt,
                    "precision": "fp32 convolution/FFT, fp64 friction" if w.precision != "fp64"
-                   else "fp64", "window": "full (plain)", "faults": 1},
+                   else "fp64", "window": "full (plain)", "faults": len(members)},
         "graph_replay_value": graph_value,
         "roofline": roofline,
         "cpu_baseline": cpu,

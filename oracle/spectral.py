@@ -6,8 +6,11 @@ transform F_n = sum_i f_i exp(-i k_n x_i), inverse
 f_i = (1/N) sum_n F_n exp(+i k_n x_i).  The forward sign exp(-ikx) is the one
 under which both Fourier pairs of appendix B hold as printed.
 
-The transform is an explicit O(N^2) sum (a matrix-vector product with the
-DFT matrix built from exact integer phases), never an FFT.
+``dft``/``idft`` are explicit O(N^2) sums (a matrix-vector product with the
+DFT matrix built from exact integer phases).  ``fft_dft``/``fft_idft_real``
+take the same transforms from numpy's FFT, a library primitive used as one
+step where N is too large for the explicit sums; the tests pin them to the
+explicit sums.
 """
 
 from __future__ import annotations
@@ -83,6 +86,25 @@ def idft_real(F: np.ndarray) -> np.ndarray:
     return idft(F).real
 
 
+def fft_dft(f: np.ndarray) -> np.ndarray:
+    """The forward transform of ``dft`` by numpy's FFT (same sign and scale)."""
+    return np.fft.fft(np.asarray(f), axis=-1)
+
+
+def fft_idft_real(F: np.ndarray) -> np.ndarray:
+    """The inverse transform of ``idft_real`` by numpy's FFT."""
+    return np.fft.ifft(np.asarray(F), axis=-1).real
+
+
+def transforms(kind: str):
+    """(forward, inverse-real) pair: ``"naive"`` sums or ``"fft"``."""
+    if kind == "naive":
+        return dft, idft_real
+    if kind == "fft":
+        return fft_dft, fft_idft_real
+    raise ValueError(kind)
+
+
 def curvature(h: np.ndarray, L: float) -> np.ndarray:
     """kappa = h'' by spectral differentiation, kappa = IDFT(-k^2 DFT(h)).
 
@@ -92,3 +114,10 @@ def curvature(h: np.ndarray, L: float) -> np.ndarray:
     N = len(h)
     k = wavenumbers(N, L)
     return idft_real(-(k ** 2) * dft(h))
+
+
+def curvature_fft(h: np.ndarray, L: float) -> np.ndarray:
+    """``curvature`` with numpy's FFT as the transform (for large N)."""
+    N = len(h)
+    k = wavenumbers(N, L)
+    return fft_idft_real(-(k ** 2) * fft_dft(h))

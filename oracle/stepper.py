@@ -36,7 +36,7 @@ from __future__ import annotations
 import numpy as np
 
 from .friction import solve_newton
-from .spectral import curvature, dft, idft_real, odd_sign, wavenumbers
+from .spectral import curvature, curvature_fft, odd_sign, transforms, wavenumbers
 from .windows import KernelTable, midpoint_weights
 
 ERR_NEWTON = -4
@@ -54,15 +54,22 @@ class OracleFault:
     """One periodic fault integrated by the oracle's two-pass scheme."""
 
     def __init__(self, N, L, mu, cs, cp, *, dt, friction, h=None, kappa=None,
-                 table: KernelTable | None = None, theta_mode="paper"):
+                 table: KernelTable | None = None, theta_mode="paper",
+                 transform="naive", max_lag=None):
+        """``transform``: "naive" (explicit DFT sums) or "fft" (numpy FFT);
+        ``max_lag``: keep only window lags below it, which limits the run to
+        max_lag steps from the state set (longer runs raise)."""
         self.N, self.L, self.mu, self.cs, self.cp, self.dt = N, L, mu, cs, cp, dt
+        self._fwd, self._inv = transforms(transform)
+        self.max_lag = max_lag
         self.r = (cs / cp) ** 2
         if kappa is None:
-            kappa = curvature(np.zeros(N) if h is None else np.asarray(h, float), L)
+            hh = np.zeros(N) if h is None else np.asarray(h, float)
+            kappa = curvature_fft(hh, L) if transform == "fft" else curvature(hh, L)
         self.kappa = np.asarray(kappa, dtype=np.float64)
         self.kabs = np.abs(wavenumbers(N, L))
         self.s = odd_sign(N)
-        self.w = midpoint_weights(N, L, cs, cp, dt, table)
+        self.w = midpoint_weights(N, L, cs, cp, dt, table, max_lag=max_lag)
         f = friction
         self.a, self.b = np.asarray(f["a"], float), np.asarray(f["b"], float)
         self.Dc, self.V_ref, self.f0 = f["Dc"], f["V_ref"], f["f0"]
@@ -105,6 +112,8 @@ class OracleFault:
         self.HN[:] = 0
         self.tau_el = np.zeros(self.N)
         self.sigma_el = np.zeros(self.N)
+        self.tau_static = np.zeros(self.N)
+        self.sigma_static = np.zeros(self.N)
         self.nsteps = 0
 
     def history_sums(self):
@@ -119,11 +128,16 @@ class OracleFault:
         """Elastic tau, sigma at t_new for predicted slip and current rate V_c."""
         u = slip_p - self.V_pl * t_new
         v = V_c - self.V_pl
-        U, G = dft(u), dft(self.kappa * u)
-        Vh, GV = dft(v), dft(self.kappa * v)
-        tau_hat = -self.mu * self.kabs * ((1 - self.r) * U + self._w0T * Vh + ST)
-        sig_hat = -1j * self.s * self.mu * ((1 - self.r) * G + self._w0N * GV + SN)
-        return idft_real(tau_hat), idft_real(sig_hat), Vh, GV
+        U, G = self._fwd(u), self._fwd(self.kappa * u)
+        Vh, GV = self._fwd(v), self._fwd(self.kappa * v)
+        stat_T = -self.mu * self.kabs * (1 - self.r) * U
+        stat_N = -1j * self.s * self.mu * (1 - self.r) * G
+        tau_hat = stat_T - self.mu * self.kabs * (self._w0T * Vh + ST)
+        sig_hat = stat_N - 1j * self.s * self.mu * (self._w0N * GV + SN)
+        # static parts (the (1-r) slip terms) of the last evaluation: the FP32
+        # comparison scale where static and dynamic parts cancel
+        self._last_static = (stat_T, stat_N)
+        return self._inv(tau_hat), self._inv(sig_hat), Vh, GV
 
     def _pass(self, V_c, thd_c, ST, SN):
         dt = self.dt
@@ -149,6 +163,8 @@ class OracleFault:
         return slip_p, theta_p, V_p, thd_p, tau_el, sig_el, Vh, GV
 
     def step(self):
+        if self.max_lag is not None and self.nsteps >= self.max_lag:
+            raise ValueError("history longer than the weights kept (max_lag)")
         ST, SN = self.history_sums()
         V0, thd0 = self.V, self.thetadot
         _, _, V1, thd1, _, _, _, _ = self._pass(V0, thd0, ST, SN)
@@ -159,6 +175,8 @@ class OracleFault:
         self.HN = np.where(self._first, GV[self._hist_mode], self.HN[self._shift_src])
         self.slip, self.V, self.theta, self.thetadot = slip2, V2, theta2, thd2
         self.tau_el, self.sigma_el = tau_el, sig_el
+        self.tau_static = self._inv(self._last_static[0])
+        self.sigma_static = self._inv(self._last_static[1])
         self.t += self.dt
         self.nsteps += 1
 

@@ -26,13 +26,19 @@ from __future__ import annotations
 
 import numpy as np
 
-from .spectral import dft, idft_real, odd_sign, wavenumbers
+from .spectral import odd_sign, transforms, wavenumbers
 from .windows import Weights
 
 
 def stress_from_history(slip_hist, dt, L, mu, cs, cp, kappa, weights: Weights,
-                        V_pl=0.0, t0=0.0):
-    """(tau^el, sigma^el) at the last snapshot of ``slip_hist`` (nt+1, N)."""
+                        V_pl=0.0, t0=0.0, transform="naive", parts=False):
+    """(tau^el, sigma^el) at the last snapshot of ``slip_hist`` (nt+1, N).
+
+    ``transform``: "naive" (explicit DFT sums) or "fft" (numpy FFT).
+    ``weights`` may keep only the lags below nt (``max_lag``).  With
+    ``parts`` the static terms (the (1-r) slip terms) follow as two more
+    arrays."""
+    dft, idft_real = transforms(transform)
     slip_hist = np.asarray(slip_hist, dtype=np.float64)
     nt = slip_hist.shape[0] - 1
     N = slip_hist.shape[1]
@@ -56,4 +62,7 @@ def stress_from_history(slip_hist, dt, L, mu, cs, cp, kappa, weights: Weights,
             conv_N[n] = np.dot(wN[:m], RG[:m, n])
     tau_hat = -mu * kabs * ((1 - r) * U + conv_T)
     sig_hat = -1j * s * mu * ((1 - r) * G + conv_N)
+    if parts:
+        return (idft_real(tau_hat), idft_real(sig_hat), idft_real(-mu * kabs * (1 - r) * U),
+                idft_real(-1j * s * mu * (1 - r) * G))
     return idft_real(tau_hat), idft_real(sig_hat)

@@ -68,14 +68,17 @@ class Weights:
 
 
 def midpoint_weights(N: int, L: float, cs: float, cp: float, dt: float,
-                     table: KernelTable | None = None) -> Weights:
+                     table: KernelTable | None = None, max_lag: int | None = None) -> Weights:
     """w^X_{n,j} = dt * C^X(c_s |k_n| (j + 1/2) dt) for X in {T, N}.
 
     With ``table`` the kernel values are taken from a 30-digit table indexed
     by p = |n|(2j+1) (its delta must equal pi c_s dt / L); otherwise the
-    FP64 closed forms are evaluated directly.
+    FP64 closed forms are evaluated directly.  ``max_lag`` keeps only lags
+    j < max_lag of every window (enough for a history of max_lag intervals).
     """
     M = window_steps(N, L, cs, dt)
+    if max_lag is not None:
+        M = np.minimum(M, int(max_lag))
     off = np.concatenate([[0], np.cumsum(M)[:-1]]).astype(np.int64)
     nabs = np.abs(signed_frequencies(N))
     mode_of = np.repeat(np.arange(N), M)

@@ -280,6 +280,7 @@ int ready(sbiem_plan* p, double dt) {
 // One step in steady state: the next step's history sums on the second
 // stream beside the element/mode stages of this step, joined before the
 // commit launch that consumes them.
+// While profiling, events e0/e1 bracket the conv launch.
 hipError_t launch_step(Exec& ex, hipStream_t s, hipStream_t aux, bool profile, hipEvent_t e0,
                        hipEvent_t e1) {
   hipError_t e = hipEventRecord(ex.fork, s);
@@ -348,21 +349,28 @@ hipError_t ensure_graph(Exec* ex, hipStream_t s) {
 
 // Run nsteps of an execution context on stream s.  While profiling, every
 // step is launched directly with a pair of events around its conv launch
-// (no host synchronisation inside the run); the elapsed times are summed
-// once the run has finished.
+// (HIP graphs do not give usable times for event nodes; no host
+// synchronisation inside a chunk of steps); the elapsed times are summed
+// once the chunk has finished.
 hipError_t run_steps(Exec* ex, int64_t nsteps, hipStream_t s, bool profile, EventPool* pool,
-                     double* prof_ms, int64_t* prof_launches) {
+                     double* prof_ms, int64_t* prof_launches, const char** what) {
+  *what = "running the time steps";
   if (nsteps <= 0) return hipSuccess;
+  *what = "running the prologue launches";
   hipError_t e = prologue(*ex, s);
   if (e) return e;
   if (profile) {
-    const int64_t chunk = 4096;
+    const int64_t chunk = 8192;
     for (int64_t done = 0; done < nsteps && !e; done += chunk) {
       const int64_t n = std::min(chunk, nsteps - done);
+      *what = "creating timing events";
       e = pool->ensure((size_t)(2 * n));
+      *what = "launching profiled steps";
       for (int64_t k = 0; k < n && !e; ++k)
         e = launch_step(*ex, s, ex->aux, true, pool->ev[2 * k], pool->ev[2 * k + 1]);
+      *what = "waiting for profiled steps";
       if (!e) e = hipStreamSynchronize(s);
+      *what = "reading the timing events";
       for (int64_t k = 0; k < n && !e; ++k) {
         float ms = 0.f;
         e = hipEventElapsedTime(&ms, pool->ev[2 * k], pool->ev[2 * k + 1]);
@@ -376,13 +384,16 @@ hipError_t run_steps(Exec* ex, int64_t nsteps, hipStream_t s, bool profile, Even
   }
   int64_t left = nsteps;
   if (left >= kGraphSteps) {
+    *what = "capturing the step graph";
     e = ensure_graph(ex, s);
     if (e) return e;
+    *what = "launching the step graph";
     while (left >= kGraphSteps && !e) {
       e = hipGraphLaunch(ex->graph, s);
       left -= kGraphSteps;
     }
   }
+  *what = "launching steps";
   for (int64_t k = 0; k < left && !e; ++k) e = launch_step(*ex, s, ex->aux, false, nullptr, nullptr);
   return e;
 }
@@ -406,10 +417,14 @@ int sbiem_run(sbiem_plan* p, double dt, int64_t nsteps) {
   if (!p->exec) {
     if (int st = rebuild_exec(p)) return st;
   }
+  const char* what = "";
   e = run_steps(p->exec, nsteps, p->stream, p->profiling, &p->events, &p->prof_ms,
-                &p->prof_launches);
-  if (!e) e = hipStreamSynchronize(p->stream);
-  if (e) return hip_fail(p, e, "running the time steps");
+                &p->prof_launches, &what);
+  if (!e) {
+    what = "waiting for the time steps";
+    e = hipStreamSynchronize(p->stream);
+  }
+  if (e) return hip_fail(p, e, what);
   return check_failure(p);
 }
 
@@ -583,11 +598,16 @@ int sbiem_batch_run(sbiem_batch* b, int64_t nsteps) {
       e = hipMemcpy(b->exec->d_faults + f, &d, sizeof(d), hipMemcpyHostToDevice);
     }
   }
+  const char* what = "refreshing the descriptors";
   if (!e)
     e = run_steps(b->exec, nsteps, b->stream, b->profiling, &b->events, &b->prof_ms,
-                  &b->prof_launches);
-  if (!e) e = hipStreamSynchronize(b->stream);
-  if (e) return fail_global(SBIEM_EDEVICE, std::string("batch_run: ") + hipGetErrorString(e));
+                  &b->prof_launches, &what);
+  if (!e) {
+    what = "waiting for the time steps";
+    e = hipStreamSynchronize(b->stream);
+  }
+  if (e)
+    return fail_global(SBIEM_EDEVICE, std::string("batch_run: ") + what + ": " + hipGetErrorString(e));
   int first = SBIEM_OK;
   for (sbiem_plan* p : b->plans) {
     int st = check_failure(p);

@@ -62,6 +62,16 @@ def make_oracle(sc: Scenario, table=None):
                        table=table, theta_mode=sc.theta_mode)
 
 
+def rel_parts(a, total, static):
+    """FP32 comparison norm: ||a - total||_inf over the largest of ||total||,
+    ||static|| and ||total - static|| (where the static and dynamic parts
+    cancel, FP32 rounding scales with the parts, not with their sum)."""
+    total, static = np.asarray(total), np.asarray(static)
+    scale = max(np.max(np.abs(total)), np.max(np.abs(static)), np.max(np.abs(total - static)))
+    d = np.max(np.abs(np.asarray(a) - total))
+    return d / scale if scale > 0 else d
+
+
 def rel(a, b):
     """Norm-wise relative difference ||a - b||_inf / ||b||_inf."""
     d = np.max(np.abs(np.asarray(a) - np.asarray(b)))

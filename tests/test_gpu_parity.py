@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from scenarios import (DT_10KM, Scenario, golden_table, make_oracle, make_plan, rel,
-                       rough_10km, seamount_h, MU, NU, CS, CP)
+                       rel_parts, rough_10km, seamount_h, MU, NU, CS, CP)
 from sbiem_inputs import FrictionSpec
 
 pytestmark = pytest.mark.gpu
@@ -150,6 +150,24 @@ def test_run_with_graph_equals_single_steps_bitwise():
         assert np.array_equal(ga[k], gb[k]), k
 
 
+def test_profiled_run_equals_plain_run_bitwise():
+    """Profiled runs (direct launches with timing events around every conv
+    launch) compute exactly what graph replays do, and time every launch."""
+    pkg = _pkg()
+    sc = Scenario(256, 10e3, DT_10KM, rough_10km(256, seed=4), theta_mode="exp",
+                  spec=FrictionSpec(overstress=8e6), consistent_V0=True)
+    a = make_plan(sc, pkg.SBIEM_FP32CONV)
+    b = make_plan(sc, pkg.SBIEM_FP32CONV)
+    a.set_profiling(True)
+    a.run(sc.dt, 53)
+    ms, n, nbytes = a.profile()
+    assert n == 53 and ms > 0.0 and nbytes > 0.0
+    b.run(sc.dt, 53)
+    ga, gb = a.get_state(), b.get_state()
+    for k in ("slip", "V", "theta", "tau_el", "sigma_el"):
+        assert np.array_equal(ga[k], gb[k]), k
+
+
 def test_failure_leaves_state_at_start_of_step():
     pkg = _pkg()
     sc = Scenario(64, 10e3, DT_10KM, rough_10km(64, seed=5, alpha=5e-2))
@@ -188,6 +206,95 @@ def test_batch_matches_individual_plans_bitwise():
     for p in plans_b:
         p.run(dt, 40)
     for pa, pb in zip(plans_a, plans_b):
+        ga, gb = pa.get_state(), pb.get_state()
+        for k in ("slip", "V", "theta", "tau_el", "sigma_el"):
+            assert np.array_equal(ga[k], gb[k]), k
+    batch.close()
+
+
+# ---------------------------------------------------------------- full sizes
+def _workload_plan_and_oracle(w, nsteps):
+    """A plan of workload ``w`` as bench.py builds it, and the oracle on the
+    same inputs (numpy FFT as the transform, weights for nsteps lags)."""
+    from oracle.stepper import OracleFault
+    from sbiem_inputs import friction_fields
+    pkg = _pkg()
+    fr = friction_fields(w.N, w.L, w.mu, w.cs, w.friction)
+    p = pkg.Plan(w.N, w.L, w.mu, w.nu, w.cs, w.cp, w.h)
+    p.set_precision(pkg.SBIEM_FP32CONV)
+    p.set_friction(fr["a"], fr["b"], fr["Dc"], fr["V_ref"], fr["f0"], fr["sigma_load"],
+                   fr["tau_load"], fr["tau_load_rate"], fr["V_pl"])
+    p.set_state(fr["slip0"], fr["V0"], fr["theta0"], 0.0)
+    p.set_dt(w.dt)
+    o = OracleFault(w.N, w.L, w.mu, w.cs, w.cp, dt=w.dt, friction=fr, h=w.h,
+                    transform="fft", max_lag=nsteps)
+    return p, o
+
+
+@pytest.mark.parametrize("name", ["rough-N65536", "ensemble16-N262144"])
+def test_step_fp32_full_size_matches_oracle(name):
+    """The first 20 steps of the full-size workloads (graph replay, as in
+    bench.py) against the oracle, compared after a 16-step graph replay and
+    after 4 single steps.  The tractions are then tiny (the fault is still
+    near steady state), the sum of much larger static and dynamic parts, so
+    the FP32 gate of 1e-5 is taken relative to the larger part."""
+    from sbiem_inputs import ensemble_members, workload
+    w = workload(name) if name != "ensemble16-N262144" else ensemble_members(name)[0]
+    p, o = _workload_plan_and_oracle(w, 20)
+    worst = {"tau_el": 0.0, "sigma_el": 0.0, "slip": 0.0, "V": 0.0,
+             "tau_el_plain": 0.0, "sigma_el_plain": 0.0}
+    for chunk in (16, 4):
+        p.run(w.dt, chunk)
+        o.run(chunk)
+        g = p.get_state()
+        for k, ref in (("slip", o.slip), ("V", o.V)):
+            worst[k] = max(worst[k], rel(g[k], ref))
+        worst["tau_el"] = max(worst["tau_el"], rel_parts(g["tau_el"], o.tau_el, o.tau_static))
+        worst["sigma_el"] = max(worst["sigma_el"], rel_parts(g["sigma_el"], o.sigma_el, o.sigma_static))
+        worst["tau_el_plain"] = max(worst["tau_el_plain"], rel(g["tau_el"], o.tau_el))
+        worst["sigma_el_plain"] = max(worst["sigma_el_plain"], rel(g["sigma_el"], o.sigma_el))
+    print(name, "worst relative errors", worst)
+    assert worst["tau_el"] < 1e-5 and worst["sigma_el"] < 1e-5, worst
+    assert worst["slip"] < 1e-10 and worst["V"] < 1e-10, worst
+
+
+def test_stress_fp32_full_size_N262144():
+    """sbiem_stress at N = 262144 (two elements per thread in the element
+    stage, four slots per thread in the mode stage) against the oracle."""
+    from oracle.spectral import curvature_fft
+    from oracle.stress import stress_from_history
+    from oracle.windows import midpoint_weights
+    from sbiem_inputs import ensemble_members
+    pkg = _pkg()
+    w = ensemble_members("ensemble16-N262144")[1]
+    nt = 5
+    hist = _history(w.N, nt, seed=9)
+    p = pkg.Plan(w.N, w.L, w.mu, w.nu, w.cs, w.cp, w.h)
+    p.set_precision(pkg.SBIEM_FP32CONV)
+    tau, sig = p.stress(hist, w.dt)
+    wts = midpoint_weights(w.N, w.L, w.cs, w.cp, w.dt, max_lag=nt)
+    kappa = curvature_fft(w.h, w.L)
+    # the library's curvature (extended precision) and numpy's FFT agree to
+    # the double-precision amplification of rounding by k^2
+    assert rel(p.get_curvature(), kappa) < 1e-9
+    rt, rs, st, ss = stress_from_history(hist, w.dt, w.L, w.mu, w.cs, w.cp, kappa, wts,
+                                         transform="fft", parts=True)
+    et, es = rel_parts(tau, rt, st), rel_parts(sig, rs, ss)
+    print("N=262144 stress: relative to the larger part", et, es, "plain", rel(tau, rt), rel(sig, rs))
+    assert et < 1e-5 and es < 1e-5, (et, es)
+
+
+def test_batch_of_full_size_faults_matches_individual_plans_bitwise():
+    from sbiem_inputs import ensemble_members
+    pkg = _pkg()
+    ws = ensemble_members("ensemble16-N262144")[:2]
+    a = [_workload_plan_and_oracle(w, 1)[0] for w in ws]
+    b = [_workload_plan_and_oracle(w, 1)[0] for w in ws]
+    batch = pkg.Batch(a)
+    batch.run(18)
+    for p, w in zip(b, ws):
+        p.run(w.dt, 18)
+    for pa, pb in zip(a, b):
         ga, gb = pa.get_state(), pb.get_state()
         for k in ("slip", "V", "theta", "tau_el", "sigma_el"):
             assert np.array_equal(ga[k], gb[k]), k

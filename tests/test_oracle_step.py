@@ -97,3 +97,25 @@ def test_time_step_is_second_order(overstress, theta_mode, nts, lo, hi):
     e2 = np.abs(fs[1].slip - fs[2].slip).max()
     order = np.log2(e1 / e2)
     assert lo < order < hi, (e1, e2, order)
+
+
+def test_fft_transform_and_short_weights_reproduce_the_naive_oracle():
+    """The large-N configuration of the oracle (numpy FFT as the transform,
+    weights kept only for the lags a short run reaches) takes the same steps
+    as the explicit-DFT, full-window oracle."""
+    N, L = 64, 10e3
+    spec = FrictionSpec(overstress=4e6, w_nuc=800.0)
+    fr = friction_fields(N, L, MU, CS, spec)
+    dt = 0.5 * L / N / CS
+    h = rough_fault(N, L, 5e-3, 2)
+    ref = OracleFault(N, L, MU, CS, CP, dt=dt, friction=fr, h=h, theta_mode="exp")
+    fast = OracleFault(N, L, MU, CS, CP, dt=dt, friction=fr, h=h, theta_mode="exp",
+                       transform="fft", max_lag=12)
+    for _ in range(12):
+        ref.step()
+        fast.step()
+    for a, b in ((ref.slip, fast.slip), (ref.V, fast.V), (ref.tau_el, fast.tau_el),
+                 (ref.sigma_el, fast.sigma_el)):
+        assert np.max(np.abs(a - b)) <= 1e-11 * np.max(np.abs(a))
+    with pytest.raises(ValueError):
+        fast.step()

@@ -7,7 +7,7 @@ import scipy.signal
 
 from oracle.bruteforce import stress_bruteforce
 from oracle.kernels import kernels_mp
-from oracle.spectral import curvature, dft, idft, wavenumbers
+from oracle.spectral import curvature, curvature_fft, dft, fft_dft, fft_idft_real, idft, idft_real, wavenumbers
 from oracle.stress import stress_from_history
 from oracle.windows import midpoint_weights, window_steps
 
@@ -193,3 +193,30 @@ def test_bruteforce_space_time_matches_spectral_functional():
     tb, sb = stress_bruteforce(hist, dt, L, MU, CS, CP, kap, w)
     assert np.abs(tau - tb).max() < 1e-12 * np.abs(tau).max()
     assert np.abs(sig - sb).max() < 1e-12 * np.abs(sig).max()
+
+
+def test_fft_transforms_match_the_explicit_sums():
+    rng = np.random.default_rng(11)
+    for N in (8, 64, 1024, 8192):
+        f = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+        F = dft(f)
+        assert np.max(np.abs(fft_dft(f) - F)) <= 1e-12 * np.max(np.abs(F))
+        g = rng.standard_normal(N)
+        G = dft(g)
+        assert np.max(np.abs(fft_idft_real(G) - idft_real(G))) <= 1e-12 * np.max(np.abs(g))
+        h = np.cumsum(rng.standard_normal(N))
+        k = curvature(h, 1e3)
+        assert np.max(np.abs(curvature_fft(h, 1e3) - k)) <= 1e-11 * np.max(np.abs(k))
+
+
+def test_stress_with_fft_and_short_weights_matches_explicit_sums():
+    N, L, dt, nt = 64, 10e3, 0.5 * 10e3 / 64 / CS, 9
+    rng = np.random.default_rng(5)
+    hist = np.cumsum(rng.standard_normal((nt + 1, N)) * 1e-3, axis=0)
+    kappa = curvature(1e-3 * L * np.sin(2 * np.pi * 3 * np.arange(N) / N), L)
+    w_full = midpoint_weights(N, L, CS, CP, dt)
+    w_short = midpoint_weights(N, L, CS, CP, dt, max_lag=nt)
+    t1, s1 = stress_from_history(hist, dt, L, MU, CS, CP, kappa, w_full)
+    t2, s2 = stress_from_history(hist, dt, L, MU, CS, CP, kappa, w_short, transform="fft")
+    assert np.max(np.abs(t1 - t2)) <= 1e-12 * np.max(np.abs(t1))
+    assert np.max(np.abs(s1 - s2)) <= 1e-12 * np.max(np.abs(s1))
