@@ -59,8 +59,10 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
   for (int f = 0; f < ex->nfaults; ++f) {
     DtData* d = dts[f];
     const int base = (int)tiles.size();
+    const size_t rec_bytes = precision == SBIEM_FP32CONV ? 16 : 32;
     for (Tile t : d->tiles) {
       t.fault = f;
+      t.rec = (const char*)d->ring + (size_t)t.ring_off * rec_bytes;
       tiles.push_back(t);
     }
     for (ConvTask k : d->tasks) tasks.push_back(ConvTask{k.t0 + base, k.t1 + base});
@@ -103,7 +105,9 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
   ex->d_tasks = (ConvTask*)ex->mem.get(sizeof(ConvTask) * std::max(1, ex->ntasks));
   ex->d_mode_map = (int2*)ex->mem.get(sizeof(int2) * std::max(1, ex->mode_blocks));
   ex->d_elem_map = (int2*)ex->mem.get(sizeof(int2) * std::max(1, ex->elem_blocks));
-  if (!ex->d_faults || !ex->d_tiles || !ex->d_tasks || !ex->d_mode_map || !ex->d_elem_map) {
+  ex->conv_ctr = (int*)ex->mem.get(sizeof(int) * 2);
+  if (!ex->d_faults || !ex->d_tiles || !ex->d_tasks || !ex->d_mode_map || !ex->d_elem_map ||
+      !ex->conv_ctr) {
     *err = "device allocation of the execution context failed";
     delete ex;
     return SBIEM_ENOMEM;
@@ -118,6 +122,7 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
     e = hipMemcpy(ex->d_mode_map, mmap.data(), sizeof(int2) * ex->mode_blocks, hipMemcpyHostToDevice);
   if (!e)
     e = hipMemcpy(ex->d_elem_map, emap.data(), sizeof(int2) * ex->elem_blocks, hipMemcpyHostToDevice);
+  if (!e) e = hipMemset(ex->conv_ctr, 0, sizeof(int) * 2);
   if (!e) e = setup_kernel_attributes(precision);
   if (!e) e = hipStreamCreateWithFlags(&ex->aux, hipStreamNonBlocking);
   if (!e) e = hipEventCreateWithFlags(&ex->fork, hipEventDisableTiming);

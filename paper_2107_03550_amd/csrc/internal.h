@@ -102,6 +102,8 @@ struct Tile {
   int pad0, pad1;
   long long ring_off;
   double th;       // FP32 weights: c_s |k_n| dt / 2 / table spacing
+  const void* rec; // the mode's first ring record (set per execution context)
+  long long pad2;
 };
 
 // A conv task: tiles [t0, t1) of one fault, handled by one workgroup.  A task
@@ -207,6 +209,7 @@ struct Exec {
   const float4* table = nullptr;  // FP32 kernel table (shared by all faults)
   int table_len = 0;
   int conv_grid = 0;
+  int* conv_ctr = nullptr;        // FP32 conv: dynamic task counter (zeroed by the mode launch after it)
   double conv_bytes = 0.0;        // algorithmic bytes per conv launch
   DevArena mem;
   hipGraphExec_t graph = nullptr;

@@ -269,74 +269,145 @@ k_conv64(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
 // argument of lag j is T = c_s |k_n| (j + 1/2) dt = (2j + 1) theta_n; the
 // table coordinate (2j + 1) theta_n / h is formed in FP64 so that the phase
 // keeps full accuracy at T ~ 200.
+//
+// Each wave of a workgroup task owns tiles k = wave and k = wave + 8.  The
+// records of the next task's tiles are requested as soon as the registers of
+// the current tile are free, so loads stay in flight across the weighting,
+// the wave reductions and the task's barriers.
+constexpr int kConvU = kTileSlots32 / 64;
+
+// The ring is streamed once per step: non-temporal loads keep it from
+// displacing the tables and spectra other launches reuse.
+typedef float f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void conv32_load(const Tile& tl, bool has, int lane, float4 (&h)[kConvU]) {
+  const float4* __restrict__ rec = (const float4*)tl.rec;
+  const int end = tl.p0 + tl.len;
+#pragma unroll
+  for (int u = 0; u < kConvU; ++u) {
+    const int p = tl.p0 + lane + 64 * u;
+    if (has && p < end) {
+      const f4v t = __builtin_nontemporal_load((const f4v*)(rec + p));
+      h[u] = make_float4(t.x, t.y, t.z, t.w);
+    } else {
+      h[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+}
+
+__device__ __forceinline__ float4 conv32_weigh(const Tile& tl, long long step, int lane,
+                                               const float4 (&h)[kConvU], const float4* tab,
+                                               int table_len) {
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  const int Rn = tl.Rn;
+  const int o = ring_phase(step, Rn);
+  const double th = tl.th;
+  const int end = tl.p0 + tl.len;
+#pragma unroll
+  for (int u = 0; u < kConvU; ++u) {
+    const int p = tl.p0 + lane + 64 * u;
+    int q = p + o;
+    q -= (q >= Rn) ? Rn : 0;
+    const int j = Rn - q + 1;                       // lag (q = 0: skipped slot)
+    const double x = (double)(2 * j + 1) * th;
+    const int i = min((int)x, table_len - 2);
+    const float f = (float)(x - (double)i);
+    const float4 n0 = tab[i], n1 = tab[i + 1];
+    const float f2 = f * f, f3 = f2 * f;
+    const float h00 = 2.f * f3 - 3.f * f2 + 1.f;
+    const float h10 = f3 - 2.f * f2 + f;
+    const float h01 = 3.f * f2 - 2.f * f3;
+    const float h11 = f3 - f2;
+    float wT = h00 * n0.x + h10 * n0.y + h01 * n1.x + h11 * n1.y;
+    float wN = h00 * n0.z + h10 * n0.w + h01 * n1.z + h11 * n1.w;
+    const bool use = (q != 0) && (p < end);
+    wT = use ? wT : 0.f;
+    wN = use ? wN : 0.f;
+    acc.x = fmaf(wT, h[u].x, acc.x);
+    acc.y = fmaf(wT, h[u].y, acc.y);
+    acc.z = fmaf(wN, h[u].z, acc.z);
+    acc.w = fmaf(wN, h[u].w, acc.w);
+  }
+  return acc;
+}
+
 __global__ void __launch_bounds__(kConvThreads)
 k_conv32(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
          const ConvTask* __restrict__ tasks, int ntasks, const float4* __restrict__ table,
-         int table_len, int ahead) {
-  constexpr int U = kTileSlots32 / 64;
+         int table_len, int ahead, int* __restrict__ ctr) {
   extern __shared__ float4 tab[];
   __shared__ TaskLds L;
-  for (int i = threadIdx.x; i < table_len; i += kConvThreads) tab[i] = table[i];
-  __syncthreads();
+  __shared__ int s_next;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wpb = kConvThreads / 64;
-  for (int task = blockIdx.x; task < ntasks; task += gridDim.x) {
-    const ConvTask tk = tasks[task];
+  // The first two tasks of a workgroup are blockIdx.x and blockIdx.x +
+  // gridDim.x; later ones come from an atomic counter (task 2 gridDim.x + c),
+  // fetched two ahead of the task being weighed, so a workgroup that starts
+  // late simply takes fewer tasks.  The counter is zeroed by the launch that
+  // consumes the sums (it runs after this one and before the next).
+  for (int i = threadIdx.x; i < table_len; i += kConvThreads) tab[i] = table[i];
+  __syncthreads();
+  int task = blockIdx.x;
+  int nxt = blockIdx.x + gridDim.x;
+  const int dyn0 = 2 * gridDim.x;
+  ConvTask tk = task < ntasks ? tasks[task] : ConvTask{0, 0};
+  Tile tA = {}, tB = {};
+  bool hasA = task < ntasks && wave < tk.t1 - tk.t0;
+  bool hasB = task < ntasks && wave + wpb < tk.t1 - tk.t0;
+  if (hasA) tA = tiles[tk.t0 + wave];
+  if (hasB) tB = tiles[tk.t0 + wave + wpb];
+  float4 hA[kConvU], hB[kConvU];
+  conv32_load(tA, hasA, lane, hA);
+  conv32_load(tB, hasB, lane, hB);
+  while (task < ntasks) {
+    int after = 0;
+    if (threadIdx.x == 0 && nxt < ntasks) after = dyn0 + atomicAdd(ctr, 1);  // returns while the tiles are weighed
+    if (nxt >= ntasks) after = ntasks;
     const int nt = tk.t1 - tk.t0;
     const FaultDev& fd = faults[tiles[tk.t0].fault];
     const int err = *fd.err;
     const long long step = *fd.step + ahead;
-    for (int k = wave; k < nt; k += wpb) {
-      const Tile tl = tiles[tk.t0 + k];
-      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (err == 0) {
-        const int Rn = tl.Rn;
-        const int o = ring_phase(step, Rn);
-        const double th = tl.th;
-        const float4* __restrict__ ring = (const float4*)fd.ring + tl.ring_off;
-        const int end = tl.p0 + tl.len;
-        float4 h[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int p = tl.p0 + lane + 64 * u;
-          h[u] = p < end ? ring[p] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int p = tl.p0 + lane + 64 * u;
-          int q = p + o;
-          q -= (q >= Rn) ? Rn : 0;
-          const int j = Rn - q + 1;                       // lag (q = 0: skipped slot)
-          const double x = (double)(2 * j + 1) * th;
-          const int i = min((int)x, table_len - 2);
-          const float f = (float)(x - (double)i);
-          const float4 n0 = tab[i], n1 = tab[i + 1];
-          const float f2 = f * f, f3 = f2 * f;
-          const float h00 = 2.f * f3 - 3.f * f2 + 1.f;
-          const float h10 = f3 - 2.f * f2 + f;
-          const float h01 = 3.f * f2 - 2.f * f3;
-          const float h11 = f3 - f2;
-          float wT = h00 * n0.x + h10 * n0.y + h01 * n1.x + h11 * n1.y;
-          float wN = h00 * n0.z + h10 * n0.w + h01 * n1.z + h11 * n1.w;
-          const bool use = (q != 0) && (p < end);
-          wT = use ? wT : 0.f;
-          wN = use ? wN : 0.f;
-          acc.x = fmaf(wT, h[u].x, acc.x);
-          acc.y = fmaf(wT, h[u].y, acc.y);
-          acc.z = fmaf(wN, h[u].z, acc.z);
-          acc.w = fmaf(wN, h[u].w, acc.w);
-        }
-      }
+    // next task's tiles
+    const ConvTask nk = nxt < ntasks ? tasks[nxt] : ConvTask{0, 0};
+    const bool nA = nxt < ntasks && wave < nk.t1 - nk.t0;
+    const bool nB = nxt < ntasks && wave + wpb < nk.t1 - nk.t0;
+    Tile uA = {}, uB = {};
+    if (nA) uA = tiles[nk.t0 + wave];
+    if (nB) uB = tiles[nk.t0 + wave + wpb];
+    if (hasA) {
+      float4 acc = err ? make_float4(0.f, 0.f, 0.f, 0.f) : conv32_weigh(tA, step, lane, hA, tab, table_len);
+      conv32_load(uA, nA, lane, hA);  // registers free: next task's records
       acc = wave_reduce4(acc);
       if (lane == 0) {
-        L.part[k] = make_double4(acc.x, acc.y, acc.z, acc.w);
-        L.id[k] = tl.part;
+        L.part[wave] = make_double4(acc.x, acc.y, acc.z, acc.w);
+        L.id[wave] = tA.part;
       }
+    } else {
+      conv32_load(uA, nA, lane, hA);
     }
+    if (hasB) {
+      float4 acc = err ? make_float4(0.f, 0.f, 0.f, 0.f) : conv32_weigh(tB, step, lane, hB, tab, table_len);
+      conv32_load(uB, nB, lane, hB);
+      acc = wave_reduce4(acc);
+      if (lane == 0) {
+        L.part[wave + wpb] = make_double4(acc.x, acc.y, acc.z, acc.w);
+        L.id[wave + wpb] = tB.part;
+      }
+    } else {
+      conv32_load(uB, nB, lane, hB);
+    }
+    if (threadIdx.x == 0) s_next = after;  // written and read between the two barriers
     __syncthreads();
     finish_task(fd, L, nt);
+    const int after_all = s_next;
     __syncthreads();
+    task = nxt;
+    nxt = after_all;
+    tk = nk;
+    hasA = nA;
+    hasB = nB;
+    tA = uA;
+    tB = uB;
   }
 }
 
@@ -618,7 +689,7 @@ template <typename R, int KIND>
 __global__ void __launch_bounds__(kModeThreads)
 k_modes(const FaultDev* __restrict__ faults, const int2* __restrict__ map, int measure,
         const void* __restrict__ gF_in, double2* __restrict__ outA, double2* __restrict__ outB,
-        long long stride_out) {
+        long long stride_out, int* __restrict__ conv_ctr) {
   using C = typename Prec<R>::C;
   using Rec = typename Prec<R>::Rec;
   extern __shared__ unsigned char smem_raw[];
@@ -675,6 +746,9 @@ k_modes(const FaultDev* __restrict__ faults, const int2* __restrict__ map, int m
     red[0] = kNoExp;
     red[1] = kNoExp;
   }
+  // the conv launch whose sums this launch consumes has finished: zero its
+  // task counter for the next one
+  if ((KIND == 0 || KIND == 2) && conv_ctr && blockIdx.x == 0 && threadIdx.x == 0) *conv_ctr = 0;
   if (err) return;
   __syncthreads();
   C* X = bufA;
@@ -1232,9 +1306,10 @@ hipError_t setup_kernel_attributes(int precision) {
 int conv_grid_size(int precision, int ntasks, int table_len) {
   int need = ntasks;
   if (precision == SBIEM_FP32CONV) {
-    // persistent: a few workgroups per CU amortise the LDS table load
+    // persistent: as many workgroups as are resident at once (LDS table and
+    // registers allow two per CU), so no workgroup waits for a slot
     const int per_cu = (int)(kMaxLdsBytes / ((size_t)table_len * sizeof(float4) + 1024));
-    const int cap = 256 * (per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu));
+    const int cap = 256 * (per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu));
     return need < cap ? (need < 1 ? 1 : need) : cap;
   }
   return need < 1 ? 1 : need;
@@ -1245,7 +1320,7 @@ hipError_t launch_conv(const Exec& ex, int ahead, hipStream_t s) {
   if (ex.precision == SBIEM_FP32CONV) {
     const size_t lds = (size_t)ex.table_len * sizeof(float4);
     hipLaunchKernelGGL(k_conv32, dim3(ex.conv_grid), dim3(kConvThreads), lds, s, ex.d_faults,
-                       ex.d_tiles, ex.d_tasks, ex.ntasks, ex.table, ex.table_len, ahead);
+                       ex.d_tiles, ex.d_tasks, ex.ntasks, ex.table, ex.table_len, ahead, ex.conv_ctr);
   } else {
     hipLaunchKernelGGL(k_conv64, dim3(ex.conv_grid), dim3(kConvThreads), 0, s, ex.d_faults,
                        ex.d_tiles, ex.d_tasks, ex.ntasks, ahead);
@@ -1261,15 +1336,15 @@ static void modes_kind(const Exec& ex, int kind, int measure, hipStream_t s) {
   switch (kind) {
     case 0:
       k_modes<R, 0><<<grid, block, lds, s>>>(ex.d_faults, map, measure, nullptr, nullptr,
-                                              nullptr, 0);
+                                              nullptr, 0, ex.conv_ctr);
       break;
     case 1:
       k_modes<R, 1><<<grid, block, lds, s>>>(ex.d_faults, map, 0, nullptr, nullptr,
-                                              nullptr, 0);
+                                              nullptr, 0, nullptr);
       break;
     default:
       k_modes<R, 2><<<grid, block, lds, s>>>(ex.d_faults, map, 0, nullptr, nullptr,
-                                              nullptr, 0);
+                                              nullptr, 0, ex.conv_ctr);
       break;
   }
 }
@@ -1306,10 +1381,12 @@ hipError_t launch_forward(const FaultDev* d_fault, const FaultDev& h, int precis
   const size_t el = elem_lds_bytes(precision, h.log2P, h.ncls), ml = mode_lds_bytes(precision, h.log2Q);
   if (precision == SBIEM_FP32CONV) {
     k_elems<float, 3><<<eg, dim3(kElemThreads), el, s>>>(d_fault, nullptr, a, gF);
-    k_modes<float, 3><<<mg, dim3(kModeThreads), ml, s>>>(d_fault, nullptr, 0, gF, A, B, stride_out);
+    k_modes<float, 3><<<mg, dim3(kModeThreads), ml, s>>>(d_fault, nullptr, 0, gF, A, B, stride_out,
+                                                          nullptr);
   } else {
     k_elems<double, 3><<<eg, dim3(kElemThreads), el, s>>>(d_fault, nullptr, a, gF);
-    k_modes<double, 3><<<mg, dim3(kModeThreads), ml, s>>>(d_fault, nullptr, 0, gF, A, B, stride_out);
+    k_modes<double, 3><<<mg, dim3(kModeThreads), ml, s>>>(d_fault, nullptr, 0, gF, A, B, stride_out,
+                                                           nullptr);
   }
   return hipGetLastError();
 }
