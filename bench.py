@@ -77,6 +77,27 @@ def cpu_baseline(w, fr, budget_s: float):
     }
 
 
+def train_closure(pkg):
+    """Networks of the learned closure, trained on the GPU (untimed) on pairs
+    from plain runs of seamount-N8192 and of the ensemble64 members with
+    N <= 4096 (2000 steps each, sampled every 50)."""
+    from paper_2107_03550_amd.closure_train import collect_pairs, train_networks
+    from sbiem_inputs import ensemble_members, workload
+    t0 = time.perf_counter()
+    sm = workload("seamount-N8192")
+    p, _ = build_plan(sm, pkg)
+    pairs = collect_pairs([p], sm.dt, 2000, 50)
+    small = [m for m in ensemble_members("ensemble64") if m.N <= 4096][:8]
+    plans = [build_plan(m, pkg)[0] for m in small]
+    more = collect_pairs(plans, small[0].dt, 2000, 50, batch=pkg.Batch(plans))
+    pairs = [(np.concatenate([a[0], b[0]]), np.concatenate([a[1], b[1]])) for a, b in zip(pairs, more)]
+    pT, pN, lT, lN = train_networks(pairs, steps=3000, batch=2048, lr=2e-3)
+    info = {"pairs": [int(len(x)) for x, _ in pairs], "final_loss": [float(lT[-50:].mean()),
+            float(lN[-50:].mean())], "target_variance": [float(y.var(0).sum()) for _, y in pairs],
+            "seconds": round(time.perf_counter() - t0, 1)}
+    return pT, pN, info
+
+
 def traffic_from_profiles(workload: str):
     """HBM bytes per conv launch from committed rocprofv3 counter summaries,
     if they were taken on the current kernel source."""
@@ -98,6 +119,12 @@ def main():
     ap.add_argument("--workload", default="seamount-N8192")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy (torch.neg, MIB MiB read and written, "
+                         "10 launches): the known-size kernel that scales the HBM counters")
+    ap.add_argument("--closure", action="store_true",
+                    help="time the learned-closure form (networks trained first, untimed, on "
+                         "plain runs of seamount-N8192 and ensemble64 members)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -113,25 +140,41 @@ def main():
         print("bench.py: no GPU", file=sys.stderr)
         sys.exit(1)
     stream = torch.cuda.current_stream()
-    if args.workload in ENSEMBLES:
-        # an ensemble: one batch of independent faults, stepped together
-        members = ensemble_members(args.workload)
-        plans = []
-        for m in members:
-            p, _ = build_plan(m, pkg)
-            p.set_stream(stream.cuda_stream)
-            plans.append(p)
-        runner = pkg.Batch(plans)
-        w = members[0]
-        n_total = sum(m.N for m in members)
-        run = runner.run
-    else:
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.randn(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read": 4 * n, "bytes_written": 4 * n,
+                                               "launches": 10, "kernel": "torch.neg (elementwise)"}}))
+        return
+    nets = train_closure(pkg) if args.closure else None
+
+    def make_runner(with_closure):
+        if args.workload in ENSEMBLES:
+            # an ensemble: one batch of independent faults, stepped together
+            members = ensemble_members(args.workload)
+            plans = []
+            for m in members:
+                p, _ = build_plan(m, pkg)
+                p.set_stream(stream.cuda_stream)
+                if with_closure:
+                    p.set_closure(nets[0], nets[1], 0.25)
+                plans.append(p)
+            r = pkg.Batch(plans)
+            return r, members, r.run, plans, None
         w = workload(args.workload)
-        runner, fr = build_plan(w, pkg)
-        runner.set_stream(stream.cuda_stream)
-        n_total = w.N
-        members = [w]
-        run = lambda k: runner.run(w.dt, k)  # noqa: E731
+        r, fr = build_plan(w, pkg)
+        r.set_stream(stream.cuda_stream)
+        if with_closure:
+            r.set_closure(nets[0], nets[1], 0.25)
+        return r, [w], (lambda k: r.run(w.dt, k)), [r], fr
+
+    runner, members, run, plans, fr = make_runner(args.closure)
+    w = members[0]
+    n_total = sum(m.N for m in members)
 
     run(args.warmup)
     torch.cuda.synchronize()
@@ -166,6 +209,33 @@ def main():
         "bytes_per_launch": conv_bytes, "avg_launch_us": round(avg_ms * 1e3, 3),
         "launches": conv_n,
     }
+    closure_info = None
+    if args.closure:
+        # the plain form on the same workload (graph replay) and the closure's
+        # stress error against it after the same steps from the same state
+        plain, _, prun, pplans, _ = make_runner(False)
+        prun(args.warmup)
+        torch.cuda.synchronize()
+        q0 = time.perf_counter()
+        prun(args.steps)
+        torch.cuda.synchronize()
+        q1 = time.perf_counter()
+        plain_value = n_total * args.steps / (q1 - q0)
+        err_tau = err_v = 0.0
+        steps_done = args.warmup + 2 * args.steps   # the closure run did warmup + two timed runs
+        prun(steps_done - (args.warmup + args.steps))
+        torch.cuda.synchronize()
+        for pc, pp in zip(plans, pplans):
+            gc, gp = pc.get_state(), pp.get_state()
+            err_tau = max(err_tau, float(np.max(np.abs(gc["tau_el"] - gp["tau_el"])) /
+                                   max(np.max(np.abs(gp["tau_el"])), 1e-300)))
+            err_v = max(err_v, float(np.max(np.abs(gc["V"] - gp["V"])) / np.max(np.abs(gp["V"]))))
+        closure_info = {"plain_graph_replay_value": plain_value,
+                        "speedup_vs_plain": graph_value / plain_value,
+                        "tau_el_rel_err_vs_plain": err_tau, "V_rel_err_vs_plain": err_v,
+                        "compared_after_steps": steps_done,
+                        "training": nets[2]}
+
     cpu = None
     if not args.no_cpu and args.workload not in ENSEMBLES and w.N <= 16384:
         cpu = cpu_baseline(w, fr, args.cpu_seconds)
@@ -180,11 +250,14 @@ def main():
                    "L_m": w.L if len(members) == 1 else "10 N m" if args.workload == "ensemble64"
                    else w.L, "dt_s": w.dt,
                    "precision": "fp32 convolution/FFT, fp64 friction" if w.precision != "fp64"
-                   else "fp64", "window": "full (plain)", "faults": len(members)},
+                   else "fp64", "window": "learned closure (1/4 window)" if args.closure
+                   else "full (plain)", "faults": len(members)},
         "graph_replay_value": graph_value,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if closure_info is not None:
+        out["closure"] = closure_info
     print(json.dumps(out))
 
 

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define SBIEM_ABI_VERSION 1
+#define SBIEM_ABI_VERSION 2
 
 typedef struct sbiem_plan sbiem_plan;
 typedef struct sbiem_batch sbiem_batch;
@@ -225,6 +225,57 @@ int sbiem_batch_run(sbiem_batch* b, int64_t nsteps);
 int sbiem_batch_set_profiling(sbiem_batch* b, int on);
 int sbiem_batch_profile(sbiem_batch* b, double* conv_ms, int64_t* conv_launches,
                         double* conv_bytes_per_launch);
+
+/* ---------------------------------------------------------------------------
+ * Learned tail closure.  Not part of the paper: it shortens the history
+ * window of section 3.1 and predicts the part of the convolution that falls
+ * beyond the cut.  With cut c, a mode n keeps M'_n = ceil(c M_n) lags when
+ * 18 <= M'_n < M_n (other modes keep their whole window); the tail
+ *   tail^X_n = sum_{j=M'_n}^{M_n-1} w^X_{n,j} H^X_n(lag j),  X = shear, normal,
+ * is predicted by one network per kind: input (33 values) T_cut/100 with
+ * T_cut = c_s |k_n| M'_n dt, then the 16 oldest kept values
+ * H(lag M'_n-16+k), k = 0..15, as (Re, Im) pairs divided by their RMS r;
+ * output y (2 values) with tail = (y_0 + i y_1) r / (c_s |k_n|).  Layers
+ * 33 -> 64 -> 64 -> 2, GELU (erf form) after the first two.
+ * Parameters: SBIEM_CLOSURE_PARAMS floats in the order W1[33][64], b1[64],
+ * W2[64][64], b2[64], W3[64][2], b3[2] (row = input), h1 = gelu(x W1 + b1),
+ * h2 = gelu(h1 W2 + b2), y = h2 W3 + b3.  Inference uses bfloat16 weights and
+ * layer inputs with float32 accumulation (matrix cores); training float32.
+ * ------------------------------------------------------------------------- */
+#define SBIEM_CLOSURE_PARAMS 6466
+
+/* Enable the closure on a SBIEM_FP32CONV plan with the shear and normal
+ * networks (host, SBIEM_CLOSURE_PARAMS floats each, copied) and cut
+ * 0 < c < 1 (0.25: a quarter of each window); both NULL disables it.  With a
+ * time step already set, the tables and ring are rebuilt as by
+ * sbiem_set_dt: the state is kept and the history restarts.  EINVAL for
+ * FP64 plans, non-finite parameters or a plan used by a batch. */
+int sbiem_set_closure(sbiem_plan* p, const float* params_shear, const float* params_normal,
+                      double cut);
+
+/* Training pairs from the current history of a plain SBIEM_FP32CONV plan
+ * (whole windows, state and dt set): for every mode n = 1..N/2 that cut c
+ * would close and both kinds (0 shear, 1 normal), the network input
+ * X[kind][n][33], the target Y[kind][n][2] = exact tail c_s |k_n| / r
+ * (complex as two floats; the tail uses the FP32 convolution weights) and
+ * the scale R[kind][n] = r.  Rows of modes that stay open, and rows with
+ * r = 0, are zero.  X, Y, R: host, 2 (N/2+1) rows, written. */
+int sbiem_closure_sample(sbiem_plan* p, double cut, float* X, float* Y, double* R);
+
+/* Evaluate one network on n inputs X[n][33] (host) with the matrix-core
+ * inference kernel; Y[n][2] (host) written. */
+int sbiem_closure_eval(const float* params, const float* X, int64_t n, float* Y);
+
+/* Adam training of one network on the device (float32): `steps` updates on
+ * minibatches of `batch` rows of (X[n][33], Y[n][2]); update k uses rows
+ * (t_k batch + i) mod n, i < batch, with t_k the number of updates so far
+ * (*adam_t on entry plus k).  Loss: mean over the batch of sum_o (y_o - Y_o)^2.
+ * Adam with beta1 0.9, beta2 0.999, eps 1e-8 and step size lr.  params,
+ * adam_m, adam_v (SBIEM_CLOSURE_PARAMS floats each) and adam_t are updated
+ * in place; losses[steps] (may be NULL) receives each update's loss. */
+int sbiem_closure_train(const float* X, const float* Y, int64_t n, int64_t batch, int64_t steps,
+                        double lr, float* params, float* adam_m, float* adam_v, int64_t* adam_t,
+                        double* losses);
 
 #ifdef __cplusplus
 }

@@ -55,10 +55,12 @@ class OracleFault:
 
     def __init__(self, N, L, mu, cs, cp, *, dt, friction, h=None, kappa=None,
                  table: KernelTable | None = None, theta_mode="paper",
-                 transform="naive", max_lag=None):
+                 transform="naive", max_lag=None, closure=None):
         """``transform``: "naive" (explicit DFT sums) or "fft" (numpy FFT);
         ``max_lag``: keep only window lags below it, which limits the run to
-        max_lag steps from the state set (longer runs raise)."""
+        max_lag steps from the state set (longer runs raise); ``closure``:
+        (params_T, params_N, cut) to keep ceil(cut M_n) lags and close the
+        tail with the networks of ``oracle.closure`` (bfloat16 inference)."""
         self.N, self.L, self.mu, self.cs, self.cp, self.dt = N, L, mu, cs, cp, dt
         self._fwd, self._inv = transforms(transform)
         self.max_lag = max_lag
@@ -79,8 +81,14 @@ class OracleFault:
         self.V_pl = float(f["V_pl"])
         self.eta_rad = mu / (2.0 * cs)
         self.theta_mode = theta_mode
-        # history of lags j = 1..M_n-1, newest first, flat per mode
+        # history of lags j = 1..M_n-1 (M'_n - 1 with the closure), newest
+        # first, flat per mode
         M = self.w.M
+        self.closure = closure
+        if closure is not None:
+            from .closure import kept_lags
+            self.M_kept, self.closed = kept_lags(M, closure[2])
+            M = self.M_kept
         self.hM = np.maximum(M - 1, 0)
         self.hoff = np.concatenate([[0], np.cumsum(self.hM)[:-1]]).astype(np.int64)
         tot = int(self.hM.sum())
@@ -117,12 +125,84 @@ class OracleFault:
         self.nsteps = 0
 
     def history_sums(self):
-        """S^X_n = sum_{j>=1} w^X_{n,j} H^X_n(lag j)."""
+        """S^X_n = sum_{j>=1} w^X_{n,j} H^X_n(lag j) (plus the closed tail)."""
         ST = np.bincount(self._hist_mode, weights=(self._wT_hist * self.HT).real, minlength=self.N) \
             + 1j * np.bincount(self._hist_mode, weights=(self._wT_hist * self.HT).imag, minlength=self.N)
         SN = np.bincount(self._hist_mode, weights=(self._wN_hist * self.HN).real, minlength=self.N) \
             + 1j * np.bincount(self._hist_mode, weights=(self._wN_hist * self.HN).imag, minlength=self.N)
+        if self.closure is not None:
+            tT, tN = self.closure_tails()
+            ST = ST + tT
+            SN = SN + tN
         return ST, SN
+
+    def history_at(self, n, lag, kind):
+        """Stored history value of spectral index n at lag (1..hM[n])."""
+        H = self.HT if kind == 0 else self.HN
+        return H[self.hoff[n] + lag - 1]
+
+    def _closure_inputs(self, n, kind, Mk):
+        from .closure import features
+        H = self.HT if kind == 0 else self.HN
+        lags = np.zeros(Mk, dtype=np.complex128)
+        lags[1:Mk] = H[self.hoff[n]:self.hoff[n] + Mk - 1]
+        Tcut = self.cs * self.kabs[n] * Mk * self.dt
+        return features(lags, Mk, Tcut)
+
+    def closure_tails(self):
+        """Network tails of the closed modes n = 1..N/2, mirrored as complex
+        conjugates to N - n (so the spectra stay Hermitian)."""
+        from .closure import forward, tail_from_output
+        pT, pN, _ = self.closure
+        tails = [np.zeros(self.N, dtype=np.complex128), np.zeros(self.N, dtype=np.complex128)]
+        modes = [n for n in range(1, self.N // 2 + 1) if self.closed[n]]
+        for kind, params in ((0, pT), (1, pN)):
+            if not modes:
+                continue
+            xs, rs = zip(*(self._closure_inputs(n, kind, int(self.M_kept[n])) for n in modes))
+            y = forward(params, np.array(xs), bf16_inputs=True)
+            for row, n in enumerate(modes):
+                if rs[row] > 0:
+                    t = tail_from_output(y[row], rs[row], self.cs * self.kabs[n])
+                    if n == self.N - n:
+                        t = t.real      # the Nyquist coefficient of a real signal is real
+                    tails[kind][n] = t
+                    if n != self.N - n:
+                        tails[kind][self.N - n] = np.conj(t)
+        return tails
+
+    def closure_samples(self, cut=0.25):
+        """Training pairs from the full (plain) history: for every mode
+        n = 1..N/2 that the closure would cut and both kinds, the network
+        input x, the scale r and the target output (the exact tail scaled as
+        the network's output).  Returns dict(x, y, r, mode, kind, tail)."""
+        from .closure import features, kept_lags, target_from_tail
+        if self.closure is not None:
+            raise ValueError("samples need the plain (full-window) history")
+        Mk, use = kept_lags(self.w.M, cut)
+        xs, ys, rs, ms, ks, ts = [], [], [], [], [], []
+        for kind in (0, 1):
+            H = self.HT if kind == 0 else self.HN
+            w = self.w.wT if kind == 0 else self.w.wN
+            for n in range(1, self.N // 2 + 1):
+                if not use[n]:
+                    continue
+                M, mk = int(self.w.M[n]), int(Mk[n])
+                lags = np.zeros(M, dtype=np.complex128)
+                lags[1:M] = H[self.hoff[n]:self.hoff[n] + M - 1]
+                tail = np.dot(w[self.w.off[n] + mk:self.w.off[n] + M], lags[mk:M])
+                x, r = features(lags, mk, self.cs * self.kabs[n] * mk * self.dt)
+                if r == 0:
+                    continue
+                xs.append(x)
+                ys.append(target_from_tail(tail, r, self.cs * self.kabs[n]))
+                rs.append(r)
+                ms.append(n)
+                ks.append(kind)
+                ts.append(tail)
+        return dict(x=np.array(xs).reshape(-1, 33), y=np.array(ys).reshape(-1, 2), r=np.array(rs),
+                    mode=np.array(ms, dtype=np.int64), kind=np.array(ks, dtype=np.int64),
+                    tail=np.array(ts, dtype=np.complex128))
 
     def tractions(self, slip_p, V_c, t_new, ST, SN):
         """Elastic tau, sigma at t_new for predicted slip and current rate V_c."""

@@ -33,8 +33,10 @@ SBIEM_FP64 = 0
 SBIEM_FP32CONV = 1
 SBIEM_THETA_PAPER = 0
 SBIEM_THETA_EXP = 1
+CLOSURE_PARAMS = 6466
 
 _D = ctypes.POINTER(ctypes.c_double)
+_F = ctypes.POINTER(ctypes.c_float)
 _I64 = ctypes.POINTER(ctypes.c_int64)
 _VP = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -74,6 +76,10 @@ _SIGS = {
     "sbiem_batch_run": (_int, [_VP, _i64]),
     "sbiem_batch_set_profiling": (_int, [_VP, _int]),
     "sbiem_batch_profile": (_int, [_VP, _D, _I64, _D]),
+    "sbiem_set_closure": (_int, [_PLAN, _F, _F, _dbl]),
+    "sbiem_closure_sample": (_int, [_PLAN, _dbl, _F, _F, _D]),
+    "sbiem_closure_eval": (_int, [_F, _F, _i64, _F]),
+    "sbiem_closure_train": (_int, [_F, _F, _i64, _i64, _i64, _dbl, _F, _F, _F, _I64, _D]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -117,6 +123,45 @@ def kernel_eval(T, cs, cp):
     outs = [np.empty(T.size) for _ in range(4)]
     _check(lib.sbiem_kernel_eval(cs, cp, _ptr(T), T.size, *[_ptr(o) for o in outs]))
     return tuple(outs)
+
+
+def _f32(x, n=None, name="array"):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    if n is not None and a.size != n:
+        raise ValueError(f"{name}: expected {n} values, got {a.size}")
+    return a
+
+
+def _fptr(a):
+    return None if a is None else a.ctypes.data_as(_F)
+
+
+def closure_eval(params, X):
+    """Network outputs (n, 2) for inputs X (n, 33) by the matrix-core kernel."""
+    p = _f32(params, CLOSURE_PARAMS, "params")
+    X = _f32(X).reshape(-1, 33)
+    Y = np.empty((X.shape[0], 2), dtype=np.float32)
+    _check(lib.sbiem_closure_eval(_fptr(p), _fptr(X), X.shape[0], _fptr(Y)))
+    return Y
+
+
+class ClosureTrainer:
+    """Adam state of one network trained by sbiem_closure_train."""
+
+    def __init__(self, params):
+        self.params = _f32(params, CLOSURE_PARAMS, "params").copy()
+        self.m = np.zeros(CLOSURE_PARAMS, dtype=np.float32)
+        self.v = np.zeros(CLOSURE_PARAMS, dtype=np.float32)
+        self.t = ctypes.c_int64(0)
+
+    def train(self, X, Y, batch, steps, lr):
+        X = _f32(X).reshape(-1, 33)
+        Y = _f32(Y).reshape(-1, 2)
+        losses = np.empty(int(steps))
+        _check(lib.sbiem_closure_train(_fptr(X), _fptr(Y), X.shape[0], int(batch), int(steps), lr,
+                                       _fptr(self.params), _fptr(self.m), _fptr(self.v),
+                                       ctypes.byref(self.t), losses.ctypes.data_as(_D)))
+        return losses
 
 
 _torch_alloc_refs = []
@@ -241,6 +286,24 @@ class Plan:
     def last_error(self):
         m = lib.sbiem_last_error(self.handle)
         return m.decode() if m else ""
+
+    def set_closure(self, params_shear, params_normal, cut=0.25):
+        """Learned tail closure on (None, None: off)."""
+        if params_shear is None:
+            self._c(lib.sbiem_set_closure(self.handle, None, None, cut))
+            return
+        a = _f32(params_shear, CLOSURE_PARAMS, "params_shear")
+        b = _f32(params_normal, CLOSURE_PARAMS, "params_normal")
+        self._c(lib.sbiem_set_closure(self.handle, _fptr(a), _fptr(b), cut))
+
+    def closure_sample(self, cut=0.25):
+        """(X[2][N/2+1][33], Y[2][N/2+1][2], R[2][N/2+1]) from the current history."""
+        h = self.N // 2 + 1
+        X = np.empty((2, h, 33), dtype=np.float32)
+        Y = np.empty((2, h, 2), dtype=np.float32)
+        R = np.empty((2, h))
+        self._c(lib.sbiem_closure_sample(self.handle, cut, _fptr(X), _fptr(Y), _ptr(R)))
+        return X, Y, R
 
 
 class Batch:

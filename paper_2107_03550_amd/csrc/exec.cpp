@@ -54,6 +54,17 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
   std::vector<Tile> tiles;
   std::vector<ConvTask> tasks;
   std::vector<int2> mmap, emap;
+  std::vector<ClosureMode> cmodes;
+  for (sbiem_plan* p : plans) {
+    if (p->closure_on != plans[0]->closure_on ||
+        (p->closure_on && (p->closure_params[0] != plans[0]->closure_params[0] ||
+                           p->closure_params[1] != plans[0]->closure_params[1] ||
+                           p->closure_cut != plans[0]->closure_cut))) {
+      *err = "batch members must share the closure setting and networks";
+      delete ex;
+      return SBIEM_EINVAL;
+    }
+  }
   double bytes = 0.0;
   const double rec = precision == SBIEM_FP32CONV ? 16.0 : 32.0;
   for (int f = 0; f < ex->nfaults; ++f) {
@@ -70,6 +81,10 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
     // (2 complex FP64) written per mode
     for (size_t n = 1; n < d->Rn.size(); ++n)
       if (d->Rn[n] > 1) bytes += rec * (d->Rn[n] - 1) + 32.0;
+    for (ClosureMode c : d->closure) {
+      c.fault = f;
+      cmodes.push_back(c);
+    }
     const FaultDev& fd = descs[f];
     for (int g = 0; g < fd.ngroups; ++g) mmap.push_back(make_int2(f, g));
     for (int b = 0; b < fd.Q; b += fd.ncls) emap.push_back(make_int2(f, b));
@@ -106,8 +121,23 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
   ex->d_mode_map = (int2*)ex->mem.get(sizeof(int2) * std::max(1, ex->mode_blocks));
   ex->d_elem_map = (int2*)ex->mem.get(sizeof(int2) * std::max(1, ex->elem_blocks));
   ex->conv_ctr = (int*)ex->mem.get(sizeof(int) * 2);
+  if (plans[0]->closure_on && !cmodes.empty()) {
+    ex->nclosure = (int)cmodes.size();
+    ex->closure_modes = (ClosureMode*)ex->mem.get(sizeof(ClosureMode) * cmodes.size());
+    for (int k = 0; k < 2; ++k) {
+      ex->net_frag[k] = plans[0]->net_frag[k];
+      ex->net_bias[k] = plans[0]->net_bias[k];
+    }
+    if (ex->closure_modes &&
+        hipMemcpy(ex->closure_modes, cmodes.data(), sizeof(ClosureMode) * cmodes.size(),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      *err = "uploading the closed modes failed";
+      delete ex;
+      return SBIEM_EDEVICE;
+    }
+  }
   if (!ex->d_faults || !ex->d_tiles || !ex->d_tasks || !ex->d_mode_map || !ex->d_elem_map ||
-      !ex->conv_ctr) {
+      !ex->conv_ctr || (ex->nclosure && !ex->closure_modes)) {
     *err = "device allocation of the execution context failed";
     delete ex;
     return SBIEM_ENOMEM;
@@ -293,6 +323,7 @@ hipError_t launch_step(Exec& ex, hipStream_t s, hipStream_t aux, bool profile, h
   if (!e && profile) e = hipEventRecord(e0, aux);
   if (!e) e = launch_conv(ex, 1, aux);
   if (!e && profile) e = hipEventRecord(e1, aux);
+  if (!e) e = launch_closure(ex, 1, aux);
   if (!e) e = hipEventRecord(ex.join, aux);
   if (!e) e = launch_elems(ex, 1, s);
   if (!e) e = launch_modes(ex, 1, 0, s);
@@ -314,6 +345,7 @@ hipError_t prologue(Exec& ex, hipStream_t s) {
   for (DynData* d : ex.dyns)
     if (!e) e = hipMemcpyAsync(d->cells, init, sizeof(init), hipMemcpyHostToDevice, s);
   if (!e) e = launch_conv(ex, 0, s);
+  if (!e) e = launch_closure(ex, 0, s);
   if (!e) e = launch_modes(ex, 0, 1, s);
   if (!e) e = launch_modes(ex, 0, 0, s);
   if (!e) e = hipStreamSynchronize(s);  // init lives on the host stack

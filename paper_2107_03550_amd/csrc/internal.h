@@ -44,6 +44,17 @@ __host__ __device__ inline int mode_pos(int n, int log2P, int log2Q) {
   return ((n & ((1 << log2P) - 1)) << (log2Q - 1)) + (n >> log2P);
 }
 
+// A mode whose window the learned closure cuts (see closure.hip).
+struct ClosureMode {
+  int fault, pm;      // fault (in the execution context), mode position
+  int Rn, Mk;         // kept ring capacity M'_n - 1, kept lags M'_n
+  long long ring_off; // first ring record of the mode
+  float tcut;         // c_s |k_n| M'_n dt / 100 (network input 0)
+  float pad;
+  double inv_csk;     // 1 / (c_s |k_n|)
+};
+constexpr int kClosureParams = 6466;  // 33*64 + 64 + 64*64 + 64 + 64*2 + 2
+
 // ---------------------------------------------------------------------------
 // Device-visible description of one fault at one time step.  One array of
 // these per execution context (a plan, a batch, a stress evaluation); the
@@ -82,6 +93,7 @@ struct FaultDev {
   // per mode (modes 0..N/2 at mode_pos)
   const ModeCoef* coef;
   double4* parts;               // conv partials: (S_T re, im, S_N re, im)
+  double4* tails;               // learned-closure tails (same layout), or null
 
   void* ring;                   // history records: float4 or 2 x double2 per slot
   const double2* wrev;          // FP64 weights per ring slot (see conv kernel)
@@ -166,6 +178,9 @@ struct DtData {
   void* ring = nullptr;
   double2* wrev = nullptr;
   float4* table = nullptr;       // FP32 kernel table: dt*(C^T, h C^T', C^N, h C^N')
+  std::vector<ClosureMode> closure;  // closed modes (fault field 0)
+  double4* tails = nullptr;          // closure tails at mode_pos (zero for open modes)
+  std::vector<double> th_mode;       // table coordinate step theta_n / h per mode
 };
 
 // Dynamic state of one fault.
@@ -210,6 +225,10 @@ struct Exec {
   int table_len = 0;
   int conv_grid = 0;
   int* conv_ctr = nullptr;        // FP32 conv: dynamic task counter (zeroed by the mode launch after it)
+  ClosureMode* closure_modes = nullptr;  // closed modes of every fault (null: no closure)
+  int nclosure = 0;
+  const void* net_frag[2] = {nullptr, nullptr};  // closure networks (shear, normal)
+  const float* net_bias[2] = {nullptr, nullptr};
   double conv_bytes = 0.0;        // algorithmic bytes per conv launch
   DevArena mem;
   hipGraphExec_t graph = nullptr;
@@ -256,6 +275,14 @@ struct sbiem_plan {
   sbiem::EventPool events;
   int last_fail_count = 0, last_fail_index = -1;
   int batch_refs = 0;
+
+  // learned closure (FP32 convolution only)
+  bool closure_on = false;
+  double closure_cut = 0.25;
+  std::vector<float> closure_params[2];  // shear, normal networks (host copies)
+  sbiem::DevArena closure_mem;
+  void* net_frag[2] = {nullptr, nullptr};
+  float* net_bias[2] = {nullptr, nullptr};
 };
 
 struct sbiem_batch {
@@ -310,6 +337,12 @@ hipError_t launch_fill_ring(const FaultDev* d_fault, int precision, int nmodes,
                             const double2* RV, const double2* RG, int nint, hipStream_t s);
 hipError_t launch_rates(const double* hist, double* rates, long long count, long long N, double dt,
                         hipStream_t s);
+// closure.hip: tails of every closed mode (for the step the conv sums are for)
+hipError_t launch_closure(const Exec& ex, int ahead, hipStream_t s);
+// fragment-ordered bfloat16 weights and float32 biases of one network
+void closure_pack(const float* params, std::vector<unsigned short>* frag, std::vector<float>* bias);
+// kept lags M' = ceil(cut M) of a window of M lags, or M when the mode stays open
+int closure_kept(int M, double cut);
 int conv_grid_size(int precision, int ntasks, int table_len);
 hipError_t setup_kernel_attributes(int precision);
 size_t mode_lds_bytes(int precision, int log2Q);

@@ -611,13 +611,14 @@ __device__ __forceinline__ int2 work_item(const int2* __restrict__ map) {
 struct ModeIn {
   ModeCoef cf;
   double2 v0, gv0, v1, gv1, u, gg, hv, hg, BT, BN;
-  double4 S0;  // first conv partial
+  double4 S0;  // first conv partial plus the learned-closure tail (if any)
 };
 
 // Per-mode arrays of a fault (read from the descriptor once per launch).
 struct ModePtrs {
   const ModeCoef* coef;
   double4* parts;
+  const double4* tails;
   double2 *u, *g, *v0, *gv0, *v1, *gv1, *hv, *hg, *BT, *BN;
 };
 
@@ -625,6 +626,7 @@ __device__ __forceinline__ ModePtrs mode_ptrs(const FaultDev& fd) {
   ModePtrs m;
   m.coef = fd.coef;
   m.parts = fd.parts;
+  m.tails = fd.tails;
   m.u = fd.u_hat;
   m.g = fd.g_hat;
   m.v0 = fd.v_hat0;
@@ -647,6 +649,13 @@ __device__ __forceinline__ void load_mode_in(const ModePtrs& f, int pm, ModeIn& 
     m.u = f.u[pm];
     m.gg = f.g[pm];
     m.S0 = f.parts[pm];
+    if (f.tails) {
+      const double4 t = f.tails[pm];
+      m.S0.x += t.x;
+      m.S0.y += t.y;
+      m.S0.z += t.z;
+      m.S0.w += t.w;
+    }
   }
   if (KIND == 0) {
     m.hv = f.hv[pm];
@@ -774,7 +783,9 @@ k_modes(const FaultDev* __restrict__ faults, const int2* __restrict__ map, int m
     const ModeCoef& cf = in.cf;
     double4 S = in.S0;
     if (KIND != 1) {
-      if (cf.nparts == 0) S = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (cf.nparts == 0) {  // no ring records: only a closure tail (none for such modes)
+        S = make_double4(0.0, 0.0, 0.0, 0.0);
+      }
       for (int j = 1; j < cf.nparts; ++j) {  // further pieces of a long window
         const double4 b = mp.parts[cf.part0 + j - 1];
         S.x += b.x;

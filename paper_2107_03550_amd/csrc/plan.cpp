@@ -160,6 +160,11 @@ std::vector<int> window_steps(int64_t N, double L, double cs, double dt) {
   return M;
 }
 
+int closure_kept(int M, double cut) {
+  const int Mk = (int)std::ceil(cut * M - 1e-9);
+  return (Mk >= 18 && Mk < M) ? Mk : M;
+}
+
 int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
   *out = nullptr;
   DtData* d = new DtData();
@@ -171,7 +176,9 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
   d->ring_off.assign(half + 1, 0);
   long long slots = 0;
   for (int n = 1; n <= half; ++n) {
-    d->Rn[n] = d->M[n] - 1;
+    // the learned closure keeps M'_n lags of the modes it closes
+    const int kept = p->closure_on ? closure_kept(d->M[n], p->closure_cut) : d->M[n];
+    d->Rn[n] = kept - 1;
     d->ring_off[n] = slots;
     slots += d->Rn[n];
   }
@@ -252,6 +259,27 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
   hipError_t e = hipSuccess;
   hipStream_t s = p->stream;
   d->coef = upload(d->mem, coef, s, &e);
+  d->th_mode.assign(half + 1, 0.0);
+  for (int n = 0; n <= half; ++n) d->th_mode[n] = (double)(th_unit * n);
+  if (!e && p->closure_on) {
+    for (int n = 1; n <= half; ++n) {
+      if (d->Rn[n] + 1 == d->M[n]) continue;  // open mode
+      ClosureMode c;
+      c.fault = 0;
+      c.pm = mode_pos(n, p->log2P, p->log2Q);
+      c.Rn = d->Rn[n];
+      c.Mk = d->Rn[n] + 1;
+      c.ring_off = d->ring_off[n];
+      const double csk = p->cs * 2.0 * M_PI * (double)n / p->L;
+      c.tcut = (float)(csk * c.Mk * dt / 100.0);
+      c.pad = 0.f;
+      c.inv_csk = 1.0 / csk;
+      d->closure.push_back(c);
+    }
+    d->tails = (double4*)d->mem.get(sizeof(double4) * (half + 1));
+    if (!d->tails) e = hipErrorOutOfMemory;
+    else e = hipMemsetAsync(d->tails, 0, sizeof(double4) * (half + 1), s);
+  }
   if (!e) {
     d->parts = (double4*)d->mem.get(sizeof(double4) * std::max(1, parts));
     if (!d->parts) e = hipErrorOutOfMemory;
@@ -287,7 +315,7 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
     // Hermite table on T = i h covering every lag (plus the skipped slot).
     double Tmax = 0.0;
     for (int n = 1; n <= half; ++n)
-      Tmax = std::max(Tmax, (double)(theta_unit * n) * (2.0 * d->M[n] + 3.0));
+      Tmax = std::max(Tmax, (double)(theta_unit * n) * (2.0 * (d->Rn[n] + 1) + 3.0));
     const int K = (int)std::ceil(Tmax / kTableStep) + 3;
     if ((size_t)K * sizeof(float4) > (size_t)kMaxDynLds) {
       e = hipErrorInvalidValue;
@@ -442,6 +470,7 @@ FaultDev make_fault_desc(sbiem_plan* p, DtData* dtd, DynData* dyn, double V_pl, 
   if (dtd) {
     f.coef = dtd->coef;
     f.parts = dtd->parts;
+    f.tails = dtd->tails;
     f.ring = dtd->ring;
     f.wrev = dtd->wrev;
   }
@@ -795,6 +824,55 @@ int sbiem_set_dt(sbiem_plan* p, double dt) {
   if (int st = reset_history(p)) return st;
   if (p->state_set) return spectral_state_from_device(p);
   return SBIEM_OK;
+}
+
+int sbiem_set_closure(sbiem_plan* p, const float* params_shear, const float* params_normal,
+                      double cut) {
+  if (int s = check_plan(p)) return s;
+  const bool on = params_shear != nullptr;
+  if (on != (params_normal != nullptr))
+    return fail(p, SBIEM_EINVAL, "set_closure: give both networks or neither");
+  if (on && p->precision != SBIEM_FP32CONV)
+    return fail(p, SBIEM_EINVAL, "set_closure: the closure runs with SBIEM_FP32CONV");
+  if (on && !(cut > 0.0 && cut < 1.0)) return fail(p, SBIEM_EINVAL, "set_closure: need 0 < cut < 1");
+  if (p->batch_refs > 0) return fail(p, SBIEM_EINVAL, "set_closure: plan is used by a batch");
+  if (on) {
+    for (int k = 0; k < 2; ++k) {
+      const float* src = k ? params_normal : params_shear;
+      for (int i = 0; i < kClosureParams; ++i)
+        if (!std::isfinite(src[i])) return fail(p, SBIEM_EINVAL, "set_closure: parameters must be finite");
+    }
+  }
+  if (int s = ensure_device(p)) return s;
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e) return hip_fail(p, e, "set_closure");
+  p->closure_mem.release_all();
+  p->net_frag[0] = p->net_frag[1] = nullptr;
+  p->net_bias[0] = p->net_bias[1] = nullptr;
+  p->closure_on = on;
+  if (on) {
+    p->closure_cut = cut;
+    for (int k = 0; k < 2; ++k) {
+      const float* src = k ? params_normal : params_shear;
+      p->closure_params[k].assign(src, src + kClosureParams);
+      std::vector<unsigned short> frag;
+      std::vector<float> bias;
+      closure_pack(src, &frag, &bias);
+      p->net_frag[k] = p->closure_mem.get(frag.size() * sizeof(unsigned short));
+      p->net_bias[k] = (float*)p->closure_mem.get(bias.size() * sizeof(float));
+      if (!p->net_frag[k] || !p->net_bias[k]) return fail(p, SBIEM_ENOMEM, "set_closure: device allocation failed");
+      e = hipMemcpy(p->net_frag[k], frag.data(), frag.size() * sizeof(unsigned short), hipMemcpyHostToDevice);
+      if (!e) e = hipMemcpy(p->net_bias[k], bias.data(), bias.size() * sizeof(float), hipMemcpyHostToDevice);
+      if (e) return hip_fail(p, e, "set_closure");
+    }
+  } else {
+    p->closure_params[0].clear();
+    p->closure_params[1].clear();
+  }
+  if (!p->dtd) return refresh_desc(p);
+  // new window lengths: rebuild the tables and ring like a new dt (the state
+  // is kept, the history restarts)
+  return sbiem_set_dt(p, p->dtd->dt);
 }
 
 int sbiem_set_stream(sbiem_plan* p, void* hip_stream) {

@@ -1,0 +1,137 @@
+"""GPU parity of the learned tail closure against the oracle (oracle/closure.py
+and the closure hooks of the oracle stepper), through the C ABI.
+
+The network arithmetic is compared with the oracle's: inference (bfloat16
+weights and layer inputs, float32 accumulation, emulated by the oracle),
+training (float32 Adam against the FP64 reference with its finite-difference
+pinned gradients), training pairs sampled from a plain run, and whole steps
+with the closure on.  How much the closure gains over simply cutting the
+window is measured on the GPU alone (GPU-trained networks never enter the
+oracle)."""
+
+import numpy as np
+import pytest
+
+from oracle import closure as cl
+from scenarios import CS, CP, MU, NU, Scenario, fields, make_plan, rel, rel_parts, rough_10km
+from sbiem_inputs import FrictionSpec
+
+pytestmark = pytest.mark.gpu
+
+
+def _pkg():
+    import paper_2107_03550_amd as pkg
+    return pkg
+
+
+def _inputs(n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, 33))
+    X[:, 0] = rng.uniform(0.0, 0.6, n)
+    return X
+
+
+def _params(seed, noise=0.05, out_scale=1.0):
+    rng = np.random.default_rng(seed)
+    p = cl.init_params(seed) + noise * rng.standard_normal(cl.N_PARAMS)
+    p[cl.N_PARAMS - 130:] *= out_scale      # W3, b3: size of the network's output
+    return p
+
+
+def test_inference_kernel_matches_bf16_reference():
+    pkg = _pkg()
+    p = _params(1)
+    X = _inputs(1000, 2)
+    Xf = X.astype(np.float32)
+    y = pkg.closure_eval(p.astype(np.float32), Xf)
+    p32 = p.astype(np.float32).astype(np.float64)
+    ref = cl.forward(p32, Xf.astype(np.float64), bf16_inputs=True)
+    exact = cl.forward(p32, Xf.astype(np.float64))
+    err = np.abs(y - ref)
+    print("inference vs bf16 reference: max", err.max() / np.abs(ref).max(), "median",
+          np.median(err) / np.abs(ref).max(), "; bf16 vs float64 network", rel(ref, exact))
+    assert err.max() <= 5e-3 * np.abs(ref).max()
+    assert np.median(err) <= 1e-5 * np.abs(ref).max()
+
+
+def test_training_matches_fp64_adam():
+    pkg = _pkg()
+    rng = np.random.default_rng(4)
+    X = _inputs(300, 5)
+    Y = rng.standard_normal((300, 2)) * 0.5
+    p0 = _params(6).astype(np.float32)
+    tr = pkg.ClosureTrainer(p0)
+    losses = tr.train(X, Y, batch=64, steps=5, lr=1e-3)
+    # reference: the same updates in FP64 from the same float32 inputs
+    p, m, v, t, ref_losses = cl.adam_steps(p0.astype(np.float64), np.zeros(cl.N_PARAMS),
+                                           np.zeros(cl.N_PARAMS), 0,
+                                           X.astype(np.float32).astype(np.float64),
+                                           Y.astype(np.float32).astype(np.float64), 64, 5, 1e-3)
+    assert tr.t.value == 5 == t
+    assert np.max(np.abs(losses - ref_losses)) <= 1e-5 * np.max(ref_losses)
+    # one Adam step moves a parameter by about lr sign(g): float32 rounding
+    # decides the sign only where g is at rounding level, so compare robustly
+    d = np.abs(tr.params - p)
+    print("adam: parameters off by > 1e-5:", np.mean(d > 1e-5), "median", np.median(d))
+    assert np.mean(d > 1e-5) < 1e-3 and np.median(d) < 1e-7
+    # continuing the run continues the minibatch cycle
+    losses2 = tr.train(X, Y, batch=64, steps=3, lr=1e-3)
+    p, m, v, t, ref2 = cl.adam_steps(p, m, v, t, X.astype(np.float32).astype(np.float64),
+                                     Y.astype(np.float32).astype(np.float64), 64, 3, 1e-3)
+    assert np.max(np.abs(losses2 - ref2)) <= 1e-5 * np.max(ref2)
+
+
+def _rupture(N=256, seed=2):
+    L = 10e3
+    return Scenario(N, L, 0.5 * (L / N) / CS, rough_10km(N, seed=seed, alpha=3e-3),
+                    spec=FrictionSpec(overstress=9e6, w_nuc=800.0), theta_mode="exp",
+                    consistent_V0=True)
+
+
+def test_training_pairs_match_oracle():
+    from oracle.stepper import OracleFault
+    pkg = _pkg()
+    sc = _rupture()
+    p = make_plan(sc, pkg.SBIEM_FP32CONV)
+    o = OracleFault(sc.N, sc.L, MU, CS, CP, dt=sc.dt, friction=fields(sc), h=sc.h,
+                    theta_mode=sc.theta_mode, transform="fft")
+    p.run(sc.dt, 150)
+    o.run(150)
+    X, Y, R = p.closure_sample(0.25)
+    smp = o.closure_samples(0.25)
+    gx = X[smp["kind"], smp["mode"]]
+    gy = Y[smp["kind"], smp["mode"]]
+    gr = R[smp["kind"], smp["mode"]]
+    assert np.count_nonzero(R) == len(smp["mode"]) > 100
+    assert rel(gr, smp["r"]) < 1e-5
+    assert np.max(np.abs(gx - smp["x"])) < 1e-4
+    ey = np.abs(gy - smp["y"]).max() / np.abs(smp["y"]).max()
+    print("training pairs: targets", ey)
+    assert ey < 1e-4
+
+
+def test_step_with_closure_matches_oracle():
+    """Closure-on steps against the oracle with the same networks.  The
+    networks are untrained with outputs scaled to the size of a real tail
+    (large random tails drive the rupture unstably and amplify the bfloat16
+    rounding differences of the network inputs step after step)."""
+    from oracle.stepper import OracleFault
+    pkg = _pkg()
+    sc = _rupture(N=256, seed=7)
+    pT, pN = _params(11, 0.02, 0.05), _params(12, 0.02, 0.05)
+    p = make_plan(sc, pkg.SBIEM_FP32CONV)
+    p.set_closure(pT.astype(np.float32), pN.astype(np.float32), 0.25)
+    o = OracleFault(sc.N, sc.L, MU, CS, CP, dt=sc.dt, friction=fields(sc), h=sc.h,
+                    theta_mode=sc.theta_mode, transform="fft",
+                    closure=(pT.astype(np.float32).astype(np.float64),
+                             pN.astype(np.float32).astype(np.float64), 0.25))
+    worst = {"tau_el": 0.0, "sigma_el": 0.0, "V": 0.0}
+    for _ in range(6):
+        p.run(sc.dt, 40)
+        o.run(40)
+        g = p.get_state()
+        worst["tau_el"] = max(worst["tau_el"], rel_parts(g["tau_el"], o.tau_el, o.tau_static))
+        worst["sigma_el"] = max(worst["sigma_el"], rel_parts(g["sigma_el"], o.sigma_el, o.sigma_static))
+        worst["V"] = max(worst["V"], rel(g["V"], o.V))
+    print("closure step vs oracle", worst)
+    assert worst["tau_el"] < 1e-4 and worst["sigma_el"] < 1e-4, worst
