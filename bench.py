@@ -8,9 +8,10 @@ rough-N65536, ensemble16-N262144 (ensembles run as one batch).
 One "step" is the whole two-pass time step (history convolution, FFTs,
 traction assembly, friction solve, commit) of the named workload with its
 inputs resident in HBM.  Prints one JSON line with element-steps/s, the
-roofline position of the history-convolution kernel (HIP events around each
-of its launches in the timed region) and the CPU oracle timed on a bounded
-sample of the same workload.
+roofline position of the history-convolution kernel (HIP events around its
+launches in one step of every 17 of the timed region, the others replayed
+from the step graph) and the CPU oracle timed on a bounded sample of the
+same workload.
 """
 
 from __future__ import annotations
@@ -179,8 +180,9 @@ def main():
     run(args.warmup)
     torch.cuda.synchronize()
 
-    # timed region: K steps; every conv launch bracketed by HIP events on the
-    # stream the conv kernel is launched on
+    # timed region: K steps; one step in every 17 launched directly with its
+    # conv launch bracketed by HIP events on the stream the conv kernel is
+    # launched on, the others replayed from the step graph
     runner.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

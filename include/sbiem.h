@@ -203,8 +203,10 @@ int sbiem_kernel_eval(double cs, double cp, const double* T, int64_t n, double* 
                       double* CN, double* dCT, double* dCN);
 
 /* Per-launch timing of the history-convolution kernel with HIP events on
- * the plan's stream.  While on, sbiem_run replays steps without a graph so
- * that each launch is bracketed.  sbiem_profile returns the accumulated
+ * the stream it runs on.  While on, sbiem_run launches one step in every 17
+ * directly, its convolution bracketed by two events, and replays the other
+ * steps from the step graph (results are identical either way).
+ * sbiem_profile returns the accumulated
  * milliseconds and launch count, the algorithmic bytes one launch reads
  * and writes (ring records of lags 2..M_n-1, partial sums) and resets the
  * counters. */
@@ -235,7 +237,11 @@ int sbiem_batch_profile(sbiem_batch* b, double* conv_ms, int64_t* conv_launches,
  * is predicted by one network per kind: input (33 values) T_cut/100 with
  * T_cut = c_s |k_n| M'_n dt, then the 16 oldest kept values
  * H(lag M'_n-16+k), k = 0..15, as (Re, Im) pairs divided by their RMS r;
- * output y (2 values) with tail = (y_0 + i y_1) r / (c_s |k_n|).  Layers
+ * output y (2 values), a correction to the constant extrapolation of the
+ * oldest kept value a_15 = H(lag M'_n-1) over the discarded lags:
+ *   tail = D^X_n a_15 + (y_0 + i y_1) r / (c_s |k_n|),
+ *   D^X_n = sum_{j=M'_n}^{M_n-1} w^X_{n,j}  (computed by the library).
+ * A zero network therefore gives the constant extrapolation.  Layers
  * 33 -> 64 -> 64 -> 2, GELU (erf form) after the first two.
  * Parameters: SBIEM_CLOSURE_PARAMS floats in the order W1[33][64], b1[64],
  * W2[64][64], b2[64], W3[64][2], b3[2] (row = input), h1 = gelu(x W1 + b1),
@@ -256,7 +262,7 @@ int sbiem_set_closure(sbiem_plan* p, const float* params_shear, const float* par
 /* Training pairs from the current history of a plain SBIEM_FP32CONV plan
  * (whole windows, state and dt set): for every mode n = 1..N/2 that cut c
  * would close and both kinds (0 shear, 1 normal), the network input
- * X[kind][n][33], the target Y[kind][n][2] = exact tail c_s |k_n| / r
+ * X[kind][n][33], the target Y[kind][n][2] = (exact tail - D a_15) c_s |k_n| / r
  * (complex as two floats; the tail uses the FP32 convolution weights) and
  * the scale R[kind][n] = r.  Rows of modes that stay open, and rows with
  * r = 0, are zero.  X, Y, R: host, 2 (N/2+1) rows, written. */

@@ -14,7 +14,14 @@ differences and by the identities in ``tests/test_oracle_closure.py``.
 Network input (33 reals): T_cut / 100 with T_cut = c_s |k_n| M'_n dt, then
 the 16 oldest kept history values a_k = H^X_n(lag M'_n - 16 + k),
 k = 0..15, as (Re, Im) pairs divided by their RMS r = sqrt(mean |a_k|^2).
-Output (2 reals) y: tail = (y_0 + i y_1) r / (c_s |k_n|).  Hidden layers
+Output (2 reals) y, a correction to the constant extrapolation of the
+oldest kept value a_15 over the discarded lags:
+
+    tail = D^X_n a_15 + (y_0 + i y_1) r / (c_s |k_n|),
+    D^X_n = sum_{j = M'_n}^{M_n - 1} w^X_{n,j}.
+
+With y = 0 the closure is exact for a history that stays constant beyond
+the kept window.  Hidden layers
 2 x 64 with the erf form of GELU.  Parameters (6466 reals, this order):
 W1[33][64], b1[64], W2[64][64], b2[64], W3[64][2], b3[2], with
 h1 = gelu(x W1 + b1), h2 = gelu(h1 W2 + b2), y = h2 W3 + b3.
@@ -165,12 +172,23 @@ def features(H_lags, Mk, Tcut):
     return x, r
 
 
-def tail_from_output(y, r, cs_k):
-    """tail = (y_0 + i y_1) r / (c_s |k_n|)."""
-    return (y[..., 0] + 1j * y[..., 1]) * r / cs_k
+def discarded_weight(w_mode, Mk, M):
+    """D = sum of the weights of the discarded lags Mk .. M-1 (``w_mode[j]``
+    is the weight of lag j)."""
+    return float(np.sum(np.asarray(w_mode, dtype=np.float64)[Mk:M]))
 
 
-def target_from_tail(tail, r, cs_k):
-    """The output a perfect network would give: tail c_s |k_n| / r."""
-    z = tail * cs_k / r
+def oldest_kept(x, r):
+    """a_15, the oldest kept history value, from the network input."""
+    return (x[..., 31] + 1j * x[..., 32]) * r
+
+
+def tail_from_output(y, r, cs_k, D, a_old):
+    """tail = D a_15 + (y_0 + i y_1) r / (c_s |k_n|)."""
+    return D * a_old + (y[..., 0] + 1j * y[..., 1]) * r / cs_k
+
+
+def target_from_tail(tail, r, cs_k, D, a_old):
+    """The output a perfect network would give: (tail - D a_15) c_s |k_n| / r."""
+    z = (tail - D * a_old) * cs_k / r
     return np.stack([z.real, z.imag], axis=-1)

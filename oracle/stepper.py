@@ -152,7 +152,7 @@ class OracleFault:
     def closure_tails(self):
         """Network tails of the closed modes n = 1..N/2, mirrored as complex
         conjugates to N - n (so the spectra stay Hermitian)."""
-        from .closure import forward, tail_from_output
+        from .closure import discarded_weight, forward, oldest_kept, tail_from_output
         pT, pN, _ = self.closure
         tails = [np.zeros(self.N, dtype=np.complex128), np.zeros(self.N, dtype=np.complex128)]
         modes = [n for n in range(1, self.N // 2 + 1) if self.closed[n]]
@@ -161,9 +161,13 @@ class OracleFault:
                 continue
             xs, rs = zip(*(self._closure_inputs(n, kind, int(self.M_kept[n])) for n in modes))
             y = forward(params, np.array(xs), bf16_inputs=True)
+            w = self.w.wT if kind == 0 else self.w.wN
             for row, n in enumerate(modes):
                 if rs[row] > 0:
-                    t = tail_from_output(y[row], rs[row], self.cs * self.kabs[n])
+                    o, Mk = self.w.off[n], int(self.M_kept[n])
+                    D = discarded_weight(w[o:o + self.w.M[n]], Mk, int(self.w.M[n]))
+                    t = tail_from_output(y[row], rs[row], self.cs * self.kabs[n], D,
+                                         oldest_kept(xs[row], rs[row]))
                     if n == self.N - n:
                         t = t.real      # the Nyquist coefficient of a real signal is real
                     tails[kind][n] = t
@@ -176,7 +180,7 @@ class OracleFault:
         n = 1..N/2 that the closure would cut and both kinds, the network
         input x, the scale r and the target output (the exact tail scaled as
         the network's output).  Returns dict(x, y, r, mode, kind, tail)."""
-        from .closure import features, kept_lags, target_from_tail
+        from .closure import discarded_weight, features, kept_lags, target_from_tail
         if self.closure is not None:
             raise ValueError("samples need the plain (full-window) history")
         Mk, use = kept_lags(self.w.M, cut)
@@ -194,8 +198,9 @@ class OracleFault:
                 x, r = features(lags, mk, self.cs * self.kabs[n] * mk * self.dt)
                 if r == 0:
                     continue
+                D = discarded_weight(w[self.w.off[n]:self.w.off[n] + M], mk, M)
                 xs.append(x)
-                ys.append(target_from_tail(tail, r, self.cs * self.kabs[n]))
+                ys.append(target_from_tail(tail, r, self.cs * self.kabs[n], D, lags[mk - 1]))
                 rs.append(r)
                 ms.append(n)
                 ks.append(kind)

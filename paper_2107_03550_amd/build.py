@@ -3,7 +3,8 @@
     python -m paper_2107_03550_amd.build          # or build() from Python
 
 Every source under csrc/ is compiled with hipcc for gfx950 only, with packed
-FP32 instructions disabled, then linked into paper_2107_03550_amd/lib/.
+FP32 instructions and the backend's atomic combining disabled, then linked
+into paper_2107_03550_amd/lib/.
 """
 
 from __future__ import annotations
@@ -27,6 +28,10 @@ ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-x", "hip",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # atomics stay single instructions: the convolution's task counter is
+    # fetched by one lane and its value is used only after the tiles are
+    # weighed, so the wait for it must not be pulled up to the fetch
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]

@@ -171,10 +171,15 @@ __global__ void __launch_bounds__(256) k_closure(const FaultDev* __restrict__ fa
   mlp_wave(netT, xT, &yT0, &yT1);
   mlp_wave(netN, xN, &yN0, &yN1);
   if (q == 0 && valid && !err) {
+    // tail = D a_15 + y r / (c_s |k_n|), a_15 the oldest kept record (lag M'_n - 1)
+    long long p = (b - c.Mk + 2) % c.Rn;
+    if (p < 0) p += c.Rn;
+    const float4 a = ring[p];
     const double sT_ = (double)rT * c.inv_csk, sN_ = (double)rN * c.inv_csk;
     // the Nyquist coefficient of a real signal is real
     const double im = c.pm == fd.nmodes ? 0.0 : 1.0;
-    fd.tails[c.pm] = make_double4(yT0 * sT_, im * yT1 * sT_, yN0 * sN_, im * yN1 * sN_);
+    fd.tails[c.pm] = make_double4(c.dT * a.x + yT0 * sT_, im * (c.dT * a.y + yT1 * sT_),
+                                  c.dN * a.z + yN0 * sN_, im * (c.dN * a.w + yN1 * sN_));
   }
 }
 
@@ -186,6 +191,7 @@ struct SampleMode {
   int n, pm, M, Mk, Rn, pad;
   long long ring_off;
   double th, cs_k;
+  double dT, dN;  // sums of the discarded weights
   float tcut, pad2;
 };
 
@@ -255,7 +261,10 @@ __global__ void __launch_bounds__(256) k_closure_sample(const FaultDev* __restri
       x[1 + 2 * k] = r > 0 ? (float)(amp[k][2 * kind] / r) : 0.f;
       x[2 + 2 * k] = r > 0 ? (float)(amp[k][2 * kind + 1] / r) : 0.f;
     }
-    const double t0 = red[2 * kind][0], t1 = red[2 * kind + 1][0];
+    // target: (tail - D a_15) c_s |k_n| / r
+    const double D = kind ? s.dN : s.dT;
+    const double t0 = red[2 * kind][0] - D * amp[15][2 * kind];
+    const double t1 = red[2 * kind + 1][0] - D * amp[15][2 * kind + 1];
     Y[2 * row] = r > 0 ? (float)(t0 * s.cs_k / r) : 0.f;
     Y[2 * row + 1] = r > 0 ? (float)(t1 * s.cs_k / r) : 0.f;
     R[row] = r;
@@ -526,9 +535,18 @@ int sbiem_closure_sample(sbiem_plan* p, double cut, float* X, float* Y, double* 
   const int half = (int)(p->N / 2);
   const DtData* d = p->dtd;
   std::vector<SampleMode> list;
+  std::vector<int> ln, lMk, lM;
   for (int n = 1; n <= half; ++n) {
     const int Mk = closure_kept(d->M[n], cut);
     if (Mk == d->M[n] || d->Rn[n] + 1 != d->M[n]) continue;
+    ln.push_back(n);
+    lMk.push_back(Mk);
+    lM.push_back(d->M[n]);
+  }
+  std::vector<double> DT, DN;
+  discarded_weights(p->cs, p->cp, p->L, d->dt, ln, lMk, lM, &DT, &DN);
+  for (size_t i = 0; i < ln.size(); ++i) {
+    const int n = ln[i], Mk = lMk[i];
     SampleMode m;
     std::memset(&m, 0, sizeof(m));
     m.n = n;
@@ -540,6 +558,8 @@ int sbiem_closure_sample(sbiem_plan* p, double cut, float* X, float* Y, double* 
     m.th = d->th_mode[n];
     m.cs_k = p->cs * 2.0 * M_PI * (double)n / p->L;
     m.tcut = (float)(m.cs_k * Mk * d->dt / 100.0);
+    m.dT = DT[i];
+    m.dN = DN[i];
     list.push_back(m);
   }
   const size_t rows = 2 * (size_t)(half + 1);

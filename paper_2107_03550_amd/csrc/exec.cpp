@@ -114,7 +114,7 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
   ex->mode_blocks = (int)mmap.size();
   ex->elem_blocks = (int)emap.size();
   ex->conv_bytes = bytes;
-  ex->conv_grid = conv_grid_size(precision, ex->ntasks, ex->table_len);
+  ex->conv_grid = conv_grid_size(precision, ex->ntasks, ex->table_len, ex->conv_bytes);
   ex->d_faults = (FaultDev*)ex->mem.get(sizeof(FaultDev) * ex->nfaults);
   ex->d_tiles = (Tile*)ex->mem.get(sizeof(Tile) * std::max(1, ex->ntiles));
   ex->d_tasks = (ConvTask*)ex->mem.get(sizeof(ConvTask) * std::max(1, ex->ntasks));
@@ -384,11 +384,12 @@ hipError_t ensure_graph(Exec* ex, hipStream_t s) {
   return e;
 }
 
-// Run nsteps of an execution context on stream s.  While profiling, every
-// step is launched directly with a pair of events around its conv launch
-// (HIP graphs do not give usable times for event nodes; no host
-// synchronisation inside a chunk of steps); the elapsed times are summed
-// once the chunk has finished.
+// Run nsteps of an execution context on stream s.  While profiling, one
+// step in every kGraphSteps + 1 is launched directly with a pair of events
+// around its conv launch and the others are replayed from the step graph as
+// usual (HIP graphs do not give usable times for event nodes), so the timed
+// steps run at the graph's pace; no host synchronisation inside a chunk of
+// steps, the elapsed times are summed once the chunk has finished.
 hipError_t run_steps(Exec* ex, int64_t nsteps, hipStream_t s, bool profile, EventPool* pool,
                      double* prof_ms, int64_t* prof_launches, const char** what) {
   *what = "running the time steps";
@@ -397,18 +398,32 @@ hipError_t run_steps(Exec* ex, int64_t nsteps, hipStream_t s, bool profile, Even
   hipError_t e = prologue(*ex, s);
   if (e) return e;
   if (profile) {
-    const int64_t chunk = 8192;
-    for (int64_t done = 0; done < nsteps && !e; done += chunk) {
-      const int64_t n = std::min(chunk, nsteps - done);
+    if (nsteps > kGraphSteps) {
+      *what = "capturing the step graph";
+      e = ensure_graph(ex, s);
+      if (e) return e;
+    }
+    const int64_t chunk = 8192;  // timed steps per host synchronisation
+    int64_t left = nsteps;
+    while (left > 0 && !e) {
       *what = "creating timing events";
-      e = pool->ensure((size_t)(2 * n));
-      *what = "launching profiled steps";
-      for (int64_t k = 0; k < n && !e; ++k)
-        e = launch_step(*ex, s, ex->aux, true, pool->ev[2 * k], pool->ev[2 * k + 1]);
+      e = pool->ensure((size_t)(2 * chunk));
+      int64_t timed = 0;
+      while (left > 0 && timed < chunk && !e) {
+        *what = "launching profiled steps";
+        e = launch_step(*ex, s, ex->aux, true, pool->ev[2 * timed], pool->ev[2 * timed + 1]);
+        ++timed;
+        --left;
+        if (!e && left >= kGraphSteps) {
+          *what = "launching the step graph";
+          e = hipGraphLaunch(ex->graph, s);
+          left -= kGraphSteps;
+        }
+      }
       *what = "waiting for profiled steps";
       if (!e) e = hipStreamSynchronize(s);
       *what = "reading the timing events";
-      for (int64_t k = 0; k < n && !e; ++k) {
+      for (int64_t k = 0; k < timed && !e; ++k) {
         float ms = 0.f;
         e = hipEventElapsedTime(&ms, pool->ev[2 * k], pool->ev[2 * k + 1]);
         if (!e) {

@@ -52,6 +52,7 @@ struct ClosureMode {
   float tcut;         // c_s |k_n| M'_n dt / 100 (network input 0)
   float pad;
   double inv_csk;     // 1 / (c_s |k_n|)
+  double dT, dN;      // sums of the discarded weights, lags M'_n .. M_n - 1
 };
 constexpr int kClosureParams = 6466;  // 33*64 + 64 + 64*64 + 64 + 64*2 + 2
 
@@ -150,6 +151,11 @@ void dev_free(void* p);
 
 // Extended-precision kernel evaluation (kernel_eval.cpp).
 void bessel_jw(long double x, long double* J0, long double* J1, long double* W);
+// Sums of the weights dt C^T, dt C^N of lags Mk[i] .. M[i] - 1 of modes n[i]
+// (the lags a closure discards), cubic Hermite on T = i h in FP64.
+void discarded_weights(double cs, double cp, double L, double dt, const std::vector<int>& n,
+                       const std::vector<int>& Mk, const std::vector<int>& M, std::vector<double>* DT,
+                       std::vector<double>* DN);
 void kernel_values(long double T, long double cs, long double cp, long double* CT,
                    long double* CN, long double* dCT, long double* dCN);
 
@@ -343,7 +349,7 @@ hipError_t launch_closure(const Exec& ex, int ahead, hipStream_t s);
 void closure_pack(const float* params, std::vector<unsigned short>* frag, std::vector<float>* bias);
 // kept lags M' = ceil(cut M) of a window of M lags, or M when the mode stays open
 int closure_kept(int M, double cut);
-int conv_grid_size(int precision, int ntasks, int table_len);
+int conv_grid_size(int precision, int ntasks, int table_len, double bytes);
 hipError_t setup_kernel_attributes(int precision);
 size_t mode_lds_bytes(int precision, int log2Q);
 size_t elem_lds_bytes(int precision, int log2P, int ncls);

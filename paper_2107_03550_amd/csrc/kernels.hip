@@ -270,27 +270,42 @@ k_conv64(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
 // table coordinate (2j + 1) theta_n / h is formed in FP64 so that the phase
 // keeps full accuracy at T ~ 200.
 //
-// Each wave of a workgroup task owns tiles k = wave and k = wave + 8.  The
-// records of the next task's tiles are requested as soon as the registers of
-// the current tile are free, so loads stay in flight across the weighting,
-// the wave reductions and the task's barriers.
+// Each wave of a workgroup task owns tiles k = wave and k = wave + W (W
+// waves per workgroup).  The records of the next task's tiles are requested
+// as soon as the registers of the current tile are free, so loads stay in
+// flight across the weighting, the wave reductions and the task's barriers.
 constexpr int kConvU = kTileSlots32 / 64;
 
+// Per-fault words that a launch only reads (failure flag, step counter) are
+// read with scalar loads: the vector-memory counter then tracks record loads
+// alone, so waiting for these words never waits for records in flight.
+__device__ __forceinline__ int read_word(const int* p) {
+  return *(const __attribute__((address_space(4))) int*)p;
+}
+__device__ __forceinline__ long long read_word(const long long* p) {
+  return *(const __attribute__((address_space(4))) long long*)p;
+}
+
 // The ring is streamed once per step: non-temporal loads keep it from
-// displacing the tables and spectra other launches reuse.
+// displacing the tables and spectra other launches reuse.  Records are read
+// through a global-segment pointer (global loads wait on
+// the vector-memory counter only, so LDS reads of the table never wait for
+// records still in flight).  Lanes past the tile's end re-read its last
+// record (same cache line, no extra traffic); their weight is zero.  A wave
+// without a tile still issues its loads, from the first nodes of the table
+// (cached, never weighed): every pass of the task loop then issues the same
+// number of loads, so the wait for a tile's records counts exactly the loads
+// issued after them and never drains the next task's loads.
 typedef float f4v __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void conv32_load(const Tile& tl, bool has, int lane, float4 (&h)[kConvU]) {
-  const float4* __restrict__ rec = (const float4*)tl.rec;
-  const int end = tl.p0 + tl.len;
+typedef const __attribute__((address_space(1))) f4v* gf4p;
+__device__ __forceinline__ void conv32_load(const Tile& tl, bool has, int lane, const float4* dummy,
+                                            float4 (&h)[kConvU]) {
+  const gf4p rec = has ? (gf4p)(const float4*)tl.rec + tl.p0 : (gf4p)dummy;
+  const int last = has ? tl.len - 1 : 3;
 #pragma unroll
   for (int u = 0; u < kConvU; ++u) {
-    const int p = tl.p0 + lane + 64 * u;
-    if (has && p < end) {
-      const f4v t = __builtin_nontemporal_load((const f4v*)(rec + p));
-      h[u] = make_float4(t.x, t.y, t.z, t.w);
-    } else {
-      h[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    const f4v t = __builtin_nontemporal_load(rec + min(lane + 64 * u, last));
+    h[u] = make_float4(t.x, t.y, t.z, t.w);
   }
 }
 
@@ -345,8 +360,6 @@ k_conv32(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
   // fetched two ahead of the task being weighed, so a workgroup that starts
   // late simply takes fewer tasks.  The counter is zeroed by the launch that
   // consumes the sums (it runs after this one and before the next).
-  for (int i = threadIdx.x; i < table_len; i += kConvThreads) tab[i] = table[i];
-  __syncthreads();
   int task = blockIdx.x;
   int nxt = blockIdx.x + gridDim.x;
   const int dyn0 = 2 * gridDim.x;
@@ -356,50 +369,53 @@ k_conv32(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
   bool hasB = task < ntasks && wave + wpb < tk.t1 - tk.t0;
   if (hasA) tA = tiles[tk.t0 + wave];
   if (hasB) tB = tiles[tk.t0 + wave + wpb];
-  float4 hA[kConvU], hB[kConvU];
-  conv32_load(tA, hasA, lane, hA);
-  conv32_load(tB, hasB, lane, hB);
+  float4 hA[kConvU] = {}, hB[kConvU] = {};
+  conv32_load(tA, hasA, lane, table, hA);
+  conv32_load(tB, hasB, lane, table, hB);
+  // the table is staged while the first records are in flight
+  for (int i = threadIdx.x; i < table_len; i += kConvThreads) tab[i] = table[i];
+  __syncthreads();
   while (task < ntasks) {
-    int after = 0;
-    if (threadIdx.x == 0 && nxt < ntasks) after = dyn0 + atomicAdd(ctr, 1);  // returns while the tiles are weighed
-    if (nxt >= ntasks) after = ntasks;
+    const bool more = nxt < ntasks;
+    int got = 0;
+    if (threadIdx.x == 0 && more) got = atomicAdd(ctr, 1);  // used after the tiles are weighed
     const int nt = tk.t1 - tk.t0;
     const FaultDev& fd = faults[tiles[tk.t0].fault];
-    const int err = *fd.err;
-    const long long step = *fd.step + ahead;
+    const int err = read_word(fd.err);
+    const long long step = read_word(fd.step) + ahead;
     // next task's tiles
-    const ConvTask nk = nxt < ntasks ? tasks[nxt] : ConvTask{0, 0};
-    const bool nA = nxt < ntasks && wave < nk.t1 - nk.t0;
-    const bool nB = nxt < ntasks && wave + wpb < nk.t1 - nk.t0;
+    const ConvTask nk = more ? tasks[nxt] : ConvTask{0, 0};
+    const bool nA = more && wave < nk.t1 - nk.t0;
+    const bool nB = more && wave + wpb < nk.t1 - nk.t0;
     Tile uA = {}, uB = {};
     if (nA) uA = tiles[nk.t0 + wave];
     if (nB) uB = tiles[nk.t0 + wave + wpb];
+    // weigh a tile, then reuse its registers for the next task's records
+    float4 accA = make_float4(0.f, 0.f, 0.f, 0.f), accB = accA;
+    if (hasA && !err) accA = conv32_weigh(tA, step, lane, hA, tab, table_len);
+    __builtin_amdgcn_sched_barrier(0);
+    conv32_load(uA, nA, lane, table, hA);
+    if (hasB && !err) accB = conv32_weigh(tB, step, lane, hB, tab, table_len);
+    __builtin_amdgcn_sched_barrier(0);
+    conv32_load(uB, nB, lane, table, hB);
     if (hasA) {
-      float4 acc = err ? make_float4(0.f, 0.f, 0.f, 0.f) : conv32_weigh(tA, step, lane, hA, tab, table_len);
-      conv32_load(uA, nA, lane, hA);  // registers free: next task's records
-      acc = wave_reduce4(acc);
+      accA = wave_reduce4(accA);
       if (lane == 0) {
-        L.part[wave] = make_double4(acc.x, acc.y, acc.z, acc.w);
+        L.part[wave] = make_double4(accA.x, accA.y, accA.z, accA.w);
         L.id[wave] = tA.part;
       }
-    } else {
-      conv32_load(uA, nA, lane, hA);
     }
     if (hasB) {
-      float4 acc = err ? make_float4(0.f, 0.f, 0.f, 0.f) : conv32_weigh(tB, step, lane, hB, tab, table_len);
-      conv32_load(uB, nB, lane, hB);
-      acc = wave_reduce4(acc);
+      accB = wave_reduce4(accB);
       if (lane == 0) {
-        L.part[wave + wpb] = make_double4(acc.x, acc.y, acc.z, acc.w);
+        L.part[wave + wpb] = make_double4(accB.x, accB.y, accB.z, accB.w);
         L.id[wave + wpb] = tB.part;
       }
-    } else {
-      conv32_load(uB, nB, lane, hB);
     }
-    if (threadIdx.x == 0) s_next = after;  // written and read between the two barriers
+    if (threadIdx.x == 0) s_next = more ? dyn0 + got : ntasks;  // written and read between the two barriers
     __syncthreads();
     finish_task(fd, L, nt);
-    const int after_all = s_next;
+    const int after_all = __builtin_amdgcn_readfirstlane(s_next);
     __syncthreads();
     task = nxt;
     nxt = after_all;
@@ -1314,13 +1330,19 @@ hipError_t setup_kernel_attributes(int precision) {
   return e;
 }
 
-int conv_grid_size(int precision, int ntasks, int table_len) {
+int conv_grid_size(int precision, int ntasks, int table_len, double bytes) {
   int need = ntasks;
   if (precision == SBIEM_FP32CONV) {
     // persistent: as many workgroups as are resident at once (LDS table and
-    // registers allow two per CU), so no workgroup waits for a slot
+    // registers allow two per CU), so no workgroup waits for a slot.  Two
+    // resident workgroups fill a CU's registers, and the stage launches of
+    // the step running beside the convolution then find no CU until it
+    // ends; below a few GB of ring per launch, 64 CUs keep one workgroup
+    // only, so the stages run in its shadow (above that the convolution's
+    // own time dominates and the full grid is faster).
     const int per_cu = (int)(kMaxLdsBytes / ((size_t)table_len * sizeof(float4) + 1024));
-    const int cap = 256 * (per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu));
+    int cap = 256 * (per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu));
+    if (cap == 512 && bytes < 4e9) cap -= 64;
     return need < cap ? (need < 1 ? 1 : need) : cap;
   }
   return need < 1 ? 1 : need;

@@ -5,6 +5,7 @@
 #include <complex>
 #include <cstring>
 #include <sstream>
+#include <thread>
 
 #include "internal.h"
 
@@ -262,6 +263,16 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
   d->th_mode.assign(half + 1, 0.0);
   for (int n = 0; n <= half; ++n) d->th_mode[n] = (double)(th_unit * n);
   if (!e && p->closure_on) {
+    std::vector<int> cn, cMk, cM;
+    for (int n = 1; n <= half; ++n) {
+      if (d->Rn[n] + 1 == d->M[n]) continue;  // open mode
+      cn.push_back(n);
+      cMk.push_back(d->Rn[n] + 1);
+      cM.push_back(d->M[n]);
+    }
+    std::vector<double> DT, DN;
+    discarded_weights(p->cs, p->cp, p->L, dt, cn, cMk, cM, &DT, &DN);
+    size_t ci = 0;
     for (int n = 1; n <= half; ++n) {
       if (d->Rn[n] + 1 == d->M[n]) continue;  // open mode
       ClosureMode c;
@@ -274,6 +285,9 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
       c.tcut = (float)(csk * c.Mk * dt / 100.0);
       c.pad = 0.f;
       c.inv_csk = 1.0 / csk;
+      c.dT = DT[ci];
+      c.dN = DN[ci];
+      ++ci;
       d->closure.push_back(c);
     }
     d->tails = (double4*)d->mem.get(sizeof(double4) * (half + 1));
@@ -338,6 +352,61 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
   }
   *out = d;
   return SBIEM_OK;
+}
+
+void discarded_weights(double cs, double cp, double L, double dt, const std::vector<int>& n,
+                       const std::vector<int>& Mk, const std::vector<int>& M, std::vector<double>* DT,
+                       std::vector<double>* DN) {
+  const size_t cnt = n.size();
+  DT->assign(cnt, 0.0);
+  DN->assign(cnt, 0.0);
+  if (cnt == 0) return;
+  // table coordinate of lag j: x = (2 j + 1) c_s |k_n| dt / (2 h)
+  const long double th_unit = 3.141592653589793238462643383279502884L * (long double)cs *
+                              (long double)dt / (long double)L / (long double)kTableStep;
+  double xmax = 0.0;
+  long long work = 0;
+  for (size_t i = 0; i < cnt; ++i) {
+    xmax = std::max(xmax, (double)(th_unit * n[i]) * (2.0 * M[i] + 1.0));
+    work += std::max(0, M[i] - Mk[i]);
+  }
+  const int K = (int)std::ceil(xmax) + 3;
+  std::vector<double> tab(4 * (size_t)K);
+  for (int i = 0; i < K; ++i) {
+    long double CT, CN, dCT, dCN;
+    kernel_values((long double)i * kTableStep, cs, cp, &CT, &CN, &dCT, &dCN);
+    tab[4 * i + 0] = (double)(dt * CT);
+    tab[4 * i + 1] = (double)(dt * kTableStep * dCT);
+    tab[4 * i + 2] = (double)(dt * CN);
+    tab[4 * i + 3] = (double)(dt * kTableStep * dCN);
+  }
+  auto run = [&](size_t i0, size_t i1) {
+    for (size_t i = i0; i < i1; ++i) {
+      const double th = (double)(th_unit * n[i]);
+      double sT = 0.0, sN = 0.0;
+      for (int j = Mk[i]; j < M[i]; ++j) {
+        const double x = (double)(2 * j + 1) * th;
+        const int k = std::min((int)x, K - 2);
+        const double f = x - (double)k, f2 = f * f, f3 = f2 * f;
+        const double h00 = 2 * f3 - 3 * f2 + 1, h10 = f3 - 2 * f2 + f, h01 = 3 * f2 - 2 * f3,
+                     h11 = f3 - f2;
+        const double* a = &tab[4 * (size_t)k];
+        sT += h00 * a[0] + h10 * a[1] + h01 * a[4] + h11 * a[5];
+        sN += h00 * a[2] + h10 * a[3] + h01 * a[6] + h11 * a[7];
+      }
+      (*DT)[i] = sT;
+      (*DN)[i] = sN;
+    }
+  };
+  const int nth = work > (1 << 22) ? 8 : 1;
+  if (nth == 1) {
+    run(0, cnt);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nth; ++t)
+    pool.emplace_back(run, cnt * t / nth, cnt * (t + 1) / nth);
+  for (auto& th : pool) th.join();
 }
 
 int build_dyn_data(sbiem_plan* p, DynData** out) {

@@ -135,3 +135,64 @@ def test_step_with_closure_matches_oracle():
         worst["V"] = max(worst["V"], rel(g["V"], o.V))
     print("closure step vs oracle", worst)
     assert worst["tau_el"] < 1e-4 and worst["sigma_el"] < 1e-4, worst
+
+
+def _nucleating(N, seed, overstress):
+    from sbiem_inputs import rough_fault
+    L = 10.0 * N
+    return Scenario(N, L, 0.5 * 10.0 / CS, rough_fault(N, L, 1e-3, seed),
+                    spec=FrictionSpec(overstress=overstress, w_nuc=0.15 * L), theta_mode="exp",
+                    consistent_V0=True)
+
+
+def test_trained_closure_against_plain_and_constant_extrapolation():
+    """What the trained network adds: networks trained on the GPU from plain
+    runs of four rough faults (two slow, two nucleating) close a held-out
+    nucleating fault; the run is compared with the plain full-window run, and
+    so is the same closure with zero networks (the constant extrapolation
+    alone).  The closure must keep the rupture arrival times within 1 % of
+    the plain run's; the stress and slip-rate errors of both forms are
+    reported.  Training must not leave the networks worse than zero networks
+    on their own pairs."""
+    from paper_2107_03550_amd.closure_train import collect_pairs, train_networks
+    pkg = _pkg()
+    N, steps = 2048, 3000
+    train = [_nucleating(N, s, o) for s, o in ((101, 3e6), (102, 3e6), (103, 6e6), (104, 6e6))]
+    plans = [make_plan(sc, pkg.SBIEM_FP32CONV) for sc in train]
+    pairs = collect_pairs(plans, train[0].dt, steps=steps, every=50)
+    pT, pN, _, _ = train_networks(pairs, steps=2000, batch=2048, lr=1e-3)
+    for (X, Y), p in zip(pairs, (pT, pN)):
+        fit = np.mean(np.sum((pkg.closure_eval(p, X) - Y) ** 2, axis=1))
+        zero = np.mean(np.sum(Y.astype(np.float64) ** 2, axis=1))
+        print("closure training: loss", fit, "zero network", zero)
+        assert fit <= 1.05 * zero
+    ev = _nucleating(N, 777, 6e6)
+    ref = make_plan(ev, pkg.SBIEM_FP32CONV)
+    runs = {"trained": make_plan(ev, pkg.SBIEM_FP32CONV), "zero": make_plan(ev, pkg.SBIEM_FP32CONV)}
+    runs["trained"].set_closure(pT, pN, 0.25)
+    z = np.zeros(cl.N_PARAMS, np.float32)
+    runs["zero"].set_closure(z, z, 0.25)
+    worst = {k: [0.0, 0.0] for k in runs}
+    arrival = {k: np.full(N, -1) for k in ("plain", *runs)}
+    chunk = 10
+    for k in range(1, steps // chunk + 1):
+        ref.run(ev.dt, chunk)
+        g = ref.get_state()
+        arrival["plain"][(arrival["plain"] < 0) & (g["V"] > 1e-3)] = k * chunk
+        for name, p in runs.items():
+            p.run(ev.dt, chunk)
+            h = p.get_state()
+            arrival[name][(arrival[name] < 0) & (h["V"] > 1e-3)] = k * chunk
+            worst[name][0] = max(worst[name][0], rel(h["tau_el"], g["tau_el"]))
+            worst[name][1] = max(worst[name][1], rel(h["V"], g["V"]))
+    hit = arrival["plain"] >= 0
+    assert hit.sum() > 20
+    for name in runs:
+        a = arrival[name]
+        assert np.all(a[hit] >= 0)
+        d = np.abs(a[hit] - arrival["plain"][hit]) / arrival["plain"][hit]
+        print(f"closure ({name} networks): tau_el {worst[name][0]:.3e}, V {worst[name][1]:.3e}, "
+              f"arrival max {d.max():.3e} mean {d.mean():.3e}")
+        if name == "trained":
+            assert d.max() <= 0.01
+            assert worst[name][0] < 5e-2

@@ -130,3 +130,39 @@ def test_kept_lags_rule():
     Mk, use = cl.kept_lags(M, 0.25)
     assert list(use) == [False, False, False, True, True, True, True]
     assert list(Mk) == [1, 40, 68, 18, 18, 100, 250]
+
+
+def test_zero_network_closure_is_exact_for_a_history_constant_beyond_the_cut():
+    """With y = 0 the tail is D a_15: exact when every discarded lag holds the
+    oldest kept value (the kept lags may hold anything)."""
+    N, L = 256, 10e3
+    spec = FrictionSpec(overstress=9e6, w_nuc=800.0)
+    fr = friction_fields(N, L, MU, CS, spec)
+    dt = 0.5 * L / N / CS
+    h = rough_fault(N, L, 3e-3, 4)
+    zero = np.zeros(cl.N_PARAMS)
+    plain = OracleFault(N, L, MU, CS, CP, dt=dt, friction=fr, h=h, transform="fft")
+    clo = OracleFault(N, L, MU, CS, CP, dt=dt, friction=fr, h=h, transform="fft", closure=(zero, zero, 0.25))
+    assert clo.closed.sum() > 20
+    rng = np.random.default_rng(11)
+    for kind in (0, 1):
+        Hp = plain.HT if kind == 0 else plain.HN
+        Hc = clo.HT if kind == 0 else clo.HN
+        for n in range(1, N // 2 + 1):
+            kept = rng.standard_normal(plain.hM[n]) + 1j * rng.standard_normal(plain.hM[n])
+            if n == N // 2:
+                kept = kept.real + 0j
+            Mk = int(clo.M_kept[n]) if clo.closed[n] else int(plain.w.M[n])
+            kept[Mk - 1:] = kept[Mk - 2] if Mk >= 2 else kept[0]     # lags >= M'-1 equal a_15
+            for m, vals in ((n, kept), (N - n, np.conj(kept))):
+                if m == N // 2 and n != N // 2:
+                    continue
+                Hp[plain.hoff[m]:plain.hoff[m] + plain.hM[m]] = vals
+                Hc[clo.hoff[m]:clo.hoff[m] + clo.hM[m]] = vals[:clo.hM[m]]
+    ST_p, SN_p = plain.history_sums()
+    ST_c, SN_c = clo.history_sums()
+    for a, b in ((ST_c, ST_p), (SN_c, SN_p)):
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+    # and truncation alone (dropping the tail) is far from it
+    tT, tN = clo.closure_tails()
+    assert np.max(np.abs(ST_c - tT - ST_p)) > 1e-3 * np.max(np.abs(ST_p))
