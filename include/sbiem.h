@@ -246,7 +246,8 @@ int sbiem_batch_profile(sbiem_batch* b, double* conv_ms, int64_t* conv_launches,
  * Parameters: SBIEM_CLOSURE_PARAMS floats in the order W1[33][64], b1[64],
  * W2[64][64], b2[64], W3[64][2], b3[2] (row = input), h1 = gelu(x W1 + b1),
  * h2 = gelu(h1 W2 + b2), y = h2 W3 + b3.  Inference uses bfloat16 weights and
- * layer inputs with float32 accumulation (matrix cores); training float32.
+ * layer inputs with float32 accumulation (matrix cores) and evaluates erf by
+ * Abramowitz & Stegun 7.1.26 (error < 1.5e-7); training float32 with erf.
  * ------------------------------------------------------------------------- */
 #define SBIEM_CLOSURE_PARAMS 6466
 

@@ -12,6 +12,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -30,6 +31,23 @@ __device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.f + erff
 __device__ __forceinline__ float gelu_grad_f(float z) {
   return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
 }
+// GELU for inference, whose outputs are rounded to bfloat16: erf from
+// Abramowitz & Stegun, formula 7.1.26 (absolute error below 1.5e-7, far
+// under half a bfloat16 unit), with the hardware reciprocal and exp2.
+__device__ __forceinline__ float gelu_infer(float z) {
+  const float x = z * 0.70710678118654752f;
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.f));
+  float poly = fmaf(1.061405429f, t, -1.453152027f);
+  poly = fmaf(poly, t, 1.421413741f);
+  poly = fmaf(poly, t, -0.284496736f);
+  poly = fmaf(poly, t, 0.254829592f);
+  poly *= t;
+  const float e = __builtin_amdgcn_exp2f(-ax * ax * 1.4426950408889634f);
+  const float erf_ax = fmaf(-poly, e, 1.f);
+  return 0.5f * z * (1.f + copysignf(erf_ax, x));
+}
+
 // float -> bfloat16 bits, round to nearest even
 __device__ __forceinline__ short bf16_bits(float x) {
   unsigned u = __float_as_uint(x);
@@ -59,10 +77,11 @@ struct NetDev {
 
 // x: the lane's 12 input values (features 16 kb + 4 (lane/16) + e) as
 // bfloat16 B fragments; returns y0, y1 (valid in lanes 0..15).
-__device__ __forceinline__ void mlp_wave(const NetDev& net, const v4s (&x)[3], float* y0, float* y1) {
+__device__ __forceinline__ void mlp_wave(const v4s* __restrict__ frag, const float* __restrict__ bias,
+                                         const v4s (&x)[3], float* y0, float* y1) {
   const int lane = threadIdx.x & 63;
   const int q = lane >> 4;
-  const v4s* __restrict__ fr = net.frag + lane;
+  const v4s* __restrict__ fr = frag + lane;
   v4s h1[4], h2[4];
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb) {
@@ -70,7 +89,8 @@ __device__ __forceinline__ void mlp_wave(const NetDev& net, const v4s (&x)[3], f
 #pragma unroll
     for (int kb = 0; kb < 3; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fr[64 * (3 * nb + kb)], x[kb], acc, 0, 0, 0);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) h1[nb][r] = bf16_bits(gelu_f(acc[r] + net.bias[16 * nb + 4 * q + r]));
+    for (int r = 0; r < 4; ++r) h1[nb][r] = bf16_bits(gelu_infer(acc[r] + bias[16 * nb + 4 * q + r]));
+    __builtin_amdgcn_sched_barrier(0);  // one block's weight fragments live at a time
   }
 #pragma unroll
   for (int ob = 0; ob < 4; ++ob) {
@@ -78,13 +98,14 @@ __device__ __forceinline__ void mlp_wave(const NetDev& net, const v4s (&x)[3], f
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fr[64 * (12 + 4 * ob + kb)], h1[kb], acc, 0, 0, 0);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) h2[ob][r] = bf16_bits(gelu_f(acc[r] + net.bias[64 + 16 * ob + 4 * q + r]));
+    for (int r = 0; r < 4; ++r) h2[ob][r] = bf16_bits(gelu_infer(acc[r] + bias[64 + 16 * ob + 4 * q + r]));
+    __builtin_amdgcn_sched_barrier(0);
   }
   v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fr[64 * (28 + kb)], h2[kb], acc, 0, 0, 0);
-  *y0 = acc[0] + net.bias[128];
-  *y1 = acc[1] + net.bias[129];
+  *y0 = acc[0] + bias[128];
+  *y1 = acc[1] + bias[129];
 }
 
 // Standalone evaluation: y = net(x) for n inputs (rows of 33 floats).
@@ -102,7 +123,7 @@ __global__ void __launch_bounds__(256) k_mlp_eval(NetDev net, const float* __res
       x[kb][e] = bf16_bits((m < n && f < kIn) ? X[m * kIn + f] : 0.f);
     }
   float y0, y1;
-  mlp_wave(net, x, &y0, &y1);
+  mlp_wave(net.frag, net.bias, x, &y0, &y1);
   if (q == 0 && m < n) {
     Y[2 * m] = y0;
     Y[2 * m + 1] = y1;
@@ -117,69 +138,90 @@ __global__ void __launch_bounds__(256) k_mlp_eval(NetDev net, const float* __res
 __global__ void __launch_bounds__(256) k_closure(const FaultDev* __restrict__ faults,
                                                  const ClosureMode* __restrict__ cm, int ncm,
                                                  NetDev netT, NetDev netN, int ahead) {
+  // both networks staged in LDS once per workgroup; each wave then loops
+  // over groups of 16 closed modes
+  __shared__ v4s sfrag[2][32 * 64];
+  __shared__ float sbias[2][132];
+  for (int i = threadIdx.x; i < 32 * 64; i += 256) {
+    sfrag[0][i] = netT.frag[i];
+    sfrag[1][i] = netN.frag[i];
+  }
+  for (int i = threadIdx.x; i < 130; i += 256) {
+    sbias[0][i] = netT.bias[i];
+    sbias[1][i] = netN.bias[i];
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int q = lane >> 4, j = lane & 15;
-  const int m = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 + j;
-  const bool valid = m < ncm;
-  const ClosureMode c = cm[valid ? m : 0];
-  const FaultDev& fd = faults[c.fault];
-  const int err = *fd.err;
-  const long long b = *fd.step + ahead - 1;
-  const float4* __restrict__ ring = (const float4*)fd.ring + c.ring_off;
-  // raw inputs of this lane: features f = 16 kb + 4 q + e
-  float vT[12], vN[12];
-  float sT = 0.f, sN = 0.f;
+  const int ngroups = (ncm + 15) / 16;
+  for (int grp = blockIdx.x * 4 + (threadIdx.x >> 6); grp < ngroups; grp += gridDim.x * 4) {
+    const int m = grp * 16 + j;
+    const bool valid = m < ncm;
+    const ClosureMode c = cm[valid ? m : 0];
+    const FaultDev& fd = faults[c.fault];
+    const int err = *(const __attribute__((address_space(1))) int*)fd.err;
+    const long long b = *(const __attribute__((address_space(1))) long long*)fd.step + ahead - 1;
+    typedef const __attribute__((address_space(1))) v4f* gring;
+    const gring ring = (gring)((const float4*)fd.ring + c.ring_off);
+    // ring slot of lag M'_n - 16 (the first input); lag M'_n - 16 + k sits k
+    // slots before it (cyclically)
+    const int Rn = c.Rn;
+    long long p0l = (b - (c.Mk - 16) + 1) % Rn;
+    if (p0l < 0) p0l += Rn;
+    const int p0 = (int)p0l;
+    // the oldest kept record (k = 15), for the constant extrapolation
+    const v4f a = ring[p0 >= 15 ? p0 - 15 : p0 - 15 + Rn];
+    // raw inputs of this lane: features f = 16 kb + 4 q + e
+    float vT[12], vN[12];
+    float sT = 0.f, sN = 0.f;
 #pragma unroll
-  for (int kb = 0; kb < 3; ++kb)
+    for (int kb = 0; kb < 3; ++kb)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int f = 16 * kb + 4 * q + e;
-      float t = 0.f, g = 0.f;
-      if (f == 0) {
-        t = g = c.tcut;
-      } else if (f <= 32 && valid) {
-        const int k = (f - 1) >> 1;
-        const int lag = c.Mk - 16 + k;
-        long long p = (b - lag + 1) % c.Rn;
-        if (p < 0) p += c.Rn;
-        const float4 rec = ring[p];
-        t = (f & 1) ? rec.x : rec.y;   // f odd: real part, even: imaginary part
-        g = (f & 1) ? rec.z : rec.w;
-        sT += t * t;
-        sN += g * g;
+      for (int e = 0; e < 4; ++e) {
+        const int f = 16 * kb + 4 * q + e;
+        float t = 0.f, g = 0.f;
+        if (f == 0) {
+          t = g = c.tcut;
+        } else if (f <= 32) {
+          const int k = (f - 1) >> 1;
+          const int pk = p0 - k;
+          const v4f rec = ring[pk >= 0 ? pk : pk + Rn];
+          t = (f & 1) ? rec.x : rec.y;   // f odd: real part, even: imaginary part
+          g = (f & 1) ? rec.z : rec.w;
+          sT += t * t;
+          sN += g * g;
+        }
+        vT[4 * kb + e] = t;
+        vN[4 * kb + e] = g;
       }
-      vT[4 * kb + e] = t;
-      vN[4 * kb + e] = g;
-    }
-  // RMS over the 16 values (the four lanes of column j hold them)
-  sT += __shfl_xor(sT, 16);
-  sT += __shfl_xor(sT, 32);
-  sN += __shfl_xor(sN, 16);
-  sN += __shfl_xor(sN, 32);
-  const float rT = sqrtf(sT * (1.f / 16.f)), rN = sqrtf(sN * (1.f / 16.f));
-  const float iT = rT > 0.f ? 1.f / rT : 0.f, iN = rN > 0.f ? 1.f / rN : 0.f;
-  v4s xT[3], xN[3];
+    // RMS over the 16 values (the four lanes of column j hold them)
+    sT += __shfl_xor(sT, 16);
+    sT += __shfl_xor(sT, 32);
+    sN += __shfl_xor(sN, 16);
+    sN += __shfl_xor(sN, 32);
+    const float rT = sqrtf(sT * (1.f / 16.f)), rN = sqrtf(sN * (1.f / 16.f));
+    const float iT = rT > 0.f ? 1.f / rT : 0.f, iN = rN > 0.f ? 1.f / rN : 0.f;
+    v4s xT[3], xN[3];
 #pragma unroll
-  for (int kb = 0; kb < 3; ++kb)
+    for (int kb = 0; kb < 3; ++kb)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int f = 16 * kb + 4 * q + e;
-      xT[kb][e] = bf16_bits(f == 0 ? vT[4 * kb + e] : vT[4 * kb + e] * iT);
-      xN[kb][e] = bf16_bits(f == 0 ? vN[4 * kb + e] : vN[4 * kb + e] * iN);
+      for (int e = 0; e < 4; ++e) {
+        const int f = 16 * kb + 4 * q + e;
+        xT[kb][e] = bf16_bits(f == 0 ? vT[4 * kb + e] : vT[4 * kb + e] * iT);
+        xN[kb][e] = bf16_bits(f == 0 ? vN[4 * kb + e] : vN[4 * kb + e] * iN);
+      }
+    float yT0, yT1, yN0, yN1;
+    mlp_wave(sfrag[0], sbias[0], xT, &yT0, &yT1);
+    __builtin_amdgcn_sched_barrier(0);
+    mlp_wave(sfrag[1], sbias[1], xN, &yN0, &yN1);
+    if (q == 0 && valid && !err) {
+      // tail = D a_15 + y r / (c_s |k_n|), a_15 the oldest kept record (lag M'_n - 1)
+      const double sT_ = (double)rT * c.inv_csk, sN_ = (double)rN * c.inv_csk;
+      // the Nyquist coefficient of a real signal is real
+      const double im = c.pm == fd.nmodes ? 0.0 : 1.0;
+      fd.tails[c.pm] = make_double4(c.dT * a.x + yT0 * sT_, im * (c.dT * a.y + yT1 * sT_),
+                                    c.dN * a.z + yN0 * sN_, im * (c.dN * a.w + yN1 * sN_));
     }
-  float yT0, yT1, yN0, yN1;
-  mlp_wave(netT, xT, &yT0, &yT1);
-  mlp_wave(netN, xN, &yN0, &yN1);
-  if (q == 0 && valid && !err) {
-    // tail = D a_15 + y r / (c_s |k_n|), a_15 the oldest kept record (lag M'_n - 1)
-    long long p = (b - c.Mk + 2) % c.Rn;
-    if (p < 0) p += c.Rn;
-    const float4 a = ring[p];
-    const double sT_ = (double)rT * c.inv_csk, sN_ = (double)rN * c.inv_csk;
-    // the Nyquist coefficient of a real signal is real
-    const double im = c.pm == fd.nmodes ? 0.0 : 1.0;
-    fd.tails[c.pm] = make_double4(c.dT * a.x + yT0 * sT_, im * (c.dT * a.y + yT1 * sT_),
-                                  c.dN * a.z + yN0 * sN_, im * (c.dN * a.w + yN1 * sN_));
   }
 }
 
@@ -437,7 +479,8 @@ hipError_t launch_closure(const Exec& ex, int ahead, hipStream_t s) {
   if (!ex.closure_modes || ex.nclosure == 0) return hipSuccess;
   NetDev T{(const v4s*)ex.net_frag[0], ex.net_bias[0]};
   NetDev N{(const v4s*)ex.net_frag[1], ex.net_bias[1]};
-  const int blocks = (ex.nclosure + 63) / 64;
+  const int groups = (ex.nclosure + 15) / 16;  // one wave per 16 modes and pass
+  const int blocks = std::min((groups + 3) / 4, 4 * 256);
   hipLaunchKernelGGL(k_closure, dim3(blocks), dim3(256), 0, s, ex.d_faults, ex.closure_modes,
                      ex.nclosure, T, N, ahead);
   return hipGetLastError();

@@ -120,17 +120,19 @@ struct Tile {
 };
 
 // A conv task: tiles [t0, t1) of one fault, handled by one workgroup.  A task
-// holds whole modes, or one piece of a mode longer than kTaskTiles tiles; it
+// holds whole modes, or one piece of a mode longer than a task's tiles; it
 // writes one FP64 partial sum per (task, mode) and the spectral kernel adds a
 // mode's pieces in order.
 struct ConvTask {
   int t0, t1;
 };
-constexpr int kTaskTiles = 16;  // at most this many tiles per task
-
-constexpr int kTileSlots32 = 512;   // FP32 records per wavefront tile
-constexpr int kTileSlots64 = 256;   // FP64 records per wavefront tile
 constexpr int kConvThreads = 512;   // 8 wavefronts
+constexpr int kTileSlots32 = 512;   // FP32 records per wavefront tile
+constexpr int kWaveTiles32 = 2;     // FP32 tiles per wavefront and task
+constexpr int kTaskTiles32 = kWaveTiles32 * (kConvThreads / 64);
+constexpr int kTileSlots64 = 256;   // FP64 records per wavefront tile
+constexpr int kTaskTiles64 = 16;
+constexpr int kTaskTiles = kTaskTiles32 > kTaskTiles64 ? kTaskTiles32 : kTaskTiles64;  // at most
 constexpr int kModeThreads = 256;   // mode-stage workgroups
 constexpr int kElemThreads = 256;   // element-stage workgroups
 constexpr double kTableStep = 1.0 / 16.0;  // spacing of the FP32 kernel table in T

@@ -364,14 +364,18 @@ k_conv32(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
   int nxt = blockIdx.x + gridDim.x;
   const int dyn0 = 2 * gridDim.x;
   ConvTask tk = task < ntasks ? tasks[task] : ConvTask{0, 0};
-  Tile tA = {}, tB = {};
-  bool hasA = task < ntasks && wave < tk.t1 - tk.t0;
-  bool hasB = task < ntasks && wave + wpb < tk.t1 - tk.t0;
-  if (hasA) tA = tiles[tk.t0 + wave];
-  if (hasB) tB = tiles[tk.t0 + wave + wpb];
-  float4 hA[kConvU] = {}, hB[kConvU] = {};
-  conv32_load(tA, hasA, lane, table, hA);
-  conv32_load(tB, hasB, lane, table, hB);
+  constexpr int K = kWaveTiles32;
+  Tile t[K];
+  bool has[K];
+  float4 h[K][kConvU];
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    has[i] = task < ntasks && wave + wpb * i < tk.t1 - tk.t0;
+    t[i] = has[i] ? tiles[tk.t0 + wave + wpb * i] : Tile{};
+#pragma unroll
+    for (int u = 0; u < kConvU; ++u) h[i][u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    conv32_load(t[i], has[i], lane, table, h[i]);
+  }
   // the table is staged while the first records are in flight
   for (int i = threadIdx.x; i < table_len; i += kConvThreads) tab[i] = table[i];
   __syncthreads();
@@ -383,34 +387,25 @@ k_conv32(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
     const FaultDev& fd = faults[tiles[tk.t0].fault];
     const int err = read_word(fd.err);
     const long long step = read_word(fd.step) + ahead;
-    // next task's tiles
     const ConvTask nk = more ? tasks[nxt] : ConvTask{0, 0};
-    const bool nA = more && wave < nk.t1 - nk.t0;
-    const bool nB = more && wave + wpb < nk.t1 - nk.t0;
-    Tile uA = {}, uB = {};
-    if (nA) uA = tiles[nk.t0 + wave];
-    if (nB) uB = tiles[nk.t0 + wave + wpb];
-    // weigh a tile, then reuse its registers for the next task's records
-    float4 accA = make_float4(0.f, 0.f, 0.f, 0.f), accB = accA;
-    if (hasA && !err) accA = conv32_weigh(tA, step, lane, hA, tab, table_len);
-    __builtin_amdgcn_sched_barrier(0);
-    conv32_load(uA, nA, lane, table, hA);
-    if (hasB && !err) accB = conv32_weigh(tB, step, lane, hB, tab, table_len);
-    __builtin_amdgcn_sched_barrier(0);
-    conv32_load(uB, nB, lane, table, hB);
-    if (hasA) {
-      accA = wave_reduce4(accA);
-      if (lane == 0) {
-        L.part[wave] = make_double4(accA.x, accA.y, accA.z, accA.w);
-        L.id[wave] = tA.part;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      // weigh tile i, then reuse its registers for the next task's tile i
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (has[i] && !err) acc = conv32_weigh(t[i], step, lane, h[i], tab, table_len);
+      __builtin_amdgcn_sched_barrier(0);
+      const bool nh = more && wave + wpb * i < nk.t1 - nk.t0;
+      const Tile u = nh ? tiles[nk.t0 + wave + wpb * i] : Tile{};
+      conv32_load(u, nh, lane, table, h[i]);
+      if (has[i]) {
+        acc = wave_reduce4(acc);
+        if (lane == 0) {
+          L.part[wave + wpb * i] = make_double4(acc.x, acc.y, acc.z, acc.w);
+          L.id[wave + wpb * i] = t[i].part;
+        }
       }
-    }
-    if (hasB) {
-      accB = wave_reduce4(accB);
-      if (lane == 0) {
-        L.part[wave + wpb] = make_double4(accB.x, accB.y, accB.z, accB.w);
-        L.id[wave + wpb] = tB.part;
-      }
+      t[i] = u;
+      has[i] = nh;
     }
     if (threadIdx.x == 0) s_next = more ? dyn0 + got : ntasks;  // written and read between the two barriers
     __syncthreads();
@@ -420,10 +415,6 @@ k_conv32(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
     task = nxt;
     nxt = after_all;
     tk = nk;
-    hasA = nA;
-    hasB = nB;
-    tA = uA;
-    tB = uB;
   }
 }
 

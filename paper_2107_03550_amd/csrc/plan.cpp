@@ -185,9 +185,10 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
   }
   d->ring_slots = slots;
   // conv tiles (one wavefront each) and tasks (one workgroup each): a task
-  // holds whole modes up to kTaskTiles tiles, a longer mode is cut into
-  // pieces of kTaskTiles tiles
+  // holds whole modes up to task_tiles tiles, a longer mode is cut into
+  // pieces of task_tiles tiles
   const int tile = p->precision == SBIEM_FP32CONV ? kTileSlots32 : kTileSlots64;
+  const int task_tiles = p->precision == SBIEM_FP32CONV ? kTaskTiles32 : kTaskTiles64;
   const long double th_unit = 3.141592653589793238462643383279502884L * (long double)p->cs *
                               (long double)dt / (long double)p->L / (long double)kTableStep;
   d->part0.assign(half + 1, 0);
@@ -203,11 +204,11 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
   for (int n = 1; n <= half; ++n) {
     const int count = (d->Rn[n] + tile - 1) / tile;
     if (count == 0) continue;
-    if (d->tasks.empty() || cur_tiles + std::min(count, kTaskTiles) > kTaskTiles) open_task();
+    if (d->tasks.empty() || cur_tiles + std::min(count, task_tiles) > task_tiles) open_task();
     const int extra0 = extra;
     int part = mode_pos(n, p->log2P, p->log2Q);
     for (int k = 0; k < count; ++k) {
-      if (cur_tiles == kTaskTiles) {  // a long mode continues in a new task
+      if (cur_tiles == task_tiles) {  // a long mode continues in a new task
         open_task();
         part = extra++;
       }
