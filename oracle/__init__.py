@@ -1,8 +1,8 @@
 """CPU FP64 oracle for the non-planar spectral BIEM (Romanet & Ozawa, 2021).
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
-execute anything in this package; only the test-suite, the smoke check of the
-graft entry point and the ``cpu_baseline`` leg of ``bench.py`` use it.  It
+execute anything in this package; only the test-suite, the ``smoke()`` check
+of ``__graft_entry__.py`` and the ``cpu_baseline`` leg of ``bench.py`` use it.  It
 shares no code with the HIP library (``paper_2107_03550_amd``) and imports
 nothing from it.
 
