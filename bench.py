@@ -165,19 +165,24 @@ def main():
                     p.set_closure(nets[0], nets[1], 0.25)
                 plans.append(p)
             r = pkg.Batch(plans)
-            return r, members, r.run, plans, None
+            return r, members, r.run, plans, None, r.tune
         w = workload(args.workload)
         r, fr = build_plan(w, pkg)
         r.set_stream(stream.cuda_stream)
         if with_closure:
             r.set_closure(nets[0], nets[1], 0.25)
-        return r, [w], (lambda k: r.run(w.dt, k)), [r], fr
+        return r, [w], (lambda k: r.run(w.dt, k)), [r], fr, (lambda k: r.tune(w.dt, k))
 
-    runner, members, run, plans, fr = make_runner(args.closure)
+    runner, members, run, plans, fr, tune = make_runner(args.closure)
     w = members[0]
     n_total = sum(m.N for m in members)
 
-    run(args.warmup)
+    # warm-up: autotune the convolution grid on ordinary steps (untimed; the
+    # results do not depend on it), then the remaining warm-up steps
+    n0 = plans[0].steps_done()
+    conv_grid = tune(max(16, min(128, args.warmup)))
+    tuned_steps = plans[0].steps_done() - n0
+    run(max(0, args.warmup - tuned_steps))
     torch.cuda.synchronize()
 
     # timed region: K steps; one step in every 17 launched directly with its
@@ -207,7 +212,7 @@ def main():
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(args.workload),
-        "kernel": "k_conv32" if w.precision != "fp64" else "k_conv64",
+        "kernel": "k_conv32" if w.precision != "fp64" else "k_conv64", "conv_workgroups": conv_grid,
         "bytes_per_launch": conv_bytes, "avg_launch_us": round(avg_ms * 1e3, 3),
         "launches": conv_n,
     }
@@ -215,8 +220,10 @@ def main():
     if args.closure:
         # the plain form on the same workload (graph replay) and the closure's
         # stress error against it after the same steps from the same state
-        plain, _, prun, pplans, _ = make_runner(False)
-        prun(args.warmup)
+        plain, _, prun, pplans, _, ptune = make_runner(False)
+        m0 = pplans[0].steps_done()
+        ptune(max(16, min(128, args.warmup)))
+        prun(max(0, args.warmup - (pplans[0].steps_done() - m0)))
         torch.cuda.synchronize()
         q0 = time.perf_counter()
         prun(args.steps)
@@ -224,8 +231,8 @@ def main():
         q1 = time.perf_counter()
         plain_value = n_total * args.steps / (q1 - q0)
         err_tau = err_v = 0.0
-        steps_done = args.warmup + 2 * args.steps   # the closure run did warmup + two timed runs
-        prun(steps_done - (args.warmup + args.steps))
+        steps_done = plans[0].steps_done()
+        prun(steps_done - pplans[0].steps_done())
         torch.cuda.synchronize()
         for pc, pp in zip(plans, pplans):
             gc, gp = pc.get_state(), pp.get_state()
@@ -255,6 +262,7 @@ def main():
                    else "fp64", "window": "learned closure (1/4 window)" if args.closure
                    else "full (plain)", "faults": len(members)},
         "graph_replay_value": graph_value,
+        "tuning_steps": tuned_steps,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -76,6 +76,8 @@ _SIGS = {
     "sbiem_batch_run": (_int, [_VP, _i64]),
     "sbiem_batch_set_profiling": (_int, [_VP, _int]),
     "sbiem_batch_profile": (_int, [_VP, _D, _I64, _D]),
+    "sbiem_tune": (_int, [_PLAN, _dbl, _i64, ctypes.POINTER(ctypes.c_int32)]),
+    "sbiem_batch_tune": (_int, [_VP, _i64, ctypes.POINTER(ctypes.c_int32)]),
     "sbiem_set_closure": (_int, [_PLAN, _F, _F, _dbl]),
     "sbiem_closure_sample": (_int, [_PLAN, _dbl, _F, _F, _D]),
     "sbiem_closure_eval": (_int, [_F, _F, _i64, _F]),
@@ -283,6 +285,13 @@ class Plan:
         self._c(lib.sbiem_profile(self.handle, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
         return ms.value, n.value, b.value
 
+    def tune(self, dt, steps_per_trial=64):
+        """Autotune the convolution grid on ordinary steps; returns the
+        chosen number of conv workgroups (the state advances)."""
+        g = ctypes.c_int32()
+        self._c(lib.sbiem_tune(self.handle, dt, int(steps_per_trial), ctypes.byref(g)))
+        return g.value
+
     def last_error(self):
         m = lib.sbiem_last_error(self.handle)
         return m.decode() if m else ""
@@ -332,6 +341,15 @@ class Batch:
 
     def run_status(self, nsteps):
         return lib.sbiem_batch_run(self.handle, int(nsteps))
+
+    def tune(self, steps_per_trial=64):
+        """Autotune the convolution grid on ordinary steps; returns the
+        chosen number of conv workgroups (the faults advance)."""
+        g = ctypes.c_int32()
+        st = lib.sbiem_batch_tune(self.handle, int(steps_per_trial), ctypes.byref(g))
+        if st != 0:
+            raise SbiemError(st, lib.sbiem_last_error(None).decode())
+        return g.value
 
     def set_profiling(self, on=True):
         _check(lib.sbiem_batch_set_profiling(self.handle, 1 if on else 0))

@@ -114,7 +114,7 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
   ex->mode_blocks = (int)mmap.size();
   ex->elem_blocks = (int)emap.size();
   ex->conv_bytes = bytes;
-  ex->conv_grid = conv_grid_size(precision, ex->ntasks, ex->table_len, ex->conv_bytes);
+  ex->conv_grid = conv_grid_size(precision, ex->ntasks, ex->table_len, default_conv_reserve(ex->conv_bytes));
   ex->d_faults = (FaultDev*)ex->mem.get(sizeof(FaultDev) * ex->nfaults);
   ex->d_tiles = (Tile*)ex->mem.get(sizeof(Tile) * std::max(1, ex->ntiles));
   ex->d_tasks = (ConvTask*)ex->mem.get(sizeof(ConvTask) * std::max(1, ex->ntasks));
@@ -450,6 +450,56 @@ hipError_t run_steps(Exec* ex, int64_t nsteps, hipStream_t s, bool profile, Even
   return e;
 }
 
+// Autotuning of the convolution grid: whole steps are replayed from the
+// step graph with each candidate number of conv workgroups (events on s
+// around chunks of graph launches), and the fastest is kept.  Results do not
+// depend on the grid (every task writes its own partial sums), so the trial
+// steps are ordinary steps of the simulation.
+hipError_t tune_conv(Exec* ex, int64_t steps_per_trial, hipStream_t s, int* chosen,
+                     const char** what) {
+  *chosen = ex->conv_grid;
+  if (ex->precision != SBIEM_FP32CONV || ex->ntasks == 0) return hipSuccess;
+  *what = "running the prologue launches";
+  hipError_t e = prologue(*ex, s);
+  if (e) return e;
+  std::vector<int> cand;
+  for (int reserve : {0, 64, 128, 192}) {
+    const int g = conv_grid_size(ex->precision, ex->ntasks, ex->table_len, reserve);
+    if (std::find(cand.begin(), cand.end(), g) == cand.end()) cand.push_back(g);
+  }
+  const int64_t chunks = std::max<int64_t>(1, steps_per_trial / kGraphSteps);
+  hipEvent_t a = nullptr, b = nullptr;
+  *what = "creating tuning events";
+  e = hipEventCreate(&a);
+  if (!e) e = hipEventCreate(&b);
+  float best_ms = 0.f;
+  int best = ex->conv_grid;
+  for (size_t c = 0; c < cand.size() && !e; ++c) {
+    ex->drop_graph();
+    ex->conv_grid = cand[c];
+    *what = "capturing the step graph";
+    e = ensure_graph(ex, s);
+    *what = "launching tuning steps";
+    if (!e) e = hipGraphLaunch(ex->graph, s);  // settles the new grid
+    if (!e) e = hipEventRecord(a, s);
+    for (int64_t k = 0; k < chunks && !e; ++k) e = hipGraphLaunch(ex->graph, s);
+    if (!e) e = hipEventRecord(b, s);
+    if (!e) e = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (!e) e = hipEventElapsedTime(&ms, a, b);
+    if (!e && (c == 0 || ms < best_ms)) {
+      best_ms = ms;
+      best = cand[c];
+    }
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  ex->drop_graph();
+  ex->conv_grid = best;
+  *chosen = best;
+  return e;
+}
+
 }  // namespace
 
 }  // namespace sbiem
@@ -660,6 +710,49 @@ int sbiem_batch_run(sbiem_batch* b, int64_t nsteps) {
   }
   if (e)
     return fail_global(SBIEM_EDEVICE, std::string("batch_run: ") + what + ": " + hipGetErrorString(e));
+  int first = SBIEM_OK;
+  for (sbiem_plan* p : b->plans) {
+    int st = check_failure(p);
+    if (st && first == SBIEM_OK) first = st;
+  }
+  return first;
+}
+
+int sbiem_tune(sbiem_plan* p, double dt, int64_t steps_per_trial, int32_t* conv_workgroups) {
+  if (!p) return fail_global(SBIEM_EINVAL, "NULL plan");
+  if (steps_per_trial < 1) return fail(p, SBIEM_EINVAL, "steps_per_trial must be >= 1");
+  if (p->batch_refs > 0) return fail(p, SBIEM_EINVAL, "plan is used by a batch: tune the batch");
+  if (int st = ready(p, dt)) return st;
+  hipError_t e = hipSetDevice(p->device);
+  if (e) return hip_fail(p, e, "hipSetDevice");
+  if (!p->exec) {
+    if (int st = rebuild_exec(p)) return st;
+  }
+  const char* what = "";
+  int chosen = 0;
+  e = tune_conv(p->exec, steps_per_trial, p->stream, &chosen, &what);
+  if (!e) {
+    what = "waiting for the tuning steps";
+    e = hipStreamSynchronize(p->stream);
+  }
+  if (e) return hip_fail(p, e, what);
+  if (conv_workgroups) *conv_workgroups = chosen;
+  return check_failure(p);
+}
+
+int sbiem_batch_tune(sbiem_batch* b, int64_t steps_per_trial, int32_t* conv_workgroups) {
+  if (!b || steps_per_trial < 1) return fail_global(SBIEM_EINVAL, "batch_tune: bad arguments");
+  hipError_t e = hipSetDevice(b->device);
+  const char* what = "hipSetDevice";
+  int chosen = 0;
+  if (!e) e = tune_conv(b->exec, steps_per_trial, b->stream, &chosen, &what);
+  if (!e) {
+    what = "waiting for the tuning steps";
+    e = hipStreamSynchronize(b->stream);
+  }
+  if (e)
+    return fail_global(SBIEM_EDEVICE, std::string("batch_tune: ") + what + ": " + hipGetErrorString(e));
+  if (conv_workgroups) *conv_workgroups = chosen;
   int first = SBIEM_OK;
   for (sbiem_plan* p : b->plans) {
     int st = check_failure(p);

@@ -351,7 +351,8 @@ hipError_t launch_closure(const Exec& ex, int ahead, hipStream_t s);
 void closure_pack(const float* params, std::vector<unsigned short>* frag, std::vector<float>* bias);
 // kept lags M' = ceil(cut M) of a window of M lags, or M when the mode stays open
 int closure_kept(int M, double cut);
-int conv_grid_size(int precision, int ntasks, int table_len, double bytes);
+int conv_grid_size(int precision, int ntasks, int table_len, int reserve);
+int default_conv_reserve(double conv_bytes);
 hipError_t setup_kernel_attributes(int precision);
 size_t mode_lds_bytes(int precision, int log2Q);
 size_t elem_lds_bytes(int precision, int log2P, int ncls);

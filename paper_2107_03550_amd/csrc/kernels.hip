@@ -16,6 +16,8 @@
 // workgroups (see the index maps in internal.h).
 #include "internal.h"
 
+#include <algorithm>
+
 #include <hip/hip_runtime.h>
 
 namespace sbiem {
@@ -1321,22 +1323,28 @@ hipError_t setup_kernel_attributes(int precision) {
   return e;
 }
 
-int conv_grid_size(int precision, int ntasks, int table_len, double bytes) {
+int conv_grid_size(int precision, int ntasks, int table_len, int reserve) {
   int need = ntasks;
   if (precision == SBIEM_FP32CONV) {
-    // persistent: as many workgroups as are resident at once (LDS table and
-    // registers allow two per CU), so no workgroup waits for a slot.  Two
-    // resident workgroups fill a CU's registers, and the stage launches of
-    // the step running beside the convolution then find no CU until it
-    // ends; below a few GB of ring per launch, 64 CUs keep one workgroup
-    // only, so the stages run in its shadow (above that the convolution's
-    // own time dominates and the full grid is faster).
+    // persistent: at most as many workgroups as are resident at once (LDS
+    // table and registers allow two per CU), so no workgroup waits for a
+    // slot.  Two resident workgroups fill a CU's registers, so the stage
+    // launches of the step, which run beside the convolution, find no CU
+    // until it ends; `reserve` workgroups fewer leave that many CUs with
+    // one, where the stages run in the convolution's shadow.
     const int per_cu = (int)(kMaxLdsBytes / ((size_t)table_len * sizeof(float4) + 1024));
     int cap = 256 * (per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu));
-    if (cap == 512 && bytes < 4e9) cap -= 64;
+    cap = std::max(256, cap - std::max(0, reserve));
     return need < cap ? (need < 1 ? 1 : need) : cap;
   }
   return need < 1 ? 1 : need;
+}
+
+int default_conv_reserve(double bytes) {
+  // below a few GB of ring per launch the stages' share of the step is large
+  // enough for the overlap to pay; above, the convolution's own time
+  // dominates and the full grid is faster (sbiem_tune measures instead)
+  return bytes < 4e9 ? 64 : 0;
 }
 
 hipError_t launch_conv(const Exec& ex, int ahead, hipStream_t s) {

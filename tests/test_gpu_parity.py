@@ -313,3 +313,34 @@ def test_batch_of_full_size_faults_matches_individual_plans_bitwise():
         for k in ("slip", "V", "theta", "tau_el", "sigma_el"):
             assert np.array_equal(ga[k], gb[k]), k
     batch.close()
+
+
+def test_tuned_runs_equal_untuned_runs_bitwise():
+    """Autotuning replays ordinary steps with several convolution grids;
+    results do not depend on the grid, so a tuned plan ends where an untuned
+    one run for the same number of steps does (plans and batches)."""
+    pkg = _pkg()
+    sc = Scenario(512, 10e3, 0.5 * (10e3 / 512) / CS, rough_10km(512, seed=6), theta_mode="exp",
+                  spec=FrictionSpec(overstress=8e6), consistent_V0=True)
+    a = make_plan(sc, pkg.SBIEM_FP32CONV)
+    b = make_plan(sc, pkg.SBIEM_FP32CONV)
+    grid = a.tune(sc.dt, 16)
+    assert grid >= 1
+    a.run(sc.dt, 37)
+    done = a.steps_done()
+    assert done > 37
+    b.run(sc.dt, done)
+    ga, gb = a.get_state(), b.get_state()
+    for k in ("slip", "V", "theta", "tau_el", "sigma_el"):
+        assert np.array_equal(ga[k], gb[k]), k
+    # a batch of two faults against its members stepped alone
+    p1, p2 = make_plan(sc, pkg.SBIEM_FP32CONV), make_plan(sc, pkg.SBIEM_FP32CONV)
+    bt = pkg.Batch([p1, p2])
+    bt.tune(16)
+    n = p1.steps_done()
+    assert n == p2.steps_done() > 0
+    q = make_plan(sc, pkg.SBIEM_FP32CONV)
+    q.run(sc.dt, n)
+    g1, gq = p1.get_state(), q.get_state()
+    for k in ("slip", "V", "theta", "tau_el", "sigma_el"):
+        assert np.array_equal(g1[k], gq[k]), k

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(pkg.lib, n), n
     assert set(names) == set(pkg.EXPORTED_NAMES)
-    assert pkg.abi_version() == 2
+    assert pkg.abi_version() == 3
 
 
 def test_plan_create_validates_before_touching_the_device():
