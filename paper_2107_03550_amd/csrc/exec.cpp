@@ -240,6 +240,26 @@ int rebase_state(sbiem_plan* p) {
 // u_hat = F[slip - V_pl t], g_hat = F[kappa (slip - V_pl t)],
 // v_hat0 = F[V - V_pl], gv_hat0 = F[kappa (V - V_pl)] from host arrays
 // (natural element order).
+// Forward transforms of slip (and rate) signals for the set-up paths, in
+// FP64 whatever the convolution precision: the static term multiplies the
+// slip spectrum by |k|, so FP32 rounding of a large slip would come back
+// amplified at high wavenumbers.  An FP32 plan gets a descriptor copy that
+// points at the FP64 twiddle table.
+hipError_t forward_fp64(sbiem_plan* p, const FaultDev* d_desc, const FaultDev& h, const double* a,
+                        double2* A, double2* B, int count, long long stride, void* gF, hipStream_t s,
+                        DevArena& tmp) {
+  if (p->precision == SBIEM_FP64) return launch_forward(d_desc, h, SBIEM_FP64, a, A, B, count, stride, gF, s);
+  FaultDev h64 = h;
+  h64.twiddle = p->twiddle64;
+  FaultDev* d64 = (FaultDev*)tmp.get(sizeof(FaultDev));
+  if (!d64 || !p->twiddle64) return hipErrorOutOfMemory;
+  hipError_t e = hipStreamSynchronize(s);
+  if (!e) e = hipMemcpy(d64, &h64, sizeof(FaultDev), hipMemcpyHostToDevice);
+  if (!e) e = setup_kernel_attributes(SBIEM_FP64);
+  if (!e) e = launch_forward(d64, h64, SBIEM_FP64, a, A, B, count, stride, gF, s);
+  return e;
+}
+
 int spectral_state_from_host(sbiem_plan* p, const double* slip, const double* V, double t) {
   const int64_t N = p->N;
   std::vector<double> x(2 * N);
@@ -259,7 +279,7 @@ int spectral_state_from_host(sbiem_plan* p, const double* slip, const double* V,
   FaultDev h = make_fault_desc(p, p->dtd, d, p->V_pl, p->t0);
   hipError_t e = hipMemcpyAsync(dx, x.data(), 2 * N * sizeof(double), hipMemcpyHostToDevice, s);
   if (!e) e = setup_kernel_attributes(p->precision);
-  if (!e) e = launch_forward(p->d_desc, h, p->precision, dx, A, B, 2, (long long)M, gF, s);
+  if (!e) e = forward_fp64(p, p->d_desc, h, dx, A, B, 2, (long long)M, gF, s, tmp);
   if (!e) e = hipMemcpyAsync(d->u_hat, A, M * sizeof(double2), hipMemcpyDeviceToDevice, s);
   if (!e) e = hipMemcpyAsync(d->g_hat, B, M * sizeof(double2), hipMemcpyDeviceToDevice, s);
   if (!e) e = hipMemcpyAsync(d->v_hat0, A + M, M * sizeof(double2), hipMemcpyDeviceToDevice, s);
@@ -618,8 +638,7 @@ int sbiem_stress(sbiem_plan* p, const double* slip_hist, int64_t nt, double dt, 
     e = launch_forward(dfd, f, p->precision, d_rates, RV, RG, (int)nint, M, gF, s);
   // static part on snapshot nt-1 (its slip plus dt times the last rate is snapshot nt)
   const int64_t base = nint > 0 ? nt - 1 : 0;
-  if (!e)
-    e = launch_forward(dfd, f, p->precision, d_hist + base * N, dyn->u_hat, dyn->g_hat, 1, M, gF, s);
+  if (!e) e = forward_fp64(p, dfd, f, d_hist + base * N, dyn->u_hat, dyn->g_hat, 1, M, gF, s, tmp);
   if (!e && nint > 0) {
     e = hipMemcpyAsync(dyn->v_hat0, RV + (nint - 1) * M, M * sizeof(double2), hipMemcpyDeviceToDevice, s);
     if (!e) e = hipMemcpyAsync(dyn->gv_hat0, RG + (nint - 1) * M, M * sizeof(double2), hipMemcpyDeviceToDevice, s);

@@ -269,6 +269,7 @@ struct sbiem_plan {
   double *a = nullptr, *b = nullptr, *sigma_load = nullptr, *tau_load = nullptr,
          *kappa = nullptr;
   void* twiddle = nullptr;             // quarter-wave table, convolution precision
+  void* twiddle64 = nullptr;           // the same table in FP64 (slip transforms of set-up paths)
   std::vector<double> kappa_host;
   double fwd_scale = 1.0;              // 2^-ilogb(max|kappa|)
 

@@ -235,7 +235,9 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
   const long double theta_unit = kPiL * cs * (long double)dt / (long double)p->L;  // c_s k_1 dt / 2
   std::vector<ModeCoef> coef(half + 1);
   const double c1 = 1.0 - p->r;
-  for (int n = 0; n <= half; ++n) {
+  // two extended-precision kernel evaluations per mode: spread over threads
+  // for large N (each mode writes its own entry)
+  auto mode_coef = [&](int n) {
     const double kabs = 2.0 * M_PI * (double)n / p->L;
     const long double theta = theta_unit * n;  // c_s |k_n| dt / 2
     long double CT, CN;
@@ -257,6 +259,16 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
     c.part0 = d->part0[n];
     c.nparts = d->nparts[n];
     c.pad = 0;
+  };
+  {
+    const int nth = half >= (1 << 15) ? 8 : 1;
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nth; ++t)
+      pool.emplace_back([&, t]() {
+        for (int n = t; n <= half; n += nth) mode_coef(n);
+      });
+    for (int n = 0; n <= half; n += nth) mode_coef(n);
+    for (auto& th : pool) th.join();
   }
   hipError_t e = hipSuccess;
   hipStream_t s = p->stream;
@@ -569,7 +581,8 @@ int ensure_device(sbiem_plan* p) {
   return SBIEM_OK;
 }
 
-// Quarter-wave table cos(2 pi t / N), t = 0..N/4, in the convolution precision.
+// Quarter-wave table cos(2 pi t / N), t = 0..N/4, in the convolution
+// precision, and once in FP64 for the slip transforms of the set-up paths.
 int upload_twiddles(sbiem_plan* p) {
   const int64_t N = p->N, Q = N / 4;
   std::vector<double> t64(Q + 1);
@@ -581,8 +594,9 @@ int upload_twiddles(sbiem_plan* p) {
     t32[t] = (float)c;
   }
   hipError_t e = hipSuccess;
+  if (!p->twiddle64) p->twiddle64 = upload(p->mem, t64, p->stream, &e);
   if (p->precision == SBIEM_FP32CONV) p->twiddle = upload(p->mem, t32, p->stream, &e);
-  else p->twiddle = upload(p->mem, t64, p->stream, &e);
+  else p->twiddle = p->twiddle64;
   if (!e) e = hipStreamSynchronize(p->stream);
   if (e) return hip_fail(p, e, "uploading twiddles");
   return SBIEM_OK;

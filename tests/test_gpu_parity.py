@@ -344,3 +344,90 @@ def test_tuned_runs_equal_untuned_runs_bitwise():
     g1, gq = p1.get_state(), q.get_state()
     for k in ("slip", "V", "theta", "tau_el", "sigma_el"):
         assert np.array_equal(g1[k], gq[k]), k
+
+
+# ---------------------------------------------------------------- edge cases
+@pytest.mark.parametrize("N", [8, 16])
+def test_smallest_sizes_match_oracle(N):
+    """N = 8 and 16: transforms of P = 2 and 4 points per element class,
+    stress path and twenty steps in FP64 against the oracle."""
+    from oracle.spectral import curvature
+    from oracle.stress import stress_from_history
+    from oracle.windows import midpoint_weights
+    pkg = _pkg()
+    L = 10.0 * N
+    dt = 0.5 * (L / N) / CS
+    # the rough-fault band (wavelengths 20 dx .. L) is empty at these sizes:
+    # two explicit Fourier modes instead
+    x = np.arange(N) * (L / N)
+    h = 0.4 * np.sin(2 * np.pi * x / L) + 0.15 * np.cos(4 * np.pi * x / L + 0.3)
+    hist = _history(N, 60, seed=N)
+    p = pkg.Plan(N, L, MU, NU, CS, CP, h)
+    tau, sig = p.stress(hist, dt)
+    w = midpoint_weights(N, L, CS, CP, dt)
+    rt, rs = stress_from_history(hist, dt, L, MU, CS, CP, curvature(h, L), w)
+    assert rel(tau, rt) < 1e-10 and rel(sig, rs) < 1e-10, (rel(tau, rt), rel(sig, rs))
+    sc = Scenario(N, L, dt, h, theta_mode="exp", spec=FrictionSpec(overstress=3e6),
+                  consistent_V0=True)
+    q = make_plan(sc, pkg.SBIEM_FP64)
+    o = make_oracle(sc)
+    q.run(dt, 20)
+    o.run(20)
+    g = q.get_state()
+    for k, ref in (("slip", o.slip), ("V", o.V), ("tau_el", o.tau_el), ("sigma_el", o.sigma_el)):
+        assert rel(g[k], ref) < 1e-10, (k, rel(g[k], ref))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_planar_fault_and_zero_history(precision):
+    """h = 0: no normal traction (the packed transform's imaginary part is
+    rounding only) and the shear traction of the flat-fault oracle; a zero
+    slip history gives zero traction exactly."""
+    from oracle.stress import stress_from_history
+    from oracle.windows import midpoint_weights
+    pkg = _pkg()
+    N, L = 512, 5120.0
+    dt = 0.5 * (L / N) / CS
+    p = pkg.Plan(N, L, MU, NU, CS, CP)
+    p.set_precision(pkg.SBIEM_FP64 if precision == "fp64" else pkg.SBIEM_FP32CONV)
+    hist = _history(N, 200, seed=3)
+    tau, sig = p.stress(hist, dt)
+    w = midpoint_weights(N, L, CS, CP, dt)
+    rt, _ = stress_from_history(hist, dt, L, MU, CS, CP, np.zeros(N), w)
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    assert rel(tau, rt) < tol, rel(tau, rt)
+    assert np.max(np.abs(sig)) <= (1e-12 if precision == "fp64" else 1e-5) * np.max(np.abs(rt))
+    z = np.zeros_like(hist)
+    tz, sz = p.stress(z, dt)
+    assert not np.any(tz) and not np.any(sz)
+
+
+def test_stress_at_the_largest_size():
+    """N = 2^22, the largest size a plan accepts (FP32 ring of 51 GB, element
+    and mode transforms of 2048 points).  A slip held still over the window
+    leaves only the static terms, whose closed forms hold at any size
+    (sections 2.3 and 2.4 in the static limit): for u = D0 + D cos(k_m x) on
+    h = A sin(k_0 x), tau = -mu (1-r) k_m D cos(k_m x) and sigma =
+    mu (1-r) A k_0^2 [D0 cos(k_0 x) + D/2 (cos((k_0+k_m) x) + sgn(k_0-k_m)
+    cos((k_0-k_m) x))].  The exact weights of every mode are too costly for
+    the oracle at this size; the moving case is compared at N = 262144."""
+    pkg = _pkg()
+    N = 1 << 22
+    L = 10.0 * N
+    dt = 0.5 * (L / N) / CS
+    x = np.arange(N) * (L / N)
+    m0, mm, A, D0, D = 3000, 70001, 2.0, 0.7, 0.2
+    k0, km = 2 * np.pi * m0 / L, 2 * np.pi * mm / L
+    h = A * np.sin(k0 * x)
+    u = D0 + D * np.cos(km * x)
+    hist = np.repeat(u[None, :], 4, axis=0)
+    p = pkg.Plan(N, L, MU, NU, CS, CP, h)
+    p.set_precision(pkg.SBIEM_FP32CONV)
+    tau, sig = p.stress(hist, dt)
+    r = (CS / CP) ** 2
+    rt = -MU * (1 - r) * km * D * np.cos(km * x)
+    rs = MU * (1 - r) * A * k0 ** 2 * (D0 * np.cos(k0 * x) + 0.5 * D * (
+        np.cos((k0 + km) * x) + np.sign(k0 - km) * np.cos((k0 - km) * x)))
+    print("N=2^22 static stress:", rel(tau, rt), rel(sig, rs))
+    assert rel(tau, rt) < 1e-5 and rel(sig, rs) < 1e-5, (rel(tau, rt), rel(sig, rs))
+    p.close()
