@@ -533,6 +533,62 @@ __device__ __forceinline__ C* fft_batch(C* a, C* b, int nvec, int lm, const R* _
   return src;
 }
 
+// Forward FFT of nvec vectors of M = 64 E points (E = 1, 2, 4), one
+// wavefront per vector, held in registers.  With n = l + 64 e (lane l) and
+// k = k1 + E k2: E-point DFTs over e give k1, twiddles w_M^{l k1}, then
+// 64-point DFTs over the lanes by six radix-2 decimation-in-frequency stages
+// that exchange values with lane shuffles (no LDS passes, no barriers between
+// stages); lane l ends with k2 = bit-reverse(l).  Same layout as fft_batch
+// (a: natural order, padded; the result goes to b); ends with a barrier.
+template <typename C, typename R, int E>
+__device__ __forceinline__ C* fft_wave(const C* a, C* b, int nvec, const R* __restrict__ q) {
+  constexpr int M = 64 * E;
+  const int vs = vstride(M);
+  const int lane = threadIdx.x & 63;
+  const int v = threadIdx.x >> 6;
+  if (v < nvec) {
+    const C* s = a + v * vs;
+    C x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = s[lx(lane + 64 * e, 3)];
+    if (E == 2) dft2(x);
+    if (E == 4) dft4(x[0], x[1], x[2], x[3]);
+#pragma unroll
+    for (int k1 = 1; k1 < E; ++k1) x[k1] = cmul(x[k1], twiddle_full<C, R>(q, lane * k1, M));
+#pragma unroll
+    for (int h = 32; h >= 1; h >>= 1) {
+      const bool upper = (lane & h) != 0;
+      const C w = twiddle_half<C, R>(q, (lane & (h - 1)) * (M / (2 * h)), M);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        C p;
+        p.x = __shfl_xor(x[e].x, h);
+        p.y = __shfl_xor(x[e].y, h);
+        x[e] = upper ? cmul(csub(p, x[e]), w) : cadd(x[e], p);
+      }
+    }
+    const int k2 = (int)(__brev((unsigned)lane) >> 26);
+    C* d = b + v * vs;
+#pragma unroll
+    for (int e = 0; e < E; ++e) d[lx(e + E * k2, 3)] = x[e];
+  }
+  __syncthreads();
+  return b;
+}
+
+// The transform of nvec vectors of 2^lm points: register wave FFTs where one
+// wavefront per vector fits the workgroup and 64 <= M <= 256, else the LDS
+// Stockham passes.
+template <typename C, typename R>
+__device__ __forceinline__ C* fft_vectors(C* a, C* b, int nvec, int lm, const R* __restrict__ q) {
+  if (nvec * 64 <= (int)blockDim.x) {
+    if (lm == 6) return fft_wave<C, R, 1>(a, b, nvec, q);
+    if (lm == 7) return fft_wave<C, R, 2>(a, b, nvec, q);
+    if (lm == 8) return fft_wave<C, R, 4>(a, b, nvec, q);
+  }
+  return fft_batch<C, R>(a, b, nvec, lm, q);
+}
+
 // LDS table cos(2 pi r / M), r = 0..M/4, from the fault's N-point table.
 template <typename R>
 __device__ __forceinline__ void load_sub_table(R* q, const FaultDev& fd, int lm) {
@@ -770,7 +826,7 @@ k_modes(const FaultDev* __restrict__ faults, const int2* __restrict__ map, int m
   if (err) return;
   __syncthreads();
   C* X = bufA;
-  if (KIND != 0) X = fft_batch<C, R>(bufA, bufB, 2, lQ, q);
+  if (KIND != 0) X = fft_vectors<C, R>(bufA, bufB, 2, lQ, q);
 
   const double c = ldexp(1.0, e_in);
   double mt = 0.0, ms = 0.0;
@@ -871,7 +927,7 @@ k_modes(const FaultDev* __restrict__ faults, const int2* __restrict__ map, int m
   if (KIND == 0 && measure) return;
   if (g == 0 && threadIdx.x == 0) cells[4] = e_in;
   C* Xo = (X == bufA) ? bufB : bufA;
-  C* W = fft_batch<C, R>(X, Xo, 2, lQ, q);
+  C* W = fft_vectors<C, R>(X, Xo, 2, lQ, q);
   for (int t = threadIdx.x; t < nslot; t += blockDim.x) {
     const int v = t >> lQ, b = t & (Q - 1);
     const int cls = v ? cls1 : cls0;
@@ -1185,7 +1241,7 @@ k_elems(const FaultDev* __restrict__ faults, const int2* __restrict__ map,
   __syncthreads();
   C* X = bufA;
   if (KIND != 3) {
-    X = fft_batch<C, R>(bufA, bufB, nv, lP, q);
+    X = fft_vectors<C, R>(bufA, bufB, nv, lP, q);
     const double inv = 1.0 / N, invc = inv * ldexp(1.0, -e_used);
     auto element = [&](int t, const ElemIn& e) {
       const int v = t >> lP, a = t & (P - 1);
@@ -1211,7 +1267,7 @@ k_elems(const FaultDev* __restrict__ faults, const int2* __restrict__ map,
     __syncthreads();
   }
   C* Xo = (X == bufA) ? bufB : bufA;
-  C* Y = fft_batch<C, R>(X, Xo, nv, lP, q);
+  C* Y = fft_vectors<C, R>(X, Xo, nv, lP, q);
   if (KIND == 3) gF += (size_t)blockIdx.y * N;
   for (int t = threadIdx.x; t < E; t += blockDim.x) {
     const int v = t >> lP, cc = t & (P - 1);

@@ -245,7 +245,8 @@ def _workload_plan_and_oracle(w, nsteps):
     return p, o
 
 
-@pytest.mark.parametrize("name", ["rough-N65536", "ensemble16-N262144"])
+@pytest.mark.parametrize("name", ["seamount-N8192", "ensemble64-N16384", "rough-N65536",
+                                  "ensemble16-N262144"])
 def test_step_fp32_full_size_matches_oracle(name):
     """The first 20 steps of the full-size workloads (graph replay, as in
     bench.py) against the oracle, compared after a 16-step graph replay and
@@ -253,7 +254,12 @@ def test_step_fp32_full_size_matches_oracle(name):
     near steady state), the sum of much larger static and dynamic parts, so
     the FP32 gate of 1e-5 is taken relative to the larger part."""
     from sbiem_inputs import ensemble_members, workload
-    w = workload(name) if name != "ensemble16-N262144" else ensemble_members(name)[0]
+    if name == "ensemble16-N262144":
+        w = ensemble_members(name)[0]
+    elif name == "ensemble64-N16384":
+        w = [m for m in ensemble_members("ensemble64") if m.N == 16384][0]
+    else:
+        w = workload(name)
     p, o = _workload_plan_and_oracle(w, 20)
     worst = {"tau_el": 0.0, "sigma_el": 0.0, "slip": 0.0, "V": 0.0,
              "tau_el_plain": 0.0, "sigma_el_plain": 0.0}
@@ -431,3 +437,24 @@ def test_stress_at_the_largest_size():
     print("N=2^22 static stress:", rel(tau, rt), rel(sig, rs))
     assert rel(tau, rt) < 1e-5 and rel(sig, rs) < 1e-5, (rel(tau, rt), rel(sig, rs))
     p.close()
+
+
+@pytest.mark.parametrize("N", [4096, 16384, 65536])
+def test_stress_fp64_transform_sizes(N):
+    """FP64 stress path at the sizes whose element and mode transforms run as
+    register wave FFTs (64, 128 and 256 points per class) against the oracle."""
+    from oracle.spectral import curvature_fft
+    from oracle.stress import stress_from_history
+    from oracle.windows import midpoint_weights
+    from sbiem_inputs import rough_fault
+    pkg = _pkg()
+    L = 10.0 * N
+    dt = 0.5 * (L / N) / CS
+    h = rough_fault(N, L, 3e-3, N)
+    nt = 6
+    hist = _history(N, nt, seed=N + 1)
+    p = pkg.Plan(N, L, MU, NU, CS, CP, h)
+    tau, sig = p.stress(hist, dt)
+    w = midpoint_weights(N, L, CS, CP, dt, max_lag=nt)
+    rt, rs = stress_from_history(hist, dt, L, MU, CS, CP, curvature_fft(h, L), w, transform="fft")
+    assert rel(tau, rt) < 1e-10 and rel(sig, rs) < 1e-9, (rel(tau, rt), rel(sig, rs))
