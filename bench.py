@@ -99,15 +99,19 @@ def train_closure(pkg):
     return pT, pN, info
 
 
-def traffic_from_profiles(workload: str):
+def traffic_from_profiles(workload: str, closure: bool, alg_bytes: float):
     """HBM bytes per conv launch from committed rocprofv3 counter summaries,
-    if they were taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"conv_traffic_{workload}.json")
+    if they were taken on the current kernel source and on this very launch
+    (same workload, same form, same algorithmic bytes)."""
+    tag = workload + ("-closure" if closure else "")
+    path = os.path.join(ROOT, "profiles", f"conv_traffic_{tag}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         z = json.load(f)
     if z.get("kernel_sha256_16") != kernel_hash():
+        return None
+    if z.get("algorithmic_bytes_per_launch") != alg_bytes:
         return None
     return z.get("bytes_per_launch")
 
@@ -211,7 +215,7 @@ def main():
     achieved = conv_bytes / (avg_ms * 1e-3) / 1e9
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(args.workload),
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(args.workload, args.closure, conv_bytes),
         "kernel": "k_conv32" if w.precision != "fp64" else "k_conv64", "conv_workgroups": conv_grid,
         "bytes_per_launch": conv_bytes, "avg_launch_us": round(avg_ms * 1e3, 3),
         "launches": conv_n,

@@ -137,15 +137,27 @@ template <> struct Prec<double> {
 // with o = (-b) mod R_n: q = 0 is the skipped slot, lag j = R_n - q + 1
 // otherwise.
 // ---------------------------------------------------------------------------
+// Wavefront sum without LDS traffic: DPP exchanges inside each row of 16
+// lanes (quad swaps, then half-row and row mirrors leave every lane with its
+// row's sum), then the four row sums read from lanes 0, 16, 32, 48.  The
+// result is uniform and its summation order fixed.
+template <int C>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), C, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_mov<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_mov<0x141>(v);  // row_half_mirror
+  v += dpp_mov<0x140>(v);  // row_mirror
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+  return (r0 + r1) + (r2 + r3);
+}
 __device__ __forceinline__ float4 wave_reduce4(float4 v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    v.x += __shfl_xor(v.x, off);
-    v.y += __shfl_xor(v.y, off);
-    v.z += __shfl_xor(v.z, off);
-    v.w += __shfl_xor(v.w, off);
-  }
-  return v;
+  return make_float4(wave_sum(v.x), wave_sum(v.y), wave_sum(v.z), wave_sum(v.w));
 }
 __device__ __forceinline__ Rec64 wave_reduce_r64(Rec64 v) {
 #pragma unroll
@@ -201,7 +213,12 @@ __device__ __forceinline__ void finish_task(const FaultDev& fd, const TaskLds& L
       a.z += b.z;
       a.w += b.w;
     }
-    fd.parts[L.id[k]] = a;
+    // a global-segment store: a flat store counts as a possible LDS access,
+    // and the waits for records in flight behind it would then drain them all
+    typedef double d4v __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(1))) d4v* gd4p;
+    const d4v v = {a.x, a.y, a.z, a.w};
+    ((gd4p)(d4v*)fd.parts)[L.id[k]] = v;
   }
 }
 
