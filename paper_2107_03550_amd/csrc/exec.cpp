@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <utility>
 
 #include "internal.h"
 
@@ -334,18 +335,24 @@ int ready(sbiem_plan* p, double dt) {
 
 // One step in steady state: the next step's history sums on the second
 // stream beside the element/mode stages of this step, joined before the
-// commit launch that consumes them.
+// commit launch that consumes them.  Both the conv launch and the first
+// element launch wait only for the previous step's commit; the one enqueued
+// first follows the commit on its hardware queue, the other crosses queues,
+// which costs microseconds (most in a replayed graph).  stages_first puts the
+// element/mode chain first: it pays where that chain is the step's critical
+// path (small rings), and the conv-first order where the conv is.
 // While profiling, events e0/e1 bracket the conv launch.
 hipError_t launch_step(Exec& ex, hipStream_t s, hipStream_t aux, bool profile, hipEvent_t e0,
                        hipEvent_t e1) {
   hipError_t e = hipEventRecord(ex.fork, s);
+  if (!e && ex.stages_first) e = launch_elems(ex, 1, s);
   if (!e) e = hipStreamWaitEvent(aux, ex.fork, 0);
   if (!e && profile) e = hipEventRecord(e0, aux);
   if (!e) e = launch_conv(ex, 1, aux);
   if (!e && profile) e = hipEventRecord(e1, aux);
   if (!e) e = launch_closure(ex, 1, aux);
   if (!e) e = hipEventRecord(ex.join, aux);
-  if (!e) e = launch_elems(ex, 1, s);
+  if (!e && !ex.stages_first) e = launch_elems(ex, 1, s);
   if (!e) e = launch_modes(ex, 1, 0, s);
   if (!e) e = launch_elems(ex, 2, s);
   if (!e) e = hipStreamWaitEvent(s, ex.join, 0);
@@ -470,11 +477,12 @@ hipError_t run_steps(Exec* ex, int64_t nsteps, hipStream_t s, bool profile, Even
   return e;
 }
 
-// Autotuning of the convolution grid: whole steps are replayed from the
-// step graph with each candidate number of conv workgroups (events on s
-// around chunks of graph launches), and the fastest is kept.  Results do not
-// depend on the grid (every task writes its own partial sums), so the trial
-// steps are ordinary steps of the simulation.
+// Autotuning of the convolution launch: whole steps are replayed from the
+// step graph with each candidate number of conv workgroups, in either launch
+// order (events on s around chunks of graph launches), and the fastest is
+// kept.  Results do not depend on either (every task writes its own partial
+// sums, and the dependencies are the same), so the trial steps are ordinary
+// steps of the simulation.
 hipError_t tune_conv(Exec* ex, int64_t steps_per_trial, hipStream_t s, int* chosen,
                      const char** what) {
   *chosen = ex->conv_grid;
@@ -482,21 +490,24 @@ hipError_t tune_conv(Exec* ex, int64_t steps_per_trial, hipStream_t s, int* chos
   *what = "running the prologue launches";
   hipError_t e = prologue(*ex, s);
   if (e) return e;
-  std::vector<int> cand;
-  for (int reserve : {0, 64, 128, 192}) {
-    const int g = conv_grid_size(ex->precision, ex->ntasks, ex->table_len, reserve);
-    if (std::find(cand.begin(), cand.end(), g) == cand.end()) cand.push_back(g);
-  }
+  std::vector<std::pair<int, bool>> cand;
+  for (bool first : {false, true})
+    for (int reserve : {0, 64, 128, 192}) {
+      const std::pair<int, bool> g(conv_grid_size(ex->precision, ex->ntasks, ex->table_len, reserve),
+                                   first);
+      if (std::find(cand.begin(), cand.end(), g) == cand.end()) cand.push_back(g);
+    }
   const int64_t chunks = std::max<int64_t>(1, steps_per_trial / kGraphSteps);
   hipEvent_t a = nullptr, b = nullptr;
   *what = "creating tuning events";
   e = hipEventCreate(&a);
   if (!e) e = hipEventCreate(&b);
   float best_ms = 0.f;
-  int best = ex->conv_grid;
+  std::pair<int, bool> best(ex->conv_grid, ex->stages_first);
   for (size_t c = 0; c < cand.size() && !e; ++c) {
     ex->drop_graph();
-    ex->conv_grid = cand[c];
+    ex->conv_grid = cand[c].first;
+    ex->stages_first = cand[c].second;
     *what = "capturing the step graph";
     e = ensure_graph(ex, s);
     *what = "launching tuning steps";
@@ -515,8 +526,9 @@ hipError_t tune_conv(Exec* ex, int64_t steps_per_trial, hipStream_t s, int* chos
   if (a) (void)hipEventDestroy(a);
   if (b) (void)hipEventDestroy(b);
   ex->drop_graph();
-  ex->conv_grid = best;
-  *chosen = best;
+  ex->conv_grid = best.first;
+  ex->stages_first = best.second;
+  *chosen = best.first;
   return e;
 }
 

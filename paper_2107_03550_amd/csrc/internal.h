@@ -232,6 +232,7 @@ struct Exec {
   const float4* table = nullptr;  // FP32 kernel table (shared by all faults)
   int table_len = 0;
   int conv_grid = 0;
+  bool stages_first = false;     // enqueue a step's first stage launch before its conv launch
   int* conv_ctr = nullptr;        // FP32 conv: dynamic task counter (zeroed by the mode launch after it)
   ClosureMode* closure_modes = nullptr;  // closed modes of every fault (null: no closure)
   int nclosure = 0;
