@@ -9,7 +9,7 @@ One "step" is the whole two-pass time step (history convolution, FFTs,
 traction assembly, friction solve, commit) of the named workload with its
 inputs resident in HBM.  Prints one JSON line with element-steps/s, the
 roofline position of the history-convolution kernel (HIP events around its
-launches in one step of every 17 of the timed region, the others replayed
+launches in one step of every 33 of the timed region, the others replayed
 from the step graph) and the CPU oracle timed on a bounded sample of the
 same workload.
 """
@@ -189,7 +189,7 @@ def main():
     run(max(0, args.warmup - tuned_steps))
     torch.cuda.synchronize()
 
-    # timed region: K steps; one step in every 17 launched directly with its
+    # timed region: K steps; one step in every 33 launched directly with its
     # conv launch bracketed by HIP events on the stream the conv kernel is
     # launched on, the others replayed from the step graph
     runner.set_profiling(True)

@@ -203,7 +203,7 @@ int sbiem_kernel_eval(double cs, double cp, const double* T, int64_t n, double* 
                       double* CN, double* dCT, double* dCN);
 
 /* Per-launch timing of the history-convolution kernel with HIP events on
- * the stream it runs on.  While on, sbiem_run launches one step in every 17
+ * the stream it runs on.  While on, sbiem_run launches one step in every 33
  * directly, its convolution bracketed by two events, and replays the other
  * steps from the step graph (results are identical either way).
  * sbiem_profile returns the accumulated

@@ -12,6 +12,7 @@ namespace sbiem {
 
 namespace {
 constexpr int kGraphSteps = 16;  // steps captured in one replayable graph
+constexpr int kProfileGraphs = 2;  // graphs replayed between two evented steps
 }
 
 Exec::~Exec() {
@@ -412,11 +413,12 @@ hipError_t ensure_graph(Exec* ex, hipStream_t s) {
 }
 
 // Run nsteps of an execution context on stream s.  While profiling, one
-// step in every kGraphSteps + 1 is launched directly with a pair of events
-// around its conv launch and the others are replayed from the step graph as
-// usual (HIP graphs do not give usable times for event nodes), so the timed
-// steps run at the graph's pace; no host synchronisation inside a chunk of
-// steps, the elapsed times are summed once the chunk has finished.
+// step in every kProfileGraphs * kGraphSteps + 1 is launched directly with a
+// pair of events around its conv launch and the others are replayed from the
+// step graph as usual (HIP graphs do not give usable times for event nodes;
+// a directly launched step costs several graph steps, so the sample is kept
+// sparse); no host synchronisation inside a chunk of steps, the elapsed times
+// are summed once the chunk has finished.
 hipError_t run_steps(Exec* ex, int64_t nsteps, hipStream_t s, bool profile, EventPool* pool,
                      double* prof_ms, int64_t* prof_launches, const char** what) {
   *what = "running the time steps";
@@ -441,7 +443,7 @@ hipError_t run_steps(Exec* ex, int64_t nsteps, hipStream_t s, bool profile, Even
         e = launch_step(*ex, s, ex->aux, true, pool->ev[2 * timed], pool->ev[2 * timed + 1]);
         ++timed;
         --left;
-        if (!e && left >= kGraphSteps) {
+        for (int g = 0; g < kProfileGraphs && !e && left >= kGraphSteps; ++g) {
           *what = "launching the step graph";
           e = hipGraphLaunch(ex->graph, s);
           left -= kGraphSteps;
