@@ -341,19 +341,29 @@ int ready(sbiem_plan* p, double dt) {
 // first follows the commit on its hardware queue, the other crosses queues,
 // which costs microseconds (most in a replayed graph).  stages_first puts the
 // element/mode chain first: it pays where that chain is the step's critical
-// path (small rings), and the conv-first order where the conv is.
+// path (small rings), and the conv-first order where the conv is.  The
+// closure network (when on) follows the conv on its stream, or with
+// closure_main precedes the first stage launch: it reads only ring records
+// the step does not write before its commit and writes only the tails the
+// commit reads, so it may run beside the conv; on the stage stream it
+// shortens the conv's path where the stages have time to spare.
 // While profiling, events e0/e1 bracket the conv launch.
 hipError_t launch_step(Exec& ex, hipStream_t s, hipStream_t aux, bool profile, hipEvent_t e0,
                        hipEvent_t e1) {
+  auto stages_start = [&]() {
+    hipError_t r = ex.closure_main ? launch_closure(ex, 1, s) : hipSuccess;
+    if (!r) r = launch_elems(ex, 1, s);
+    return r;
+  };
   hipError_t e = hipEventRecord(ex.fork, s);
-  if (!e && ex.stages_first) e = launch_elems(ex, 1, s);
+  if (!e && ex.stages_first) e = stages_start();
   if (!e) e = hipStreamWaitEvent(aux, ex.fork, 0);
   if (!e && profile) e = hipEventRecord(e0, aux);
   if (!e) e = launch_conv(ex, 1, aux);
   if (!e && profile) e = hipEventRecord(e1, aux);
-  if (!e) e = launch_closure(ex, 1, aux);
+  if (!e && !ex.closure_main) e = launch_closure(ex, 1, aux);
   if (!e) e = hipEventRecord(ex.join, aux);
-  if (!e && !ex.stages_first) e = launch_elems(ex, 1, s);
+  if (!e && !ex.stages_first) e = stages_start();
   if (!e) e = launch_modes(ex, 1, 0, s);
   if (!e) e = launch_elems(ex, 2, s);
   if (!e) e = hipStreamWaitEvent(s, ex.join, 0);
@@ -481,8 +491,8 @@ hipError_t run_steps(Exec* ex, int64_t nsteps, hipStream_t s, bool profile, Even
 
 // Autotuning of the convolution launch: whole steps are replayed from the
 // step graph with each candidate number of conv workgroups, in either launch
-// order (events on s around chunks of graph launches), and the fastest is
-// kept.  Results do not depend on either (every task writes its own partial
+// order and, with the closure on, with the closure network on either stream
+// (events on s around chunks of graph launches), and the fastest is kept.  Results do not depend on either (every task writes its own partial
 // sums, and the dependencies are the same), so the trial steps are ordinary
 // steps of the simulation.
 hipError_t tune_conv(Exec* ex, int64_t steps_per_trial, hipStream_t s, int* chosen,
@@ -492,24 +502,36 @@ hipError_t tune_conv(Exec* ex, int64_t steps_per_trial, hipStream_t s, int* chos
   *what = "running the prologue launches";
   hipError_t e = prologue(*ex, s);
   if (e) return e;
-  std::vector<std::pair<int, bool>> cand;
-  for (bool first : {false, true})
-    for (int reserve : {0, 64, 128, 192}) {
-      const std::pair<int, bool> g(conv_grid_size(ex->precision, ex->ntasks, ex->table_len, reserve),
-                                   first);
-      if (std::find(cand.begin(), cand.end(), g) == cand.end()) cand.push_back(g);
+  struct Shape {
+    int grid;
+    bool first, cmain;
+    bool operator==(const Shape& o) const {
+      return grid == o.grid && first == o.first && cmain == o.cmain;
     }
+  };
+  const bool closure = ex->closure_modes && ex->nclosure > 0;
+  std::vector<Shape> cand;
+  for (bool cmain : {false, true}) {
+    if (cmain && !closure) continue;
+    for (bool first : {false, true})
+      for (int reserve : {0, 64, 128, 192}) {
+        const Shape g{conv_grid_size(ex->precision, ex->ntasks, ex->table_len, reserve), first,
+                      cmain};
+        if (std::find(cand.begin(), cand.end(), g) == cand.end()) cand.push_back(g);
+      }
+  }
   const int64_t chunks = std::max<int64_t>(1, steps_per_trial / kGraphSteps);
   hipEvent_t a = nullptr, b = nullptr;
   *what = "creating tuning events";
   e = hipEventCreate(&a);
   if (!e) e = hipEventCreate(&b);
   float best_ms = 0.f;
-  std::pair<int, bool> best(ex->conv_grid, ex->stages_first);
+  Shape best{ex->conv_grid, ex->stages_first, ex->closure_main};
   for (size_t c = 0; c < cand.size() && !e; ++c) {
     ex->drop_graph();
-    ex->conv_grid = cand[c].first;
-    ex->stages_first = cand[c].second;
+    ex->conv_grid = cand[c].grid;
+    ex->stages_first = cand[c].first;
+    ex->closure_main = cand[c].cmain;
     *what = "capturing the step graph";
     e = ensure_graph(ex, s);
     *what = "launching tuning steps";
@@ -528,9 +550,10 @@ hipError_t tune_conv(Exec* ex, int64_t steps_per_trial, hipStream_t s, int* chos
   if (a) (void)hipEventDestroy(a);
   if (b) (void)hipEventDestroy(b);
   ex->drop_graph();
-  ex->conv_grid = best.first;
-  ex->stages_first = best.second;
-  *chosen = best.first;
+  ex->conv_grid = best.grid;
+  ex->stages_first = best.first;
+  ex->closure_main = best.cmain;
+  *chosen = best.grid;
   return e;
 }
 

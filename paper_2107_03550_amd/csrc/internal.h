@@ -233,6 +233,7 @@ struct Exec {
   int table_len = 0;
   int conv_grid = 0;
   bool stages_first = false;     // enqueue a step's first stage launch before its conv launch
+  bool closure_main = false;     // closure network on the stage stream (before the first stage)
   int* conv_ctr = nullptr;        // FP32 conv: dynamic task counter (zeroed by the mode launch after it)
   ClosureMode* closure_modes = nullptr;  // closed modes of every fault (null: no closure)
   int nclosure = 0;
