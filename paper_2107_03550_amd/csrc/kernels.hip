@@ -338,6 +338,13 @@ __device__ __forceinline__ float4 conv32_weigh(const Tile& tl, long long step, i
   const int end = tl.p0 + tl.len;
 #pragma unroll
   for (int u = 0; u < kConvU; ++u) {
+    if (64 * u >= tl.len) {
+      // a row past the tile's end (short modes, most of them under the
+      // learned closure): no weights, only mark its registers as read so
+      // that every row still waits for exactly its own loads
+      asm volatile("" ::"v"(h[u].x), "v"(h[u].y), "v"(h[u].z), "v"(h[u].w));
+      continue;
+    }
     const int p = tl.p0 + lane + 64 * u;
     int q = p + o;
     q -= (q >= Rn) ? Rn : 0;
