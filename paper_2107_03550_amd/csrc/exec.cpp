@@ -99,6 +99,15 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
       }
     }
   }
+  if (precision == SBIEM_FP32CONV) {
+    ex->tile_rows = dts[0]->tile_slots / 64;
+    for (int f = 1; f < ex->nfaults; ++f)
+      if (dts[f]->tile_slots != dts[0]->tile_slots) {
+        *err = "FP32 batch members must share the conv tile size (closure setting)";
+        delete ex;
+        return SBIEM_EINVAL;
+      }
+  }
   if (precision == SBIEM_FP32CONV && ex->nfaults > 1) {
     // all faults must share the table (same dt, c_s, c_p)
     for (int f = 0; f < ex->nfaults; ++f) {

@@ -130,9 +130,16 @@ constexpr int kConvThreads = 512;   // 8 wavefronts
 constexpr int kTileSlots32 = 512;   // FP32 records per wavefront tile
 constexpr int kWaveTiles32 = 2;     // FP32 tiles per wavefront and task
 constexpr int kTaskTiles32 = kWaveTiles32 * (kConvThreads / 64);
+// FP32 tiles of the short windows the learned closure keeps: half the
+// records per tile, twice the tiles per wave (the same 16 rows of 64
+// records in flight per wave)
+constexpr int kTileSlots32s = 256;
+constexpr int kWaveTiles32s = 4;
+constexpr int kTaskTiles32s = kWaveTiles32s * (kConvThreads / 64);
 constexpr int kTileSlots64 = 256;   // FP64 records per wavefront tile
 constexpr int kTaskTiles64 = 16;
-constexpr int kTaskTiles = kTaskTiles32 > kTaskTiles64 ? kTaskTiles32 : kTaskTiles64;  // at most
+constexpr int kTaskTiles = kTaskTiles32s > kTaskTiles64 ? kTaskTiles32s : kTaskTiles64;  // at most
+static_assert(kTaskTiles >= kTaskTiles32 && kTaskTiles >= kTaskTiles32s, "task slots");
 constexpr int kModeThreads = 256;   // mode-stage workgroups
 constexpr int kElemThreads = 256;   // element-stage workgroups
 constexpr double kTableStep = 1.0 / 16.0;  // spacing of the FP32 kernel table in T
@@ -177,6 +184,7 @@ struct DtData {
   std::vector<long long> ring_off;
   long long ring_slots = 0;
   std::vector<Tile> tiles;       // this fault's tiles (fault field = 0)
+  int tile_slots = 0;            // records per tile
   std::vector<ConvTask> tasks;   // this fault's tasks (tile indices local)
   std::vector<int> part0, nparts;
   int table_len = 0;             // FP32 table nodes
@@ -232,6 +240,7 @@ struct Exec {
   const float4* table = nullptr;  // FP32 kernel table (shared by all faults)
   int table_len = 0;
   int conv_grid = 0;
+  int tile_rows = kTileSlots32 / 64;  // FP32: 64-record rows per conv tile (8, or 4 for short windows)
   bool stages_first = false;     // enqueue a step's first stage launch before its conv launch
   bool closure_main = false;     // closure network on the stage stream (before the first stage)
   int* conv_ctr = nullptr;        // FP32 conv: dynamic task counter (zeroed by the mode launch after it)

@@ -289,11 +289,12 @@ k_conv64(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
 // table coordinate (2j + 1) theta_n / h is formed in FP64 so that the phase
 // keeps full accuracy at T ~ 200.
 //
-// Each wave of a workgroup task owns tiles k = wave and k = wave + W (W
-// waves per workgroup).  The records of the next task's tiles are requested
-// as soon as the registers of the current tile are free, so loads stay in
+// Each wave of a workgroup task owns tiles k = wave + W i, i < K (W waves
+// per workgroup); a tile is U rows of 64 records (U K = 16 rows per wave:
+// 2 tiles of 8 rows for full windows, 4 of 4 for the short windows of the
+// learned closure).  The records of the next task's tiles are requested as
+// soon as the registers of the current tile are free, so loads stay in
 // flight across the weighting, the wave reductions and the task's barriers.
-constexpr int kConvU = kTileSlots32 / 64;
 
 // Per-fault words that a launch only reads (failure flag, step counter) are
 // read with scalar loads: the vector-memory counter then tracks record loads
@@ -317,19 +318,21 @@ __device__ __forceinline__ long long read_word(const long long* p) {
 // issued after them and never drains the next task's loads.
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(1))) f4v* gf4p;
+template <int U>
 __device__ __forceinline__ void conv32_load(const Tile& tl, bool has, int lane, const float4* dummy,
-                                            float4 (&h)[kConvU]) {
+                                            float4 (&h)[U]) {
   const gf4p rec = has ? (gf4p)(const float4*)tl.rec + tl.p0 : (gf4p)dummy;
   const int last = has ? tl.len - 1 : 3;
 #pragma unroll
-  for (int u = 0; u < kConvU; ++u) {
+  for (int u = 0; u < U; ++u) {
     const f4v t = __builtin_nontemporal_load(rec + min(lane + 64 * u, last));
     h[u] = make_float4(t.x, t.y, t.z, t.w);
   }
 }
 
+template <int U>
 __device__ __forceinline__ float4 conv32_weigh(const Tile& tl, long long step, int lane,
-                                               const float4 (&h)[kConvU], const float4* tab,
+                                               const float4 (&h)[U], const float4* tab,
                                                int table_len) {
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
   const int Rn = tl.Rn;
@@ -337,7 +340,7 @@ __device__ __forceinline__ float4 conv32_weigh(const Tile& tl, long long step, i
   const double th = tl.th;
   const int end = tl.p0 + tl.len;
 #pragma unroll
-  for (int u = 0; u < kConvU; ++u) {
+  for (int u = 0; u < U; ++u) {
     if (64 * u >= tl.len) {
       // a row past the tile's end (short modes, most of them under the
       // learned closure): no weights, only mark its registers as read so
@@ -371,6 +374,7 @@ __device__ __forceinline__ float4 conv32_weigh(const Tile& tl, long long step, i
   return acc;
 }
 
+template <int U, int K>
 __global__ void __launch_bounds__(kConvThreads)
 k_conv32(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
          const ConvTask* __restrict__ tasks, int ntasks, const float4* __restrict__ table,
@@ -390,16 +394,16 @@ k_conv32(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
   int nxt = blockIdx.x + gridDim.x;
   const int dyn0 = 2 * gridDim.x;
   ConvTask tk = task < ntasks ? tasks[task] : ConvTask{0, 0};
-  constexpr int K = kWaveTiles32;
+  static_assert(U * K == 16, "16 rows in flight per wave");
   Tile t[K];
   bool has[K];
-  float4 h[K][kConvU];
+  float4 h[K][U];
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     has[i] = task < ntasks && wave + wpb * i < tk.t1 - tk.t0;
     t[i] = has[i] ? tiles[tk.t0 + wave + wpb * i] : Tile{};
 #pragma unroll
-    for (int u = 0; u < kConvU; ++u) h[i][u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int u = 0; u < U; ++u) h[i][u] = make_float4(0.f, 0.f, 0.f, 0.f);
     conv32_load(t[i], has[i], lane, table, h[i]);
   }
   // the table is staged while the first records are in flight
@@ -1397,8 +1401,11 @@ hipError_t setup_kernel_attributes(int precision) {
   if (done[idx]) return hipSuccess;
   hipError_t e = idx ? set_attributes<float>() : set_attributes<double>();
   if (!e && idx)
-    e = hipFuncSetAttribute((const void*)k_conv32, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kMaxDynLds);
+    e = hipFuncSetAttribute((const void*)k_conv32<8, 2>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+  if (!e && idx)
+    e = hipFuncSetAttribute((const void*)k_conv32<4, 4>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
   if (!e) done[idx] = true;
   return e;
 }
@@ -1431,8 +1438,16 @@ hipError_t launch_conv(const Exec& ex, int ahead, hipStream_t s) {
   if (ex.ntasks == 0) return hipSuccess;
   if (ex.precision == SBIEM_FP32CONV) {
     const size_t lds = (size_t)ex.table_len * sizeof(float4);
-    hipLaunchKernelGGL(k_conv32, dim3(ex.conv_grid), dim3(kConvThreads), lds, s, ex.d_faults,
-                       ex.d_tiles, ex.d_tasks, ex.ntasks, ex.table, ex.table_len, ahead, ex.conv_ctr);
+    static_assert(kTileSlots32 == 8 * 64 && kWaveTiles32 == 2, "tile shape");
+    static_assert(kTileSlots32s == 4 * 64 && kWaveTiles32s == 4, "short tile shape");
+    if (ex.tile_rows == 4)
+      hipLaunchKernelGGL((k_conv32<4, 4>), dim3(ex.conv_grid), dim3(kConvThreads), lds, s,
+                         ex.d_faults, ex.d_tiles, ex.d_tasks, ex.ntasks, ex.table, ex.table_len,
+                         ahead, ex.conv_ctr);
+    else
+      hipLaunchKernelGGL((k_conv32<8, 2>), dim3(ex.conv_grid), dim3(kConvThreads), lds, s,
+                         ex.d_faults, ex.d_tiles, ex.d_tasks, ex.ntasks, ex.table, ex.table_len,
+                         ahead, ex.conv_ctr);
   } else {
     hipLaunchKernelGGL(k_conv64, dim3(ex.conv_grid), dim3(kConvThreads), 0, s, ex.d_faults,
                        ex.d_tiles, ex.d_tasks, ex.ntasks, ahead);

@@ -187,8 +187,15 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
   // conv tiles (one wavefront each) and tasks (one workgroup each): a task
   // holds whole modes up to task_tiles tiles, a longer mode is cut into
   // pieces of task_tiles tiles
-  const int tile = p->precision == SBIEM_FP32CONV ? kTileSlots32 : kTileSlots64;
-  const int task_tiles = p->precision == SBIEM_FP32CONV ? kTaskTiles32 : kTaskTiles64;
+  // (FP32 under the learned closure: shorter tiles, most kept windows being
+  // far shorter than a full tile)
+  const bool short_tiles = p->precision == SBIEM_FP32CONV && p->closure_on;
+  const int tile = p->precision == SBIEM_FP32CONV ? (short_tiles ? kTileSlots32s : kTileSlots32)
+                                                  : kTileSlots64;
+  const int task_tiles = p->precision == SBIEM_FP32CONV
+                             ? (short_tiles ? kTaskTiles32s : kTaskTiles32)
+                             : kTaskTiles64;
+  d->tile_slots = tile;
   const long double th_unit = 3.141592653589793238462643383279502884L * (long double)p->cs *
                               (long double)dt / (long double)p->L / (long double)kTableStep;
   d->part0.assign(half + 1, 0);
