@@ -231,8 +231,8 @@ int sbiem_batch_profile(sbiem_batch* b, double* conv_ms, int64_t* conv_launches,
 /* Autotuning of the history-convolution launch for this plan's (or batch's)
  * workload: whole steps are replayed with each candidate number of
  * convolution workgroups (the full resident grid, and grids that leave one
- * workgroup fewer on 64, 128 or 192 CUs so that the element and mode
- * launches of the step run beside it), each with the convolution or the
+ * workgroup fewer on 64, 128, 192 or all 256 CUs so that the element and
+ * mode launches of the step run beside it), each with the convolution or the
  * first element launch enqueued first after the previous step's commit and,
  * with the learned closure on, with its network launched after the
  * convolution or before the first element launch, steps_per_trial steps
@@ -241,7 +241,7 @@ int sbiem_batch_profile(sbiem_batch* b, double* conv_ms, int64_t* conv_launches,
  * sbiem_set_precision, sbiem_set_closure).  The trial steps are ordinary
  * steps: results do not depend on the launch shape or order, and the state
  * advances by about (steps_per_trial + 16) times the number of candidates
- * (at most 8, 16 with the closure).  *conv_workgroups (may be NULL) receives
+ * (at most 10, 20 with the closure).  *conv_workgroups (may be NULL) receives
  * the chosen grid.  FP64 plans have nothing to tune (OK).  Errors as
  * sbiem_run; a plan used by a batch is tuned through the batch. */
 int sbiem_tune(sbiem_plan* p, double dt, int64_t steps_per_trial, int32_t* conv_workgroups);

@@ -523,7 +523,7 @@ hipError_t tune_conv(Exec* ex, int64_t steps_per_trial, hipStream_t s, int* chos
   for (bool cmain : {false, true}) {
     if (cmain && !closure) continue;
     for (bool first : {false, true})
-      for (int reserve : {0, 64, 128, 192}) {
+      for (int reserve : {0, 64, 128, 192, 256}) {
         const Shape g{conv_grid_size(ex->precision, ex->ntasks, ex->table_len, reserve), first,
                       cmain};
         if (std::find(cand.begin(), cand.end(), g) == cand.end()) cand.push_back(g);
