@@ -92,7 +92,9 @@ const char* sbiem_status_string(int status);
  *   cs, cp  shear and dilatational wave speeds [m/s], 0 < cs < cp
  *   h       fault profile h(x_i) [m], length N, copied; NULL = planar.
  *           The curvature kappa = h'' (section 2.2, small-slope
- *           approximation) is computed spectrally on the device in FP64.
+ *           approximation) is computed spectrally on the host in extended
+ *           (long double) precision: kappa = IDFT(-k_n^2 DFT(h)), Nyquist
+ *           term kept, then rounded to FP64 and uploaded.
  * Selects a device (the current HIP device) and allocates the per-element
  * buffers.  Errors: EINVAL (bad arguments, non-finite h), EDEVICE, ENOMEM.
  * On error *out is NULL. */
@@ -114,6 +116,14 @@ int sbiem_set_precision(sbiem_plan* p, int mode);
 /* Choose SBIEM_THETA_PAPER (default) or SBIEM_THETA_EXP; may change
  * between steps. */
 int sbiem_set_theta_mode(sbiem_plan* p, int mode);
+
+/* Iteration limit of the double-precision Newton phase of each element's
+ * momentum balance (section 3.3; default 100, 0 restores it; at most 1000).
+ * A solve that has not converged within the limit fails the step with
+ * SBIEM_ENEWTON (section 3.2's "Newton-Raphson did not converge"); small
+ * limits force that failure from the host.  May change between steps.
+ * Errors: EINVAL (out of range). */
+int sbiem_set_newton_limit(sbiem_plan* p, int max_iterations);
 
 /* Rate-and-state friction and loading (section 3, eq. momentum; aging law).
  *   a, b         [N] direct and evolution effects (a > 0)
@@ -141,7 +151,9 @@ int sbiem_set_state(sbiem_plan* p, const double* slip, const double* V,
 int sbiem_get_state(sbiem_plan* p, double* slip, double* V, double* theta,
                     double* tau_el, double* sigma_el, double* t);
 
-/* The device-computed curvature kappa = h'' [1/m], length N. */
+/* The plan's curvature kappa = h'' [1/m], length N, as the kernels use it
+ * (the FP64 rounding of the extended-precision spectral second derivative
+ * computed by sbiem_plan_create). */
 int sbiem_get_curvature(const sbiem_plan* p, double* kappa);
 
 /* Fix the time step dt [s] (> 0): computes the windows M_n (section 3.1:

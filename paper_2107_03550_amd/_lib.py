@@ -55,6 +55,7 @@ _SIGS = {
     "sbiem_last_error": (ctypes.c_char_p, [_PLAN]),
     "sbiem_set_precision": (_int, [_PLAN, _int]),
     "sbiem_set_theta_mode": (_int, [_PLAN, _int]),
+    "sbiem_set_newton_limit": (_int, [_PLAN, _int]),
     "sbiem_set_friction": (_int, [_PLAN, _D, _D, _dbl, _dbl, _dbl, _D, _D, _dbl, _dbl]),
     "sbiem_set_state": (_int, [_PLAN, _D, _D, _D, _dbl]),
     "sbiem_get_state": (_int, [_PLAN, _D, _D, _D, _D, _D, _D]),
@@ -184,6 +185,13 @@ def set_torch_allocator():
     _check(lib.sbiem_set_allocator(a, f, None))
 
 
+def set_default_allocator():
+    """Back to hipMalloc/hipFree for memory allocated from now on (memory
+    already allocated through torch must have been released first)."""
+    _check(lib.sbiem_set_allocator(_ALLOC(), _FREE(), None))
+    _torch_alloc_refs[:] = []
+
+
 class Plan:
     """One fault (wraps sbiem_plan)."""
 
@@ -212,6 +220,9 @@ class Plan:
 
     def set_theta_mode(self, mode):
         self._c(lib.sbiem_set_theta_mode(self.handle, mode))
+
+    def set_newton_limit(self, max_iterations):
+        self._c(lib.sbiem_set_newton_limit(self.handle, int(max_iterations)))
 
     def set_friction(self, a, b, Dc, V_ref, f0, sigma_load, tau_load, tau_load_rate=0.0, V_pl=0.0):
         n = self.N

@@ -67,6 +67,7 @@ struct FaultDev {
   int ngroups;              // mode workgroups: classes {g, P-g} (g = 0: {0, P/2})
   int ncls;                 // element classes per element workgroup
   int theta_mode;
+  int newton_max;           // FP64 Newton iterations of the momentum balance
   double L, mu, r, cs, dt, eta_rad;
   double V_pl, Dc, V_ref, f0, tau_rate, t0, ln_V_ref;
 
@@ -272,6 +273,7 @@ struct sbiem_plan {
   double L = 0, mu = 0, nu = 0, cs = 0, cp = 0, r = 0;
   int precision = SBIEM_FP64;
   int theta_mode = SBIEM_THETA_PAPER;
+  int newton_max = 100;                // FP64 Newton iterations per solve
 
   bool friction_set = false, state_set = false;
   double Dc = 0, V_ref = 0, f0 = 0, tau_rate = 0, V_pl = 0, t0 = 0;

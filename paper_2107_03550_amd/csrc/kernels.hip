@@ -995,7 +995,7 @@ k_modes(const FaultDev* __restrict__ faults, const int2* __restrict__ map, int m
 // Constants of the friction update of one fault, read once per launch.
 struct FrictionConst {
   double lnVref, eta, f0, Vref_Dc, Dc, dt, t_new_load, V_pl, s;
-  int theta_mode;
+  int theta_mode, newton_max;
 };
 
 __device__ __forceinline__ int solve_rate(double tau, double sig, double theta, double a, double b,
@@ -1040,7 +1040,7 @@ __device__ __forceinline__ int solve_rate(double tau, double sig, double theta, 
   }
 
   // double-precision phase
-  for (int it = 0; it < 100; ++it) {
+  for (int it = 0; it < k.newton_max; ++it) {
     const double ex = exp(x);
     const double g = K - eta * ex - sa * x;
     if (g == 0.0) {
@@ -1215,6 +1215,7 @@ k_elems(const FaultDev* __restrict__ faults, const int2* __restrict__ map,
     k.V_pl = fd.V_pl;
     k.s = s;
     k.theta_mode = fd.theta_mode;
+    k.newton_max = fd.newton_max;
     o.V1 = fd.V1;
     o.thd1 = fd.thd1;
     o.slip = cur ? fd.slip[0] : fd.slip[1];

@@ -513,6 +513,7 @@ FaultDev make_fault_desc(sbiem_plan* p, DtData* dtd, DynData* dyn, double V_pl, 
   f.ngroups = std::max(1, f.P / 2);
   f.ncls = p->ncls;
   f.theta_mode = p->theta_mode;
+  f.newton_max = p->newton_max;
   f.L = p->L;
   f.mu = p->mu;
   f.r = p->r;
@@ -776,6 +777,14 @@ int sbiem_set_theta_mode(sbiem_plan* p, int mode) {
   if (int s = check_plan(p)) return s;
   if (mode != SBIEM_THETA_PAPER && mode != SBIEM_THETA_EXP) return fail(p, SBIEM_EINVAL, "unknown theta mode");
   p->theta_mode = mode;
+  return refresh_desc(p);
+}
+
+int sbiem_set_newton_limit(sbiem_plan* p, int max_iterations) {
+  if (int s = check_plan(p)) return s;
+  if (max_iterations < 0 || max_iterations > 1000)
+    return fail(p, SBIEM_EINVAL, "set_newton_limit: need 0 <= max_iterations <= 1000");
+  p->newton_max = max_iterations == 0 ? 100 : max_iterations;
   return refresh_desc(p);
 }
 

@@ -56,10 +56,13 @@ def make_plan(sc: Scenario, precision):
     return p
 
 
-def make_oracle(sc: Scenario, table=None):
+def make_oracle(sc: Scenario, table=None, kappa=None):
+    """The oracle fault of a scenario; ``kappa`` (e.g. the plan's curvature)
+    replaces the oracle's own spectral h'' when given, so that a comparison
+    measures the time step alone."""
     from oracle.stepper import OracleFault
     return OracleFault(sc.N, sc.L, MU, CS, CP, dt=sc.dt, friction=fields(sc), h=sc.h,
-                       table=table, theta_mode=sc.theta_mode)
+                       kappa=kappa, table=table, theta_mode=sc.theta_mode)
 
 
 def rel_parts(a, total, static):

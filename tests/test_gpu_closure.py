@@ -134,7 +134,7 @@ def test_step_with_closure_matches_oracle():
         worst["sigma_el"] = max(worst["sigma_el"], rel_parts(g["sigma_el"], o.sigma_el, o.sigma_static))
         worst["V"] = max(worst["V"], rel(g["V"], o.V))
     print("closure step vs oracle", worst)
-    assert worst["tau_el"] < 1e-4 and worst["sigma_el"] < 1e-4, worst
+    assert worst["tau_el"] < 1e-5 and worst["sigma_el"] < 1e-5, worst
 
 
 def _nucleating(N, seed, overstress):

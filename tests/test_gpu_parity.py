@@ -103,7 +103,8 @@ def test_step_fp64_dynamic_rupture():
     sc = Scenario(128, 10e3, DT_10KM, rough_10km(128, seed=2, alpha=3e-3), spec=spec,
                   theta_mode="exp", consistent_V0=True)
     p = make_plan(sc, pkg.SBIEM_FP64)
-    o = make_oracle(sc, golden_table())
+    # the library's curvature as data: the comparison measures the step alone
+    o = make_oracle(sc, golden_table(), kappa=p.get_curvature())
     worst = 0.0
     for _ in range(6):
         p.run(sc.dt, 50)
@@ -111,8 +112,9 @@ def test_step_fp64_dynamic_rupture():
         g = p.get_state()
         for k, ref in (("slip", o.slip), ("V", o.V), ("tau_el", o.tau_el), ("sigma_el", o.sigma_el)):
             worst = max(worst, rel(g[k], ref))
+    print("fp64 rupture worst relative error", worst, "max V", o.V.max())
     assert o.V.max() > 1e-2
-    assert worst < 1e-9, worst
+    assert worst < 1e-10, worst
 
 
 def test_step_fp32_dynamic_rupture_N1024():
@@ -457,5 +459,12 @@ def test_stress_fp64_transform_sizes(N):
     p = pkg.Plan(N, L, MU, NU, CS, CP, h)
     tau, sig = p.stress(hist, dt)
     w = midpoint_weights(N, L, CS, CP, dt, max_lag=nt)
-    rt, rs = stress_from_history(hist, dt, L, MU, CS, CP, curvature_fft(h, L), w, transform="fft")
-    assert rel(tau, rt) < 1e-10 and rel(sig, rs) < 1e-9, (rel(tau, rt), rel(sig, rs))
+    # the curvature is data here (the library's, rounded from its
+    # extended-precision h''): numpy's FFT h'' differs from it by the FP64
+    # rounding of the forward transform amplified by k^2 (about 1e-10 at
+    # these sizes), which is not part of the time step being compared
+    kappa = p.get_curvature()
+    assert rel(kappa, curvature_fft(h, L)) < 1e-8
+    rt, rs = stress_from_history(hist, dt, L, MU, CS, CP, kappa, w, transform="fft")
+    print(f"fp64 stress N={N}:", rel(tau, rt), rel(sig, rs))
+    assert rel(tau, rt) < 1e-10 and rel(sig, rs) < 1e-10, (rel(tau, rt), rel(sig, rs))

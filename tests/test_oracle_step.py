@@ -119,3 +119,98 @@ def test_fft_transform_and_short_weights_reproduce_the_naive_oracle():
         assert np.max(np.abs(a - b)) <= 1e-11 * np.max(np.abs(a))
     with pytest.raises(ValueError):
         fast.step()
+
+
+def _kinematic_fault(monkeypatch, N, L, beta, pulse_steps, amp, seed=3):
+    """An oracle fault whose momentum balance is replaced by a prescribed
+    slip rate: V(step s, x) = V_pl + amp g(s) (1 + 0.7 cos(k_1 x + phi) +
+    0.3 sin(k_3 x)) with a smooth pulse g over the first ``pulse_steps``
+    steps and V = V_pl exactly afterwards.  The step's other bookkeeping
+    (predictor, slip update, spectral history push, window truncation) is
+    the oracle's own; only the Newton root is prescribed."""
+    import oracle.stepper as stepper
+    spec = FrictionSpec(overstress=0.0)
+    fr = friction_fields(N, L, MU, CS, spec)
+    dt = beta * L / N / CS
+    x = np.arange(N) * L / N
+    phi = np.random.default_rng(seed).uniform(0, 2 * np.pi)
+    shape = 1 + 0.7 * np.cos(2 * np.pi * x / L + phi) + 0.3 * np.sin(6 * np.pi * x / L)
+    V_pl = fr["V_pl"]
+
+    def rate_after(s):             # committed rate at the end of step s (s = 1, 2, ...)
+        if s >= pulse_steps:
+            return np.full(N, V_pl)
+        g = np.sin(np.pi * s / pulse_steps) ** 2
+        return V_pl + amp * g * shape
+
+    f = OracleFault(N, L, MU, CS, CP, dt=dt, friction=fr, h=rough_fault(N, L, 5e-3, seed),
+                    theta_mode="exp")
+
+    def prescribed(tau, sig, theta, a, b, f0, V_ref, Dc, eta, V_guess=None):
+        return rate_after(f.nsteps + 1), np.ones(N, dtype=bool)
+
+    monkeypatch.setattr(stepper, "solve_newton", prescribed)
+    return f, dt
+
+
+def test_stepper_history_past_the_window_equals_the_stress_functional(monkeypatch):
+    """The stepper keeps a per-mode history that it shifts and truncates
+    every step; the stress functional (section 3.1) instead sums the whole
+    slip record directly.  Driven past the longest window several times
+    (M_max = 2N = 64 lags at beta = 0.5), with motion in every retained
+    interval, the stepper's tractions equal the functional's on the
+    recorded slip after every step; once the motion stops and every window
+    has passed, only the static stiffness terms remain, exactly."""
+    from oracle.spectral import dft, idft_real, odd_sign, wavenumbers
+    from oracle.stress import stress_from_history
+    from oracle.windows import midpoint_weights
+    N, L, beta = 32, 10e3, 0.5
+    pulse = 150
+    f, dt = _kinematic_fault(monkeypatch, N, L, beta, pulse, 1e-4)
+    w = midpoint_weights(N, L, CS, CP, dt)
+    assert int(w.M.max()) == 2 * N
+    slips = [f.slip.copy()]
+    worst = 0.0
+    for s in range(1, pulse + 2 * N + 8):
+        f.step()
+        slips.append(f.slip.copy())
+        if s % 7 == 0 or s in (2 * N - 1, 2 * N, 2 * N + 1, pulse, pulse + 2 * N):
+            tau, sig = stress_from_history(np.array(slips), dt, L, MU, CS, CP, f.kappa, w,
+                                           V_pl=f.V_pl)
+            scale_t, scale_s = np.abs(tau).max(), np.abs(sig).max()
+            worst = max(worst, np.abs(f.tau_el - tau).max() / scale_t,
+                        np.abs(f.sigma_el - sig).max() / scale_s)
+    assert worst < 1e-11, worst
+    # every window has passed since the motion stopped: static terms only
+    r = (CS / CP) ** 2
+    u = f.slip - f.V_pl * f.t
+    tau_st = idft_real(-MU * np.abs(wavenumbers(N, L)) * (1 - r) * dft(u))
+    sig_st = idft_real(-1j * odd_sign(N) * MU * (1 - r) * dft(f.kappa * u))
+    assert np.abs(f.tau_el - tau_st).max() <= 1e-12 * np.abs(tau_st).max()
+    assert np.abs(f.sigma_el - sig_st).max() <= 1e-12 * np.abs(sig_st).max()
+
+
+def test_stepper_truncation_drops_exactly_the_lags_past_the_window(monkeypatch):
+    """One step before the last moving interval leaves the longest window it
+    still contributes to the tractions; one step after, the tractions are the
+    static ones.  A history kept one lag too long or too short fails one of
+    the two."""
+    from oracle.spectral import dft, idft_real, wavenumbers
+    N, L, beta = 32, 10e3, 0.5
+    pulse = 20
+    f, dt = _kinematic_fault(monkeypatch, N, L, beta, pulse, 1e-4)
+    r = (CS / CP) ** 2
+    M_max = 2 * N
+
+    def static_gap():
+        u = f.slip - f.V_pl * f.t
+        st = idft_real(-MU * np.abs(wavenumbers(N, L)) * (1 - r) * dft(u))
+        return np.abs(f.tau_el - st).max() / np.abs(st).max()
+
+    # the last moving interval is step pulse - 1 -> pulse (its rate (V0+V1)/2
+    # is non-zero); it is at lag j = s - pulse at the end of step s and
+    # contributes while j < M_max
+    f.run(pulse + M_max - 1)
+    assert static_gap() > 1e-9
+    f.step()
+    assert static_gap() < 1e-13
