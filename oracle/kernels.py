@@ -158,3 +158,116 @@ def kernel_table_mp(delta, p_max, cs, cp, processes=None):
         CT[sel] = res[:, 0]
         CN[sel] = res[:, 1]
     return CT, CN
+
+
+# ---------------------------------------------------------------------------
+# Primitives P^X(T) = integral of C^X_II from 0 to T (exact interval weights)
+#
+# Every term of C^T and C^N has an elementary primitive in W, J0, J1 and J2
+# (W' = -J1(x)/x; d/dx[x^2 J2(x)] = x^2 J1(x); d/dx[x J1(x)] = x J0(x)):
+#   int_0^T x^2 W(a x) dx = T^3 W(aT)/3 + T^2 J2(aT)/(3a)
+#   int_0^T W(a x) dx     = T W(aT) + (1 - J0(aT))/a
+#   int_0^T J1(a x) dx    = (1 - J0(aT))/a
+#   int_0^T x J0(a x) dx  = T J1(aT)/a
+# (the second and fourth extend the primitives of appendix A).  Summed over
+# the terms of C^T (section 2.3) and C^N (section 2.4), with a = eta or 1,
+# the J0 terms of the W and J1 pieces cancel pairwise, leaving
+#   P^T = T^3 [W(eta T) - W(T)]/3 + T^2 [J2(eta T)/eta - J2(T)]/3
+#         + r T W(eta T) - T W(T) - (1 - J0(T))/2 - r T J1(eta T) + T J1(T)
+#   P^N = A T W(eta T) + B T W(T) - T^3 [W(eta T) - W(T)]/3
+#         - T^2 [J2(eta T)/eta - J2(T)]/3 + r T J1(eta T) - T J1(T)
+# with A = (q-2)^2 r/2 - r and B = 1 - q/2 (the constant coefficients of
+# W(eta T) and W(T) in C^N).  The weight of a history interval [tau_a, tau_b]
+# of wavenumber k is [P(c_s|k| tau_b) - P(c_s|k| tau_a)] / (c_s |k|).
+# ---------------------------------------------------------------------------
+def primitives_mp(T, cs, cp):
+    """(P^T(T), P^N(T)) as mpmath numbers, 30 significant digits (more are
+    carried internally: the terms grow like T^(3/2) and cancel)."""
+    with mp.workdps(max(MP_DPS, mp.mp.dps) + 10):
+        r, q, eta = _mp_consts(cs, cp)
+        T = mp.mpf(T)
+        a = eta * T
+        Wa, Wb = W_mp(a), W_mp(T)
+        J0b = mp.besselj(0, T)
+        J1a, J1b = mp.besselj(1, a), mp.besselj(1, T)
+        J2a, J2b = mp.besselj(2, a), mp.besselj(2, T)
+        cubic = T ** 3 * (Wa - Wb) / 3 + T ** 2 * (J2a / eta - J2b) / 3
+        pt = cubic + r * T * Wa - T * Wb - (1 - J0b) / 2 - r * T * J1a + T * J1b
+        A = (q - 2) ** 2 * r / 2 - r
+        B = 1 - q / 2
+        pn = A * T * Wa + B * T * Wb - cubic + r * T * J1a - T * J1b
+        return +pt, +pn
+
+
+def primitives_fp(T, cs, cp):
+    """(P^T(T), P^N(T)) in FP64 (scipy), vectorised over T.  The terms grow
+    like T^(3/2) and cancel, so the absolute error grows to about 1e-12 near
+    T = 200."""
+    from scipy.special import jv as _jv
+    T = np.asarray(T, dtype=np.float64)
+    r = (cs / cp) ** 2
+    q = 1.0 / r
+    eta = cp / cs
+    a = eta * T
+    Wa, Wb = _W_fp(a), _W_fp(T)
+    J0b, J1a, J1b = _j0(T), _j1(a), _j1(T)
+    J2a, J2b = _jv(2, a), _jv(2, T)
+    cubic = T ** 3 * (Wa - Wb) / 3 + T ** 2 * (J2a / eta - J2b) / 3
+    pt = cubic + r * T * Wa - T * Wb - (1 - J0b) / 2 - r * T * J1a + T * J1b
+    A = (q - 2) ** 2 * r / 2 - r
+    B = 1 - q / 2
+    pn = A * T * Wa + B * T * Wb - cubic + r * T * J1a - T * J1b
+    bad = ~(np.isfinite(pt) & np.isfinite(pn))
+    if np.any(bad):
+        pt = np.array(pt, dtype=np.float64)
+        pn = np.array(pn, dtype=np.float64)
+        ft, fpt, fpn = T.reshape(-1), pt.reshape(-1), pn.reshape(-1)
+        for i in np.flatnonzero(bad.reshape(-1)):
+            x, y = primitives_mp(float(ft[i]), cs, cp)
+            fpt[i] = float(x)
+            fpn[i] = float(y)
+    return pt, pn
+
+
+_GL_X, _GL_W = np.polynomial.legendre.leggauss(8)
+
+
+def kernel_integrals_fp(Ta, Tb, cs, cp):
+    """(int_Ta^Tb C^T dT, int_Ta^Tb C^N dT) in FP64, vectorised.
+
+    Short spans (Tb - Ta <= 16) use composite 8-point Gauss-Legendre
+    quadrature of the FP64 closed forms on panels no wider than 1/2 (far
+    below the kernels' oscillation period), so the result carries the FP64
+    kernels' own accuracy; longer spans use the difference of the closed-form
+    primitives, whose cancellation error (about T^3 times the rounding of W)
+    is small against an integral over many units of T."""
+    Ta = np.asarray(Ta, dtype=np.float64)
+    Tb = np.asarray(Tb, dtype=np.float64)
+    Ta, Tb = np.broadcast_arrays(Ta, Tb)
+    out_t = np.zeros(Ta.shape)
+    out_n = np.zeros(Ta.shape)
+    span = Tb - Ta
+    longs = span > 16.0
+    if np.any(longs):
+        pa = primitives_fp(Ta[longs], cs, cp)
+        pb = primitives_fp(Tb[longs], cs, cp)
+        out_t[longs] = pb[0] - pa[0]
+        out_n[longs] = pb[1] - pa[1]
+    short = (~longs) & (span != 0.0)
+    if np.any(short):
+        npan = np.ceil(span[short] / 0.5).astype(np.int64)
+        npan = np.maximum(npan, 1)
+        a, s = Ta[short], span[short]
+        rt = np.zeros(a.shape)
+        rn = np.zeros(a.shape)
+        for m in np.unique(npan):
+            sel = npan == m
+            h = s[sel] / m                                   # panel width
+            left = a[sel][:, None] + h[:, None] * np.arange(m)[None, :]
+            x = left[:, :, None] + 0.5 * h[:, None, None] * (1.0 + _GL_X[None, None, :])
+            ct, cn = kernels_fp(x, cs, cp)
+            rt[sel] = 0.5 * h * np.einsum("ipq,q->i", ct, _GL_W)
+            rn[sel] = 0.5 * h * np.einsum("ipq,q->i", cn, _GL_W)
+        out_t[short] = rt
+        out_n[short] = rn
+    return out_t, out_n

@@ -37,7 +37,7 @@ import numpy as np
 
 from .friction import solve_newton
 from .spectral import curvature, curvature_fft, odd_sign, transforms, wavenumbers
-from .windows import KernelTable, midpoint_weights
+from .windows import KC_TIMES_L, KernelTable, interval_weights, midpoint_weights
 
 ERR_NEWTON = -4
 ERR_STATE = -5
@@ -55,12 +55,15 @@ class OracleFault:
 
     def __init__(self, N, L, mu, cs, cp, *, dt, friction, h=None, kappa=None,
                  table: KernelTable | None = None, theta_mode="paper",
-                 transform="naive", max_lag=None, closure=None):
+                 transform="naive", max_lag=None, closure=None, rule="R1",
+                 kc=(KC_TIMES_L, KC_TIMES_L)):
         """``transform``: "naive" (explicit DFT sums) or "fft" (numpy FFT);
         ``max_lag``: keep only window lags below it, which limits the run to
         max_lag steps from the state set (longer runs raise); ``closure``:
         (params_T, params_N, cut) to keep ceil(cut M_n) lags and close the
-        tail with the networks of ``oracle.closure`` (bfloat16 inference)."""
+        tail with the networks of ``oracle.closure`` (bfloat16 inference);
+        ``rule``: "R1" midpoint weights or "R2" exact interval integrals
+        (``oracle.windows``); ``kc``: k_c L of the shear and normal windows."""
         self.N, self.L, self.mu, self.cs, self.cp, self.dt = N, L, mu, cs, cp, dt
         self._fwd, self._inv = transforms(transform)
         self.max_lag = max_lag
@@ -71,7 +74,12 @@ class OracleFault:
         self.kappa = np.asarray(kappa, dtype=np.float64)
         self.kabs = np.abs(wavenumbers(N, L))
         self.s = odd_sign(N)
-        self.w = midpoint_weights(N, L, cs, cp, dt, table, max_lag=max_lag)
+        if rule == "R1":
+            self.w = midpoint_weights(N, L, cs, cp, dt, table, max_lag=max_lag, kc=kc)
+        elif rule == "R2":
+            self.w = interval_weights(N, L, cs, cp, dt, max_lag=max_lag, kc=kc)
+        else:
+            raise ValueError("rule must be R1 or R2")
         f = friction
         self.a, self.b = np.asarray(f["a"], float), np.asarray(f["b"], float)
         self.Dc, self.V_ref, self.f0 = f["Dc"], f["V_ref"], f["f0"]
