@@ -140,3 +140,24 @@ def test_golden_kernel_table_is_oracle_output():
         with mp.workdps(MP_DPS):
             ct, cn = kernels_mp(mp.mpf(repr(float(z["delta"]))) * p, CS, CP)
         assert z["CT"][p] == float(ct) and z["CN"][p] == float(cn)
+
+
+def test_fp64_w_and_kernels_match_the_30_digit_evaluator():
+    """The FP64 evaluator (Neumann series, quadrature of J1(t)/t, and the
+    large-argument form J0 A + J1 B) against the 30-digit closed forms of W
+    (section 2.3, via Struve functions) and of C^T, C^N, across every branch
+    and the branch points."""
+    import mpmath as mp
+    from oracle.kernels import W_mp, _W_fp, kernels_fp, kernels_mp
+    x = np.concatenate([np.linspace(0.0, 60.0, 241), [4.999999, 5.0, 34.999999, 35.0],
+                        np.linspace(60.0, 450.0, 40)])
+    w = _W_fp(x)
+    err = max(abs(w[i] - float(W_mp(v))) for i, v in enumerate(x))
+    assert err < 1e-15, err
+    T = np.array([0.01, 0.7, 2.0, 6.0, 13.0, 15.7, 20.2, 28.9, 40.0, 100.0, 199.0, 240.0])
+    ct, cn = kernels_fp(T, CS, CP)
+    for i, t in enumerate(T):
+        with mp.workdps(30):
+            a, b = kernels_mp(t, CS, CP)
+        tol = 1e-15 * max(1.0, t * t)       # the T^2 W terms amplify the rounding of W
+        assert abs(ct[i] - float(a)) < tol and abs(cn[i] - float(b)) < tol, t
