@@ -76,6 +76,25 @@ enum sbiem_precision { SBIEM_FP64 = 0, SBIEM_FP32CONV = 1 };
  * where the explicit update is unstable (V dt / Dc > 2). */
 enum sbiem_theta_mode { SBIEM_THETA_PAPER = 0, SBIEM_THETA_EXP = 1 };
 
+/* Convolution weights of the history intervals (section 3.1; the paper
+ * names only "the midpoint method").  MIDPOINT (rule R1): the weight of lag
+ * j (interval [j dt, (j+1) dt] back from the evaluation time) is
+ * dt C(c_s |k| (j + 1/2) dt).  INTERVAL (rule R2): the exact integral of the
+ * kernel over the interval, clipped at the window end T_w,
+ * [P(c_s |k| min((j+1) dt, T_w)) - P(c_s |k| j dt)] / (c_s |k|), with P the
+ * closed-form primitive of the kernel (sbiem_kernel_primitive_eval); this is
+ * the rule of variable steps. */
+enum sbiem_rule { SBIEM_RULE_MIDPOINT = 0, SBIEM_RULE_INTERVAL = 1 };
+
+/* Outcomes recorded by sbiem_adapt for each attempted step. */
+enum sbiem_adapt_outcome {
+  SBIEM_ADAPT_ACCEPT = 0,  /* eps <= eps0: kept (the two-half-step solution) */
+  SBIEM_ADAPT_REJECT = 1,  /* eps > eps0: taken again with a smaller dt      */
+  SBIEM_ADAPT_FAIL = 2,    /* a step failed: taken again with dt/2           */
+  SBIEM_ADAPT_FLOOR = 3,   /* eps > eps0 at dt_min: kept anyway              */
+  SBIEM_ADAPT_STOP = 4     /* a step failed at dt_min: the run stops         */
+};
+
 /* ABI version of the loaded library (SBIEM_ABI_VERSION it was built with). */
 int sbiem_abi_version(void);
 
@@ -125,6 +144,68 @@ int sbiem_set_theta_mode(sbiem_plan* p, int mode);
  * Errors: EINVAL (out of range). */
 int sbiem_set_newton_limit(sbiem_plan* p, int max_iterations);
 
+/* Weight rule of the history convolution (SBIEM_RULE_MIDPOINT default, or
+ * SBIEM_RULE_INTERVAL).  Must precede sbiem_set_dt / the first step
+ * (EINVAL afterwards); adaptive plans always use the INTERVAL rule.  FP32
+ * plans on the INTERVAL rule run on the variable-step engine (see
+ * sbiem_set_adaptive), whose weights are evaluated per step; FP64 plans take
+ * exact per-lag weights from the host.  The learned closure needs the
+ * MIDPOINT rule.  Errors: EINVAL. */
+int sbiem_set_rule(sbiem_plan* p, int rule);
+
+/* Cut-off wavenumbers of the truncation window (section 3.1), given as
+ * k_c L for the shear and for the normal kernel (the paper uses one value,
+ * 200, for both and suggests separate ones because the normal kernel
+ * converges more slowly): T_w^X(k) = (L/c_s) min(1, k_c^X / |k|).  A mode
+ * keeps the history of the longer window; each kind's weights are zero past
+ * its own.  Must precede sbiem_set_dt (EINVAL afterwards); values in
+ * [1, 1e6].  The learned closure needs equal values. */
+int sbiem_set_cutoffs(sbiem_plan* p, double kcL_shear, double kcL_normal);
+
+/* Variable time steps (section 3.2) on (1) or off (0).  Must precede
+ * sbiem_set_dt, whose dt then becomes the smallest step dt_min (the paper
+ * takes beta_min dx / c_s with beta_min = 0.25).  The slip-rate history is
+ * then a list of committed intervals of any length >= dt_min: each mode
+ * keeps ceil(T_w / dt_min) + 2 of them in its ring (the two more that a
+ * rejected attempt may overwrite), the interval times in a per-fault log,
+ * and every step weighs each stored interval by the exact kernel integral
+ * over its lag span (INTERVAL rule).  Steps run launch by launch (no graph,
+ * no overlap of the next step's convolution).  Not with the learned
+ * closure or in batches.  Errors: EINVAL. */
+int sbiem_set_adaptive(sbiem_plan* p, int on);
+
+/* One two-pass step of length dt >= dt_min (section 3.3) on an adaptive
+ * plan (or an FP32 INTERVAL-rule plan), against its non-uniform history.
+ * Synchronous; failures as sbiem_step (state left at the start of the
+ * step).  sbiem_step and sbiem_run on such plans take steps of the dt they
+ * are given the same way.  Errors: EINVAL (dt < dt_min, other plans),
+ * ENOTREADY, ENEWTON / ESTATE / EOPEN. */
+int sbiem_step_var(sbiem_plan* p, double dt);
+
+/* Step-size control of section 3.2 on an adaptive plan.  Each attempt takes
+ * one step of dt and, from the same state, two steps of dt/2;
+ * eps = max over elements of |ln V_1 - ln V_2| and |ln theta_1 - ln theta_2|
+ * (reading: the paper names neither the variable nor the norm).
+ *   eps <= eps0: accepted with the two-half-step solution; the next dt is
+ *     min(dt_max, 5 dt, max(dt_min, 0.9 (eps0/eps)^(1/3) dt)) (5 dt when
+ *     eps = 0);
+ *   eps > eps0: taken again with max(dt_min, 0.9 (eps0/eps)^(1/3) dt);
+ *   a failed step (ENEWTON, ESTATE, EOPEN): taken again with
+ *     max(dt_min, dt/2);
+ *   at dt_min an error above eps0 is accepted (FLOOR) and a failure stops
+ *     the run: its status is returned, the state is that of the last
+ *     accepted step.
+ * Runs until max_accepted steps are accepted or the time reaches t_end
+ * (the last step is not shortened to hit it).  *dt_io: first dt to try on
+ * entry, next dt to try on return.  log (may be NULL): host array of
+ * log_cap records of 4 doubles (t at the attempt's start, dt, eps or -1
+ * for a failed attempt, outcome from sbiem_adapt_outcome); *log_len (may be
+ * NULL) receives the number of attempts (records past log_cap are counted,
+ * not written).  eps0 > 0, dt_max >= dt_min.  Errors: EINVAL, ENOTREADY, the
+ * stopping step's status. */
+int sbiem_adapt(sbiem_plan* p, double eps0, double dt_max, double t_end, int64_t max_accepted,
+                double* dt_io, double* log, int64_t log_cap, int64_t* log_len);
+
 /* Rate-and-state friction and loading (section 3, eq. momentum; aging law).
  *   a, b         [N] direct and evolution effects (a > 0)
  *   Dc, V_ref, f0  critical slip [m], reference velocity [m/s] (the law's
@@ -164,7 +245,8 @@ int sbiem_get_curvature(const sbiem_plan* p, double* kappa);
 int sbiem_set_dt(sbiem_plan* p, double dt);
 
 /* Window lengths M_n for n = 1..N/2 (M[0] is mode 1) at time step dt,
- * computed on the host; does not change the plan. */
+ * computed on the host: the longer of the shear and normal windows
+ * (sbiem_set_cutoffs); does not change the plan. */
 int sbiem_window_lengths(const sbiem_plan* p, double dt, int64_t* M);
 
 /* Stress-only evaluation of the spectral-time functional (section 3.1):
@@ -178,7 +260,8 @@ int sbiem_stress(sbiem_plan* p, const double* slip_hist, int64_t nt, double dt,
                  double* tau_out, double* sigma_out);
 
 /* One two-pass step of length dt (section 3.3).  dt must equal the plan's
- * dt once set (variable dt is not supported: EINVAL).  Synchronous: returns
+ * dt once set, except on adaptive and FP32 INTERVAL-rule plans, which take
+ * any dt >= dt_min (sbiem_step_var).  Synchronous: returns
  * ENEWTON / ESTATE / EOPEN if the step failed, leaving the state at the
  * start of the step (section 3.2).  ENOTREADY without friction and state. */
 int sbiem_step(sbiem_plan* p, double dt);
@@ -213,6 +296,14 @@ int sbiem_set_allocator(void* (*alloc)(size_t bytes, void* ctx),
  * verification. */
 int sbiem_kernel_eval(double cs, double cp, const double* T, int64_t n, double* CT,
                       double* CN, double* dCT, double* dCN);
+
+/* Host evaluation (extended precision) of the kernel primitives
+ * P^X(T) = integral of C^X over [0, T] at T[i] >= 0 (closed form from
+ * elementary primitives of the terms of sections 2.3 and 2.4); any output
+ * may be NULL.  Used for the INTERVAL-rule weights; exported for
+ * verification. */
+int sbiem_kernel_primitive_eval(double cs, double cp, const double* T, int64_t n, double* PT,
+                                double* PN);
 
 /* Per-launch timing of the history-convolution kernel with HIP events on
  * the stream it runs on.  While on, sbiem_run launches one step in every 33

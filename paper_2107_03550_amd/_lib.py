@@ -33,6 +33,9 @@ SBIEM_FP64 = 0
 SBIEM_FP32CONV = 1
 SBIEM_THETA_PAPER = 0
 SBIEM_THETA_EXP = 1
+SBIEM_RULE_MIDPOINT = 0
+SBIEM_RULE_INTERVAL = 1
+ADAPT_OUTCOMES = ("accept", "reject", "fail", "floor", "stop")
 CLOSURE_PARAMS = 6466
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -56,6 +59,12 @@ _SIGS = {
     "sbiem_set_precision": (_int, [_PLAN, _int]),
     "sbiem_set_theta_mode": (_int, [_PLAN, _int]),
     "sbiem_set_newton_limit": (_int, [_PLAN, _int]),
+    "sbiem_set_rule": (_int, [_PLAN, _int]),
+    "sbiem_set_cutoffs": (_int, [_PLAN, _dbl, _dbl]),
+    "sbiem_set_adaptive": (_int, [_PLAN, _int]),
+    "sbiem_step_var": (_int, [_PLAN, _dbl]),
+    "sbiem_adapt": (_int, [_PLAN, _dbl, _dbl, _dbl, _i64, _D, _D, _i64, _I64]),
+    "sbiem_kernel_primitive_eval": (_int, [_dbl, _dbl, _D, _i64, _D, _D]),
     "sbiem_set_friction": (_int, [_PLAN, _D, _D, _dbl, _dbl, _dbl, _D, _D, _dbl, _dbl]),
     "sbiem_set_state": (_int, [_PLAN, _D, _D, _D, _dbl]),
     "sbiem_get_state": (_int, [_PLAN, _D, _D, _D, _D, _D, _D]),
@@ -125,6 +134,14 @@ def kernel_eval(T, cs, cp):
     T = _arr(T)
     outs = [np.empty(T.size) for _ in range(4)]
     _check(lib.sbiem_kernel_eval(cs, cp, _ptr(T), T.size, *[_ptr(o) for o in outs]))
+    return tuple(outs)
+
+
+def kernel_primitive_eval(T, cs, cp):
+    """P^T, P^N (integrals of the kernels over [0, T]) at T (host extended precision)."""
+    T = _arr(T)
+    outs = [np.empty(T.size) for _ in range(2)]
+    _check(lib.sbiem_kernel_primitive_eval(cs, cp, _ptr(T), T.size, *[_ptr(o) for o in outs]))
     return tuple(outs)
 
 
@@ -223,6 +240,34 @@ class Plan:
 
     def set_newton_limit(self, max_iterations):
         self._c(lib.sbiem_set_newton_limit(self.handle, int(max_iterations)))
+
+    def set_rule(self, rule):
+        self._c(lib.sbiem_set_rule(self.handle, int(rule)))
+
+    def set_cutoffs(self, kcL_shear, kcL_normal):
+        self._c(lib.sbiem_set_cutoffs(self.handle, float(kcL_shear), float(kcL_normal)))
+
+    def set_adaptive(self, on=True):
+        self._c(lib.sbiem_set_adaptive(self.handle, 1 if on else 0))
+
+    def step_var(self, dt):
+        self._c(lib.sbiem_step_var(self.handle, float(dt)))
+
+    def step_var_status(self, dt):
+        return lib.sbiem_step_var(self.handle, float(dt))
+
+    def adapt(self, eps0, dt_max, dt, max_accepted, t_end=np.inf, log_cap=100000):
+        """Controlled steps (sbiem_adapt).  Returns (status, next dt, log) with
+        log an array of (t, dt, eps, outcome) rows, one per attempt."""
+        d = ctypes.c_double(float(dt))
+        log = np.zeros((int(log_cap), 4))
+        n = ctypes.c_int64()
+        st = lib.sbiem_adapt(self.handle, float(eps0), float(dt_max), float(t_end),
+                             int(max_accepted), ctypes.byref(d), _ptr(log), int(log_cap),
+                             ctypes.byref(n))
+        if st not in (0, -4, -5, -6):
+            _check(st, self.handle)
+        return st, d.value, log[:min(n.value, int(log_cap))]
 
     def set_friction(self, a, b, Dc, V_ref, f0, sigma_load, tau_load, tau_load_rate=0.0, V_pl=0.0):
         n = self.N

@@ -67,6 +67,14 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
       return SBIEM_EINVAL;
     }
   }
+  if (plans.size() > 1) {
+    for (sbiem_plan* p : plans)
+      if (var_engine(p)) {
+        *err = "plans on the variable-step engine cannot be batched";
+        delete ex;
+        return SBIEM_EINVAL;
+      }
+  }
   double bytes = 0.0;
   const double rec = precision == SBIEM_FP32CONV ? 16.0 : 32.0;
   for (int f = 0; f < ex->nfaults; ++f) {
@@ -219,6 +227,8 @@ int reset_history(sbiem_plan* p) {
   if (!e && p->dtd) {
     const size_t rec = p->precision == SBIEM_FP32CONV ? 16 : 32;
     e = hipMemsetAsync(p->dtd->ring, 0, (size_t)std::max<long long>(p->dtd->ring_slots, 1) * rec, s);
+    if (!e && p->dtd->tlog)
+      e = hipMemsetAsync(p->dtd->tlog, 0, sizeof(double2) * p->dtd->tlog_cap, s);
   }
   if (!e) e = hipStreamSynchronize(s);
   if (e) return hip_fail(p, e, "resetting the history");
@@ -242,7 +252,9 @@ int rebase_state(sbiem_plan* p) {
     if (!e) e = hipMemcpy(d->sigma_el[0], d->sigma_el[1], bytes, hipMemcpyDeviceToDevice);
     if (e) return hip_fail(p, e, "rebase");
   }
-  p->t0 += (double)step * (p->dtd ? p->dtd->dt : 0.0);
+  if (p->dtd && p->dtd->var) p->t0 = p->t_var;
+  else p->t0 += (double)step * (p->dtd ? p->dtd->dt : 0.0);
+  p->t_var = p->t0;
   e = hipMemset(d->step, 0, sizeof(long long));
   if (e) return hip_fail(p, e, "rebase");
   return SBIEM_OK;
@@ -338,9 +350,83 @@ int ready(sbiem_plan* p, double dt) {
     return fail(p, SBIEM_ENOTREADY, "set_friction and set_state must precede stepping");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(p, SBIEM_EINVAL, "dt must be > 0");
   if (!p->dtd) return sbiem_set_dt(p, dt);
+  if (p->dtd->var) {
+    const double hmin = p->adaptive ? 0.5 * p->dtd->dt : p->dtd->dt;
+    if (dt < hmin * (1.0 - 1e-12))
+      return fail(p, SBIEM_EINVAL, "dt is below the shortest interval the history is sized for");
+    return SBIEM_OK;
+  }
   if (dt != p->dtd->dt)
     return fail(p, SBIEM_EINVAL, "variable dt is not supported: dt differs from the plan's");
   return SBIEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Variable-step engine (section 3.2): a step of any length against the
+// interval history, launched kernel by kernel: balance cells reset, history
+// sums at the step's end time, pass-1 maxima and assembly, the two passes,
+// the commit (which logs the interval's times).
+// ---------------------------------------------------------------------------
+int var_step(sbiem_plan* p, double dt) {
+  Exec& ex = *p->exec;
+  hipStream_t s = p->stream;
+  const VarArgs va{dt, p->t_var, p->t_var + dt, 1, 0};
+  hipError_t e = launch_reset_cells(ex, s);
+  if (!e) e = launch_conv_var(ex, va, s);
+  if (!e) e = launch_modes(ex, 0, 1, s, va);
+  if (!e) e = launch_modes(ex, 0, 0, s, va);
+  if (!e) e = launch_elems(ex, 1, s, va);
+  if (!e) e = launch_modes(ex, 1, 0, s, va);
+  if (!e) e = launch_elems(ex, 2, s, va);
+  if (!e) e = launch_modes(ex, 2, 0, s, va);
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return hip_fail(p, e, "variable step");
+  p->dyn->primed = false;
+  const int st = check_failure(p);
+  if (st == SBIEM_OK) p->t_var = va.t_new;
+  return st;
+}
+
+int snap_alloc(sbiem_plan* p) {
+  if (p->snap) return SBIEM_OK;
+  VarSnap* v = new VarSnap();
+  const size_t N = (size_t)p->N, M = (size_t)(p->N / 2 + 1);
+  bool ok = true;
+  for (double*& x : v->el) ok = ok && (x = (double*)v->mem.get(N * sizeof(double)));
+  for (double2*& x : v->sp) ok = ok && (x = (double2*)v->mem.get(M * sizeof(double2)));
+  ok = ok && (v->step = (long long*)v->mem.get(sizeof(long long)));
+  ok = ok && (v->Vf = (double*)v->mem.get(N * sizeof(double)));
+  ok = ok && (v->thf = (double*)v->mem.get(N * sizeof(double)));
+  ok = ok && (v->eps = (unsigned long long*)v->mem.get(sizeof(unsigned long long)));
+  if (!ok) {
+    delete v;
+    return fail(p, SBIEM_ENOMEM, "adaptive stepping: snapshot allocation failed");
+  }
+  p->snap = v;
+  return SBIEM_OK;
+}
+
+// Committed state <-> snapshot (to = 1: save).
+hipError_t snap_copy(sbiem_plan* p, bool save) {
+  DynData* d = p->dyn;
+  VarSnap* v = p->snap;
+  hipStream_t s = p->stream;
+  const size_t N = (size_t)p->N, M = (size_t)(p->N / 2 + 1);
+  double* el[12] = {d->slip[0], d->slip[1], d->V[0], d->V[1], d->theta[0], d->theta[1],
+                    d->thd[0], d->thd[1], d->tau_el[0], d->tau_el[1], d->sigma_el[0],
+                    d->sigma_el[1]};
+  double2* sp[6] = {d->u_hat, d->g_hat, d->v_hat0, d->gv_hat0, d->hprev_v, d->hprev_g};
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 12 && !e; ++k)
+    e = hipMemcpyAsync(save ? v->el[k] : el[k], save ? el[k] : v->el[k], N * sizeof(double),
+                       hipMemcpyDeviceToDevice, s);
+  for (int k = 0; k < 6 && !e; ++k)
+    e = hipMemcpyAsync(save ? v->sp[k] : sp[k], save ? sp[k] : v->sp[k], M * sizeof(double2),
+                       hipMemcpyDeviceToDevice, s);
+  if (!e)
+    e = hipMemcpyAsync(save ? v->step : d->step, save ? d->step : v->step, sizeof(long long),
+                       hipMemcpyDeviceToDevice, s);
+  return e;
 }
 
 // One step in steady state: the next step's history sums on the second
@@ -585,6 +671,11 @@ int sbiem_run(sbiem_plan* p, double dt, int64_t nsteps) {
   if (!p->exec) {
     if (int st = rebuild_exec(p)) return st;
   }
+  if (p->dtd->var) {
+    for (int64_t k = 0; k < nsteps; ++k)
+      if (int st = var_step(p, dt)) return st;
+    return SBIEM_OK;
+  }
   const char* what = "";
   e = run_steps(p->exec, nsteps, p->stream, p->profiling, &p->events, &p->prof_ms,
                 &p->prof_launches, &what);
@@ -594,6 +685,126 @@ int sbiem_run(sbiem_plan* p, double dt, int64_t nsteps) {
   }
   if (e) return hip_fail(p, e, what);
   return check_failure(p);
+}
+
+int sbiem_step_var(sbiem_plan* p, double dt) {
+  if (!p) return fail_global(SBIEM_EINVAL, "NULL plan");
+  if (!p->dtd || !p->dtd->var)
+    return fail(p, SBIEM_EINVAL, "step_var: the plan is not on the variable-step engine "
+                                 "(sbiem_set_adaptive, then sbiem_set_dt)");
+  return sbiem_run(p, dt, 1);
+}
+
+int sbiem_adapt(sbiem_plan* p, double eps0, double dt_max, double t_end, int64_t max_accepted,
+                double* dt_io, double* log, int64_t log_cap, int64_t* log_len) {
+  if (!p) return fail_global(SBIEM_EINVAL, "NULL plan");
+  if (!p->adaptive || !p->dtd)
+    return fail(p, SBIEM_EINVAL, "adapt: needs sbiem_set_adaptive(1) and sbiem_set_dt(dt_min)");
+  if (!p->friction_set || !p->state_set)
+    return fail(p, SBIEM_ENOTREADY, "set_friction and set_state must precede stepping");
+  const double dt_min = p->dtd->dt;
+  if (!dt_io || !(eps0 > 0) || !(dt_max >= dt_min) || max_accepted < 0 || log_cap < 0 ||
+      (log_cap > 0 && !log) || !std::isfinite(dt_max) || !(*dt_io > 0))
+    return fail(p, SBIEM_EINVAL, "adapt: need eps0 > 0, dt_max >= dt_min, *dt_io > 0");
+  hipError_t e = hipSetDevice(p->device);
+  if (e) return hip_fail(p, e, "hipSetDevice");
+  if (!p->exec) {
+    if (int st = rebuild_exec(p)) return st;
+  }
+  if (int st = snap_alloc(p)) return st;
+  DynData* d = p->dyn;
+  VarSnap* v = p->snap;
+  hipStream_t s = p->stream;
+  long long s0 = 0;
+  e = hipStreamSynchronize(s);
+  if (!e) e = hipMemcpy(&s0, d->step, sizeof(s0), hipMemcpyDeviceToHost);
+  if (e) return hip_fail(p, e, "adapt");
+  int64_t nlog = 0;
+  auto record = [&](double t, double dt, double eps, int outcome) {
+    if (nlog < log_cap) {
+      double* r = log + 4 * nlog;
+      r[0] = t;
+      r[1] = dt;
+      r[2] = eps;
+      r[3] = (double)outcome;
+    }
+    ++nlog;
+  };
+  const double growth = 5.0, safety = 0.9;
+  auto next_dt = [&](double dt, double eps) {
+    const double g = eps > 0 ? safety * std::pow(eps0 / eps, 1.0 / 3.0) * dt : growth * dt;
+    return std::min(std::min(std::max(g, dt_min), dt_max), growth * dt);
+  };
+  auto physics = [](int st) {
+    return st == SBIEM_ENEWTON || st == SBIEM_ESTATE || st == SBIEM_EOPEN;
+  };
+  double dt = std::min(std::max(*dt_io, dt_min), dt_max);
+  int64_t accepted = 0;
+  int status = SBIEM_OK;
+  while (accepted < max_accepted && p->t_var < t_end && status == SBIEM_OK) {
+    for (;;) {
+      const double t_start = p->t_var;
+      e = snap_copy(p, true);
+      if (e) return hip_fail(p, e, "adapt: snapshot");
+      // one step of dt, then two of dt/2 from the same state
+      int st = var_step(p, dt);
+      if (st == SBIEM_OK) {
+        const int c = (int)((s0 + 1) & 1);
+        e = hipMemcpyAsync(v->Vf, d->V[c], (size_t)p->N * sizeof(double), hipMemcpyDeviceToDevice, s);
+        if (!e)
+          e = hipMemcpyAsync(v->thf, d->theta[c], (size_t)p->N * sizeof(double),
+                             hipMemcpyDeviceToDevice, s);
+        if (!e) e = snap_copy(p, false);
+        if (e) return hip_fail(p, e, "adapt: snapshot");
+        p->t_var = t_start;
+        st = var_step(p, 0.5 * dt);
+        if (st == SBIEM_OK) st = var_step(p, 0.5 * dt);
+      }
+      if (st != SBIEM_OK) {
+        if (!physics(st)) return st;
+        e = snap_copy(p, false);
+        if (!e) e = hipStreamSynchronize(s);
+        if (e) return hip_fail(p, e, "adapt: snapshot");
+        p->t_var = t_start;
+        d->primed = false;
+        if (dt <= dt_min) {
+          record(t_start, dt, -1.0, SBIEM_ADAPT_STOP);
+          status = st;
+          break;
+        }
+        record(t_start, dt, -1.0, SBIEM_ADAPT_FAIL);
+        dt = std::max(0.5 * dt, dt_min);
+        continue;
+      }
+      const int c = (int)(s0 & 1);  // two steps after s0
+      unsigned long long bits = 0;
+      e = launch_err_norm(v->Vf, v->thf, d->V[c], d->theta[c], (int)p->N, v->eps, s);
+      if (!e) e = hipMemcpyAsync(&bits, v->eps, sizeof(bits), hipMemcpyDeviceToHost, s);
+      if (!e) e = hipStreamSynchronize(s);
+      if (e) return hip_fail(p, e, "adapt: error measure");
+      double eps;
+      std::memcpy(&eps, &bits, sizeof(eps));
+      if (eps <= eps0 || dt <= dt_min) {
+        record(t_start, dt, eps, eps <= eps0 ? SBIEM_ADAPT_ACCEPT : SBIEM_ADAPT_FLOOR);
+        s0 += 2;
+        ++accepted;
+        dt = next_dt(dt, eps);
+        break;
+      }
+      record(t_start, dt, eps, SBIEM_ADAPT_REJECT);
+      e = snap_copy(p, false);
+      if (!e) e = hipStreamSynchronize(s);
+      if (e) return hip_fail(p, e, "adapt: snapshot");
+      p->t_var = t_start;
+      d->primed = false;
+      dt = std::max(safety * std::pow(eps0 / eps, 1.0 / 3.0) * dt, dt_min);
+    }
+  }
+  *dt_io = dt;
+  if (log_len) *log_len = nlog;
+  if (status != SBIEM_OK)
+    return fail(p, status, "adapt: a step failed with dt at its minimum: " + p->last_error);
+  return SBIEM_OK;
 }
 
 int sbiem_steps_done(const sbiem_plan* p, int64_t* nsteps) {
@@ -692,9 +903,26 @@ int sbiem_stress(sbiem_plan* p, const double* slip_hist, int64_t nt, double dt, 
   if (!e) e = launch_fill_ring(dfd, p->precision, M - 1, RV, RG, (int)nint, s);
   const long long step = nint > 0 ? nint - 1 : 0;
   if (!e) e = hipMemcpyAsync(dyn->step, &step, sizeof(step), hipMemcpyHostToDevice, s);
+  std::vector<double2> tl;
+  if (!e && dtd->var) {
+    // interval l spans [l dt, (l + 1) dt]; the log keeps the last tlog_cap
+    tl.assign(dtd->tlog_cap, make_double2(0.0, 0.0));
+    for (int64_t l = std::max<int64_t>(0, nint - 1 - dtd->tlog_cap); l <= nint - 2; ++l)
+      tl[l % dtd->tlog_cap] = make_double2((double)l * dt, (double)(l + 1) * dt);
+    e = hipMemcpyAsync(dtd->tlog, tl.data(), sizeof(double2) * tl.size(), hipMemcpyHostToDevice, s);
+  }
   if (!e) e = hipStreamSynchronize(s);  // step lives on the host stack
   dyn->primed = false;
-  if (!e) e = prologue(*ex, s);
+  if (!e && dtd->var) {
+    const double t_new = (double)nt * dt;
+    const VarArgs va{dt, t_new - dt, t_new, 1, 0};
+    e = launch_reset_cells(*ex, s);
+    if (!e) e = launch_conv_var(*ex, va, s);
+    if (!e) e = launch_modes(*ex, 0, 1, s, va);
+    if (!e) e = launch_modes(*ex, 0, 0, s, va);
+  } else if (!e) {
+    e = prologue(*ex, s);
+  }
   if (!e) e = launch_elems(*ex, 0, s);
   if (!e) e = hipStreamSynchronize(s);
   const int slot = (int)((step + 1) & 1);
@@ -792,6 +1020,10 @@ int sbiem_tune(sbiem_plan* p, double dt, int64_t steps_per_trial, int32_t* conv_
   if (e) return hip_fail(p, e, "hipSetDevice");
   if (!p->exec) {
     if (int st = rebuild_exec(p)) return st;
+  }
+  if (p->dtd->var) {  // launch by launch: nothing to tune
+    if (conv_workgroups) *conv_workgroups = std::min(p->exec->ntasks, 4096);
+    return SBIEM_OK;
   }
   const char* what = "";
   int chosen = 0;

@@ -102,6 +102,14 @@ struct FaultDev {
   const void* twiddle;          // N/4+1 values cos(2 pi t / N), convolution precision
 
   long long* step;              // committed steps since state/dt were set
+  // variable steps and the interval rule (null/0 on the fixed-step engine)
+  double kcT, kcN;              // k_c L of the shear and normal windows
+  const double* ptab;           // primitive table: per node T = i h, (P^T, C^T, C^T',
+                                // P^N, C^N, C^N') in FP64
+  int ptab_len;                 // nodes
+  double ptab_h;                // node spacing h
+  double2* tlog;                // (start, end) time of committed interval l at l mod tlog_cap
+  int tlog_cap;
   int* err;                     // first failure status of the pending step (0 = none)
   int* err_count;               // failing elements of that pass
   int* err_index;               // first failing element
@@ -113,7 +121,7 @@ struct Tile {
   int fault, mode, p0, len;
   int Rn;          // ring capacity of the mode
   int part;        // fault-local index of the (task, mode) partial sum
-  int pad0, pad1;
+  int MT, MN;      // window lengths of the shear and normal kernels (lags >= M^X weigh 0)
   long long ring_off;
   double th;       // FP32 weights: c_s |k_n| dt / 2 / table spacing
   const void* rec; // the mode's first ring record (set per execution context)
@@ -147,6 +155,39 @@ constexpr double kTableStep = 1.0 / 16.0;  // spacing of the FP32 kernel table i
 constexpr int kMaxLdsBytes = 160 * 1024;
 constexpr int kMaxDynLds = kMaxLdsBytes - 4096;  // room for static LDS (reductions)
 
+// Launch arguments of a variable step (on = 0: the fixed-step engine, which
+// takes dt and times from the fault descriptor).
+struct VarArgs {
+  double dt;      // length of the step
+  double t_old;   // committed time at the start of the step
+  double t_new;   // t_old + dt
+  int on;
+  int pad;
+};
+
+// Quintic Hermite evaluation of the primitive table at T >= 0 (clamped to
+// the last cell): P^T and P^N from the nodes' values, first (C) and second
+// (C') derivatives.
+__host__ __device__ inline void ptab_eval(const double* __restrict__ tab, int len, double h,
+                                          double T, double* PT, double* PN) {
+  double x = T / h;
+  int i = (int)x;
+  if (i > len - 2) i = len - 2;
+  if (i < 0) i = 0;
+  const double t = x - (double)i;
+  const double t2 = t * t, t3 = t2 * t, t4 = t3 * t, t5 = t4 * t;
+  const double h0 = 1.0 - 10.0 * t3 + 15.0 * t4 - 6.0 * t5;
+  const double h1 = (t - 6.0 * t3 + 8.0 * t4 - 3.0 * t5) * h;
+  const double h2 = 0.5 * (t2 - 3.0 * t3 + 3.0 * t4 - t5) * h * h;
+  const double h3 = 10.0 * t3 - 15.0 * t4 + 6.0 * t5;
+  const double h4 = (-4.0 * t3 + 7.0 * t4 - 3.0 * t5) * h;
+  const double h5 = 0.5 * (t3 - 2.0 * t4 + t5) * h * h;
+  const double* a = tab + 6 * (size_t)i;
+  const double* b = a + 6;
+  *PT = h0 * a[0] + h1 * a[1] + h2 * a[2] + h3 * b[0] + h4 * b[1] + h5 * b[2];
+  *PN = h0 * a[3] + h1 * a[4] + h2 * a[5] + h3 * b[3] + h4 * b[4] + h5 * b[5];
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -168,6 +209,9 @@ void discarded_weights(double cs, double cp, double L, double dt, const std::vec
                        std::vector<double>* DN);
 void kernel_values(long double T, long double cs, long double cp, long double* CT,
                    long double* CN, long double* dCT, long double* dCN);
+// Primitives P^T, P^N of the kernels at T (integrals over [0, T]).
+void kernel_primitives(long double T, long double cs, long double cp, long double* PT,
+                       long double* PN);
 
 // Owner of a device allocation list.
 struct DevArena {
@@ -198,6 +242,25 @@ struct DtData {
   std::vector<ClosureMode> closure;  // closed modes (fault field 0)
   double4* tails = nullptr;          // closure tails at mode_pos (zero for open modes)
   std::vector<double> th_mode;       // table coordinate step theta_n / h per mode
+  std::vector<int> MT, MN;           // window lengths of the shear and normal kernels
+  bool var = false;                  // variable-step engine (ring of M_n + 1 intervals)
+  double* ptab = nullptr;            // primitive table (variable-step engine)
+  int ptab_len = 0;
+  double ptab_h = 0.0;
+  double2* tlog = nullptr;           // interval times (variable-step engine)
+  int tlog_cap = 0;
+};
+
+// Device snapshot of the committed state for step doubling (variable-step
+// engine): both state buffers, the spectral slip and rate accumulators and
+// the step counter; the full step's rate and state for the error measure.
+struct VarSnap {
+  DevArena mem;
+  double* el[12] = {};
+  double2* sp[6] = {};
+  long long* step = nullptr;
+  double *Vf = nullptr, *thf = nullptr;
+  unsigned long long* eps = nullptr;
 };
 
 // Dynamic state of one fault.
@@ -274,6 +337,11 @@ struct sbiem_plan {
   int precision = SBIEM_FP64;
   int theta_mode = SBIEM_THETA_PAPER;
   int newton_max = 100;                // FP64 Newton iterations per solve
+  int rule = SBIEM_RULE_MIDPOINT;      // history weights
+  double kcL[2] = {200.0, 200.0};      // k_c L of the shear and normal windows
+  bool adaptive = false;               // variable steps (dt of set_dt = dt_min)
+  double t_var = 0.0;                  // committed time on the variable-step engine
+  sbiem::VarSnap* snap = nullptr;      // step-doubling snapshot buffers
 
   bool friction_set = false, state_set = false;
   double Dc = 0, V_ref = 0, f0 = 0, tau_rate = 0, V_pl = 0, t0 = 0;
@@ -329,6 +397,10 @@ int hip_fail(sbiem_plan* p, hipError_t e, const char* what);
 std::vector<double> to_elem_order(const sbiem_plan* p, const double* x);
 hipError_t download_elems(const sbiem_plan* p, const double* dev, double* host);
 
+// Plans stepped by the variable-step engine (adaptive, or FP32 on the
+// interval rule).
+bool var_engine(const sbiem_plan* p);
+
 // Build the descriptor of a fault for an execution context.
 FaultDev make_fault_desc(sbiem_plan* p, DtData* dtd, DynData* dyn, double V_pl, double t0);
 // Allocate tables/ring for dt (host side computations + uploads).
@@ -345,10 +417,20 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
 // beside the pending step's passes, which it does not conflict with)
 hipError_t launch_conv(const Exec& ex, int ahead, hipStream_t s);
 // mode stage: kind 0 = pass-1 assembly from the stored state (measure != 0:
-// only the balance maxima), 1 = pass 2, 2 = commit and next pass 1
-hipError_t launch_modes(const Exec& ex, int kind, int measure, hipStream_t s);
+// only the balance maxima), 1 = pass 2, 2 = commit and next pass 1 (a
+// variable step commits only)
+hipError_t launch_modes(const Exec& ex, int kind, int measure, hipStream_t s,
+                        const VarArgs& va = VarArgs{0.0, 0.0, 0.0, 0, 0});
 // element stage: kind 0 = tractions only, 1 = pass 1, 2 = pass 2
-hipError_t launch_elems(const Exec& ex, int kind, hipStream_t s);
+hipError_t launch_elems(const Exec& ex, int kind, hipStream_t s,
+                        const VarArgs& va = VarArgs{0.0, 0.0, 0.0, 0, 0});
+// variable steps: history sums over every stored interval at time va.t_new
+hipError_t launch_conv_var(const Exec& ex, const VarArgs& va, hipStream_t s);
+// balance cells of every fault to "no maximum yet"
+hipError_t launch_reset_cells(const Exec& ex, hipStream_t s);
+// *out = bits of max_i max(|ln Va - ln Vb|, |ln tha - ln thb|) (zeroed first)
+hipError_t launch_err_norm(const double* Va, const double* tha, const double* Vb,
+                           const double* thb, int n, unsigned long long* out, hipStream_t s);
 // one fault: spectra A (of a) and B (of kappa a) at mode_pos for count real
 // signals a (natural element order, stride N); gF holds count * N complex
 hipError_t launch_forward(const FaultDev* d_fault, const FaultDev& h_fault, int precision,

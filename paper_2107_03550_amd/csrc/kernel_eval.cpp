@@ -153,4 +153,45 @@ void kernel_values(long double T, long double cs, long double cp, long double* C
     *dCN = 2.0L * T * (Wb - Wa) + (2.0L - qm2 / 2.0L) / eta * J0a + (q / 2.0L - 2.0L) * J0b;
 }
 
+// Primitives P^X(T) = integral of C^X over [0, T] (the interval weights of
+// the exact-integral rule and of variable steps), from the elementary
+// primitives of each term of C^T and C^N (W'(x) = -J1(x)/x, (x^2 J2)' = x^2 J1, (x J1)' = x J0):
+//   P^T = T^3 [W(eta T) - W(T)]/3 + T^2 [J2(eta T)/eta - J2(T)]/3
+//         + r T W(eta T) - T W(T) - (1 - J0(T))/2 - r T J1(eta T) + T J1(T)
+//   P^N = A T W(eta T) + B T W(T) - T^3 [W(eta T) - W(T)]/3
+//         - T^2 [J2(eta T)/eta - J2(T)]/3 + r T J1(eta T) - T J1(T)
+// with A = (q-2)^2 r/2 - r and B = 1 - q/2; J2 = 2 J1/x - J0.
+void kernel_primitives(long double T, long double cs, long double cp, long double* PT,
+                       long double* PN) {
+  const ld r = (cs / cp) * (cs / cp);
+  const ld q = 1.0L / r;
+  const ld eta = cp / cs;
+  if (T <= 0.0L) {
+    *PT = 0.0L;
+    *PN = 0.0L;
+    return;
+  }
+  ld J0a, J1a, Wa, J0b, J1b, Wb;
+  bessel_jw(eta * T, &J0a, &J1a, &Wa);
+  bessel_jw(T, &J0b, &J1b, &Wb);
+  const ld a = eta * T;
+  // J2 by the recurrence, or its series where that cancels
+  auto j2 = [](ld x, ld j0, ld j1) {
+    if (x < 1e-3L) {
+      const ld x2 = x * x;
+      return x2 / 8.0L * (1.0L - x2 / 12.0L + x2 * x2 / 384.0L);
+    }
+    return 2.0L * j1 / x - j0;
+  };
+  const ld J2a = j2(a, J0a, J1a), J2b = j2(T, J0b, J1b);
+  const ld T2 = T * T;
+  const ld cubic = T2 * T * (Wa - Wb) / 3.0L + T2 * (J2a / eta - J2b) / 3.0L;
+  // 1 - J0(T) without cancellation at small T
+  const ld one_m_j0 = T < 1e-3L ? T2 / 4.0L * (1.0L - T2 / 16.0L) : 1.0L - J0b;
+  *PT = cubic + r * T * Wa - T * Wb - 0.5L * one_m_j0 - r * T * J1a + T * J1b;
+  const ld A = (q - 2.0L) * (q - 2.0L) * r / 2.0L - r;
+  const ld B = 1.0L - q / 2.0L;
+  *PN = A * T * Wa + B * T * Wb - cubic + r * T * J1a - T * J1b;
+}
+
 }  // namespace sbiem

@@ -364,8 +364,8 @@ __device__ __forceinline__ float4 conv32_weigh(const Tile& tl, long long step, i
     float wT = h00 * n0.x + h10 * n0.y + h01 * n1.x + h11 * n1.y;
     float wN = h00 * n0.z + h10 * n0.w + h01 * n1.z + h11 * n1.w;
     const bool use = (q != 0) && (p < end);
-    wT = use ? wT : 0.f;
-    wN = use ? wN : 0.f;
+    wT = (use && j < tl.MT) ? wT : 0.f;   // each kind's own window
+    wN = (use && j < tl.MN) ? wN : 0.f;
     acc.x = fmaf(wT, h[u].x, acc.x);
     acc.y = fmaf(wT, h[u].y, acc.y);
     acc.z = fmaf(wN, h[u].z, acc.z);
@@ -787,11 +787,32 @@ __device__ __forceinline__ ModeSlot mode_slot(int t, int N, int lP, int lQ, int 
   return s;
 }
 
+// Weight of the current interval (lag span [0, dt]) of mode n in a variable
+// step: P^X(c_s |k_n| min(dt, T_w^X)) / (c_s |k_n|), added to (1 - r) dt.
+__device__ __forceinline__ void var_lag0(const FaultDev& fd, int n, double dt, double c1,
+                                         double* aT, double* aN) {
+  *aT = c1 * dt;
+  *aN = c1 * dt;
+  if (n == 0) return;
+  const double kL = 2.0 * M_PI * (double)n;
+  const double csk = fd.cs * kL / fd.L;
+  const double T = csk * dt;
+  const double cutT = fmin(kL, fd.kcT), cutN = fmin(kL, fd.kcN);
+  double pt, pn;
+  ptab_eval(fd.ptab, fd.ptab_len, fd.ptab_h, fmin(T, cutT), &pt, &pn);
+  if (cutN != cutT) {
+    double x;
+    ptab_eval(fd.ptab, fd.ptab_len, fd.ptab_h, fmin(T, cutN), &x, &pn);
+  }
+  *aT += pt / csk;
+  *aN += pn / csk;
+}
+
 template <typename R, int KIND>
 __global__ void __launch_bounds__(kModeThreads)
 k_modes(const FaultDev* __restrict__ faults, const int2* __restrict__ map, int measure,
         const void* __restrict__ gF_in, double2* __restrict__ outA, double2* __restrict__ outB,
-        long long stride_out, int* __restrict__ conv_ctr) {
+        long long stride_out, int* __restrict__ conv_ctr, VarArgs va) {
   using C = typename Prec<R>::C;
   using Rec = typename Prec<R>::Rec;
   extern __shared__ unsigned char smem_raw[];
@@ -811,7 +832,7 @@ k_modes(const FaultDev* __restrict__ faults, const int2* __restrict__ map, int m
   long long* stepp = fd.step;
   const int ngroups = fd.ngroups;
   const double inv_s = 1.0 / fd.fwd_scale;
-  const double dt = fd.dt, c1 = 1.0 - fd.r;
+  const double dt = va.on ? va.dt : fd.dt, c1 = 1.0 - fd.r;
   int err = 0;
   long long l = 0;
   int e_in = 0;
@@ -873,7 +894,8 @@ k_modes(const FaultDev* __restrict__ faults, const int2* __restrict__ map, int m
       outB[(size_t)blockIdx.y * stride_out + pm] = Bv;
       return;
     }
-    const ModeCoef& cf = in.cf;
+    ModeCoef cf = in.cf;
+    if (va.on) var_lag0(fd, sl.n, dt, c1, &cf.aT, &cf.aN);
     double4 S = in.S0;
     if (KIND != 1) {
       if (cf.nparts == 0) {  // no ring records: only a closure tail (none for such modes)
@@ -970,6 +992,7 @@ k_modes(const FaultDev* __restrict__ faults, const int2* __restrict__ map, int m
       const int prev = atomicAdd(done, 1);
       if (prev == ngroups - 1) {
         atomicExch(done, 0);
+        if (va.on) fd.tlog[l % fd.tlog_cap] = make_double2(va.t_old, va.t_new);
         *stepp = l + 1;
       }
     }
@@ -1180,7 +1203,7 @@ __device__ __forceinline__ double friction_element(const FaultDev& fd, const Fri
 template <typename R, int KIND>
 __global__ void __launch_bounds__(kElemThreads)
 k_elems(const FaultDev* __restrict__ faults, const int2* __restrict__ map,
-        const double* __restrict__ in, void* __restrict__ gF_out) {
+        const double* __restrict__ in, void* __restrict__ gF_out, VarArgs va) {
   using C = typename Prec<R>::C;
   extern __shared__ unsigned char smem_raw[];
   const int2 w = map ? map[blockIdx.x] : make_int2(0, (int)blockIdx.x * faults[0].ncls);
@@ -1210,8 +1233,8 @@ k_elems(const FaultDev* __restrict__ faults, const int2* __restrict__ map,
     k.f0 = fd.f0;
     k.Vref_Dc = fd.V_ref / fd.Dc;
     k.Dc = fd.Dc;
-    k.dt = fd.dt;
-    k.t_new_load = fd.tau_rate * (fd.t0 + (double)(l + 1) * fd.dt);
+    k.dt = va.on ? va.dt : fd.dt;
+    k.t_new_load = fd.tau_rate * (va.on ? va.t_new : fd.t0 + (double)(l + 1) * fd.dt);
     k.V_pl = fd.V_pl;
     k.s = s;
     k.theta_mode = fd.theta_mode;
@@ -1304,6 +1327,145 @@ k_elems(const FaultDev* __restrict__ faults, const int2* __restrict__ map,
     const C tw = (t == t0) ? tw0 : twiddle_full<C, R>(tq, b * cc, N);
     gF[(size_t)cc * Q + b] = cmul(Y[v * vs + lx(cc, 3)], tw);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Variable steps (section 3.2).  Slot p of mode n's ring (capacity R_n)
+// holds interval I(p) = b - ((b - p) mod R_n), b = step - 1 the last
+// committed interval (none while I < 0), whose start and end times are in
+// the fault's interval log.  At the step's end time t_new its lag span is
+// [tau_a, tau_b] = [t_new - end, t_new - start], and its weight for kind X
+//   w^X = [P^X(min(c_s|k_n| tau_b, T^X)) - P^X(min(c_s|k_n| tau_a, T^X))] / (c_s|k_n|)
+// with T^X = min(|k_n| L, k_c^X L) the window end in units of c_s|k|t: the
+// exact integral of the kernel over the part of the interval inside the
+// window.  Every stored interval is summed (lag 1 included: the mode stage
+// adds no separate lag-1 term on this engine).  One workgroup per task,
+// FP64 accumulation, the same (task, mode) partials as the fixed-step conv.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(kConvThreads)
+k_conv_var(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
+           const ConvTask* __restrict__ tasks, int ntasks, VarArgs va) {
+  using Rec = typename Prec<R>::Rec;
+  constexpr int U = kTileSlots64 / 64;
+  __shared__ TaskLds L;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wpb = kConvThreads / 64;
+  for (int task = blockIdx.x; task < ntasks; task += gridDim.x) {
+    const ConvTask tk = tasks[task];
+    const int nt = tk.t1 - tk.t0;
+    const FaultDev& fd = faults[tiles[tk.t0].fault];
+    const int err = *fd.err;
+    const long long b = *fd.step - 1;
+    for (int k = wave; k < nt; k += wpb) {
+      const Tile tl = tiles[tk.t0 + k];
+      double ax = 0.0, ay = 0.0, gx = 0.0, gy = 0.0;
+      if (err == 0 && b >= 0) {
+        const int Rn = tl.Rn;
+        const double kL = 2.0 * M_PI * (double)tl.mode;
+        const double csk = fd.cs * kL / fd.L, inv = 1.0 / csk;
+        const double cutT = fmin(kL, fd.kcT), cutN = fmin(kL, fd.kcN);
+        const Rec* __restrict__ ring = (const Rec*)fd.ring + tl.ring_off;
+        const int end = tl.p0 + tl.len;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int p = tl.p0 + lane + 64 * u;
+          if (p >= end) continue;
+          const long long I = b - (long long)mod_pos(b - p + (long long)Rn * 4, Rn);
+          if (I < 0) continue;
+          const double2 iv = fd.tlog[I % fd.tlog_cap];
+          const double Ta = csk * (va.t_new - iv.y), Tb = csk * (va.t_new - iv.x);
+          double pTa, pNa, pTb, pNb;
+          ptab_eval(fd.ptab, fd.ptab_len, fd.ptab_h, fmin(Ta, cutT), &pTa, &pNa);
+          ptab_eval(fd.ptab, fd.ptab_len, fd.ptab_h, fmin(Tb, cutT), &pTb, &pNb);
+          const double wT = (pTb - pTa) * inv;
+          if (cutN != cutT) {
+            double x;
+            ptab_eval(fd.ptab, fd.ptab_len, fd.ptab_h, fmin(Ta, cutN), &x, &pNa);
+            ptab_eval(fd.ptab, fd.ptab_len, fd.ptab_h, fmin(Tb, cutN), &x, &pNb);
+          }
+          const double wN = (pNb - pNa) * inv;
+          const Rec r = ring[p];
+          if constexpr (sizeof(R) == 4) {
+            ax = fma(wT, (double)r.x, ax);
+            ay = fma(wT, (double)r.y, ay);
+            gx = fma(wN, (double)r.z, gx);
+            gy = fma(wN, (double)r.w, gy);
+          } else {
+            ax = fma(wT, r.v.x, ax);
+            ay = fma(wT, r.v.y, ay);
+            gx = fma(wN, r.g.x, gx);
+            gy = fma(wN, r.g.y, gy);
+          }
+        }
+      }
+      Rec64 acc;
+      acc.v = d2(ax, ay);
+      acc.g = d2(gx, gy);
+      acc = wave_reduce_r64(acc);
+      if (lane == 0) {
+        L.part[k] = make_double4(acc.v.x, acc.v.y, acc.g.x, acc.g.y);
+        L.id[k] = tl.part;
+      }
+    }
+    __syncthreads();
+    finish_task(fd, L, nt);
+    __syncthreads();
+  }
+}
+
+__global__ void k_reset_cells(const FaultDev* __restrict__ faults, int nfaults) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nfaults) return;
+  int* c = faults[f].cells;
+  c[0] = kNoExp;
+  c[1] = kNoExp;
+  c[2] = kNoExp;
+  c[3] = kNoExp;
+}
+
+// max_i max(|ln Va_i - ln Vb_i|, |ln tha_i - ln thb_i|), folded into *out as
+// the bit pattern of a non-negative double (which orders like its bits).
+__global__ void k_err_norm(const double* __restrict__ Va, const double* __restrict__ tha,
+                           const double* __restrict__ Vb, const double* __restrict__ thb, int n,
+                           unsigned long long* __restrict__ out) {
+  double m = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double e1 = fabs(log(Va[i]) - log(Vb[i]));
+    const double e2 = fabs(log(tha[i]) - log(thb[i]));
+    m = fmax(m, fmax(e1, e2));
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+hipError_t launch_conv_var(const Exec& ex, const VarArgs& va, hipStream_t s) {
+  if (ex.ntasks == 0) return hipSuccess;
+  const int grid = std::min(ex.ntasks, 4096);
+  if (ex.precision == SBIEM_FP32CONV)
+    hipLaunchKernelGGL(k_conv_var<float>, dim3(grid), dim3(kConvThreads), 0, s, ex.d_faults,
+                       ex.d_tiles, ex.d_tasks, ex.ntasks, va);
+  else
+    hipLaunchKernelGGL(k_conv_var<double>, dim3(grid), dim3(kConvThreads), 0, s, ex.d_faults,
+                       ex.d_tiles, ex.d_tasks, ex.ntasks, va);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_cells(const Exec& ex, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_cells, dim3((ex.nfaults + 63) / 64), dim3(64), 0, s, ex.d_faults,
+                     ex.nfaults);
+  return hipGetLastError();
+}
+
+hipError_t launch_err_norm(const double* Va, const double* tha, const double* Vb,
+                           const double* thb, int n, unsigned long long* out, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(out, 0, sizeof(unsigned long long), s);
+  if (e) return e;
+  const int blocks = std::max(1, std::min((n + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_err_norm, dim3(blocks), dim3(256), 0, s, Va, tha, Vb, thb, n, out);
+  return hipGetLastError();
 }
 
 // Stress path: ring slot p of mode n receives the latest interval
@@ -1457,47 +1619,47 @@ hipError_t launch_conv(const Exec& ex, int ahead, hipStream_t s) {
 }
 
 template <typename R>
-static void modes_kind(const Exec& ex, int kind, int measure, hipStream_t s) {
+static void modes_kind(const Exec& ex, int kind, int measure, hipStream_t s, const VarArgs& va) {
   const dim3 grid(ex.mode_blocks), block(kModeThreads);
   const size_t lds = ex.mode_lds;
   const int2* map = ex.nfaults == 1 ? nullptr : ex.d_mode_map;  // one fault: group = block
   switch (kind) {
     case 0:
       k_modes<R, 0><<<grid, block, lds, s>>>(ex.d_faults, map, measure, nullptr, nullptr,
-                                              nullptr, 0, ex.conv_ctr);
+                                              nullptr, 0, ex.conv_ctr, va);
       break;
     case 1:
       k_modes<R, 1><<<grid, block, lds, s>>>(ex.d_faults, map, 0, nullptr, nullptr,
-                                              nullptr, 0, nullptr);
+                                              nullptr, 0, nullptr, va);
       break;
     default:
       k_modes<R, 2><<<grid, block, lds, s>>>(ex.d_faults, map, 0, nullptr, nullptr,
-                                              nullptr, 0, ex.conv_ctr);
+                                              nullptr, 0, ex.conv_ctr, va);
       break;
   }
 }
 
-hipError_t launch_modes(const Exec& ex, int kind, int measure, hipStream_t s) {
-  if (ex.precision == SBIEM_FP32CONV) modes_kind<float>(ex, kind, measure, s);
-  else modes_kind<double>(ex, kind, measure, s);
+hipError_t launch_modes(const Exec& ex, int kind, int measure, hipStream_t s, const VarArgs& va) {
+  if (ex.precision == SBIEM_FP32CONV) modes_kind<float>(ex, kind, measure, s, va);
+  else modes_kind<double>(ex, kind, measure, s, va);
   return hipGetLastError();
 }
 
 template <typename R>
-static void elems_kind(const Exec& ex, int kind, hipStream_t s) {
+static void elems_kind(const Exec& ex, int kind, hipStream_t s, const VarArgs& va) {
   const dim3 grid(ex.elem_blocks), block(kElemThreads);
   const size_t lds = ex.elem_lds;
   const int2* map = ex.nfaults == 1 ? nullptr : ex.d_elem_map;
   switch (kind) {
-    case 0: k_elems<R, 0><<<grid, block, lds, s>>>(ex.d_faults, map, nullptr, nullptr); break;
-    case 1: k_elems<R, 1><<<grid, block, lds, s>>>(ex.d_faults, map, nullptr, nullptr); break;
-    default: k_elems<R, 2><<<grid, block, lds, s>>>(ex.d_faults, map, nullptr, nullptr); break;
+    case 0: k_elems<R, 0><<<grid, block, lds, s>>>(ex.d_faults, map, nullptr, nullptr, va); break;
+    case 1: k_elems<R, 1><<<grid, block, lds, s>>>(ex.d_faults, map, nullptr, nullptr, va); break;
+    default: k_elems<R, 2><<<grid, block, lds, s>>>(ex.d_faults, map, nullptr, nullptr, va); break;
   }
 }
 
-hipError_t launch_elems(const Exec& ex, int kind, hipStream_t s) {
-  if (ex.precision == SBIEM_FP32CONV) elems_kind<float>(ex, kind, s);
-  else elems_kind<double>(ex, kind, s);
+hipError_t launch_elems(const Exec& ex, int kind, hipStream_t s, const VarArgs& va) {
+  if (ex.precision == SBIEM_FP32CONV) elems_kind<float>(ex, kind, s, va);
+  else elems_kind<double>(ex, kind, s, va);
   return hipGetLastError();
 }
 
@@ -1507,14 +1669,15 @@ hipError_t launch_forward(const FaultDev* d_fault, const FaultDev& h, int precis
   if (count <= 0) return hipSuccess;
   const dim3 eg((unsigned)(h.Q / h.ncls), (unsigned)count), mg((unsigned)h.ngroups, (unsigned)count);
   const size_t el = elem_lds_bytes(precision, h.log2P, h.ncls), ml = mode_lds_bytes(precision, h.log2Q);
+  const VarArgs off{0.0, 0.0, 0.0, 0, 0};
   if (precision == SBIEM_FP32CONV) {
-    k_elems<float, 3><<<eg, dim3(kElemThreads), el, s>>>(d_fault, nullptr, a, gF);
+    k_elems<float, 3><<<eg, dim3(kElemThreads), el, s>>>(d_fault, nullptr, a, gF, off);
     k_modes<float, 3><<<mg, dim3(kModeThreads), ml, s>>>(d_fault, nullptr, 0, gF, A, B, stride_out,
-                                                          nullptr);
+                                                          nullptr, off);
   } else {
-    k_elems<double, 3><<<eg, dim3(kElemThreads), el, s>>>(d_fault, nullptr, a, gF);
+    k_elems<double, 3><<<eg, dim3(kElemThreads), el, s>>>(d_fault, nullptr, a, gF, off);
     k_modes<double, 3><<<mg, dim3(kModeThreads), ml, s>>>(d_fault, nullptr, 0, gF, A, B, stride_out,
-                                                           nullptr);
+                                                           nullptr, off);
   }
   return hipGetLastError();
 }

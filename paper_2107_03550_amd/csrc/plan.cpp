@@ -145,10 +145,10 @@ T* upload(sbiem::DevArena& mem, const std::vector<T>& v, hipStream_t s, hipError
 }  // namespace
 
 // Window lengths M_n (n = 0..N/2) exactly as the windows are defined:
-// T_w = (L/c_s) min(1, k_c/|k|), k_c = 200/L, M = ceil(x - 1e-9 x), x = T_w/dt.
-std::vector<int> window_steps(int64_t N, double L, double cs, double dt) {
+// T_w = (L/c_s) min(1, k_c/|k|), k_c = kcL/L, M = ceil(x - 1e-9 x), x = T_w/dt.
+std::vector<int> window_steps(int64_t N, double L, double cs, double dt, double kcL) {
   std::vector<int> M(N / 2 + 1);
-  const double kc = 200.0 / (1.0 * L);
+  const double kc = kcL / (1.0 * L);
   for (int64_t n = 0; n <= N / 2; ++n) {
     const double k = 2.0 * M_PI * (double)n / L;
     const double ratio = k > kc ? kc / k : 1.0;
@@ -166,35 +166,110 @@ int closure_kept(int M, double cut) {
   return (Mk >= 18 && Mk < M) ? Mk : M;
 }
 
+bool var_engine(const sbiem_plan* p) {
+  return p->adaptive || (p->rule == SBIEM_RULE_INTERVAL && p->precision == SBIEM_FP32CONV);
+}
+
+namespace {
+
+// Weights (w^T, w^N) of lags j = 0..count-1 of mode n at step dt for the
+// plan's rule; zero from each kind's window length on.  theta = c_s |k| dt / 2.
+void lag_weights(const sbiem_plan* p, int n, double dt, int MT, int MN, int j0, int count,
+                 std::vector<long double>* wT, std::vector<long double>* wN) {
+  const long double cs = p->cs, cp = p->cp;
+  const long double theta = kPiL * cs * (long double)dt / (long double)p->L * n;
+  wT->assign(count, 0.0L);
+  wN->assign(count, 0.0L);
+  if (n == 0) return;
+  if (p->rule == SBIEM_RULE_MIDPOINT) {
+    for (int c = 0; c < count; ++c) {
+      const int j = j0 + c;
+      if (j >= MT && j >= MN) continue;
+      long double CT, CN;
+      kernel_values(theta * (long double)(2 * j + 1), cs, cp, &CT, &CN, nullptr, nullptr);
+      (*wT)[c] = j < MT ? dt * CT : 0.0L;
+      (*wN)[c] = j < MN ? dt * CN : 0.0L;
+    }
+    return;
+  }
+  // INTERVAL: [P(min((2j+2) theta, Tcut)) - P(min(2j theta, Tcut))] dt / (2 theta)
+  const long double kL = 2.0L * kPiL * n;
+  const long double cutT = std::min(kL, (long double)p->kcL[0]);
+  const long double cutN = std::min(kL, (long double)p->kcL[1]);
+  const long double scale = (long double)dt / (2.0L * theta);
+  auto prim = [&](int b, long double* PT, long double* PN) {
+    const long double T = theta * (long double)(2 * b);
+    long double pt, pn;
+    kernel_primitives(std::min(T, cutT), cs, cp, &pt, &pn);
+    *PT = pt;
+    if (cutN != cutT) kernel_primitives(std::min(T, cutN), cs, cp, &pt, &pn);
+    *PN = pn;
+  };
+  long double pT0, pN0;
+  prim(j0, &pT0, &pN0);
+  for (int c = 0; c < count; ++c) {
+    const int j = j0 + c;
+    long double pT1, pN1;
+    prim(j + 1, &pT1, &pN1);
+    (*wT)[c] = j < MT ? (pT1 - pT0) * scale : 0.0L;
+    (*wN)[c] = j < MN ? (pN1 - pN0) * scale : 0.0L;
+    pT0 = pT1;
+    pN0 = pN1;
+  }
+}
+
+}  // namespace
+
 int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
   *out = nullptr;
   DtData* d = new DtData();
   d->dt = dt;
+  d->var = var_engine(p);
   const int64_t N = p->N;
   const int half = (int)(N / 2);
-  d->M = window_steps(N, p->L, p->cs, dt);
+  d->MT = window_steps(N, p->L, p->cs, dt, p->kcL[0]);
+  d->MN = window_steps(N, p->L, p->cs, dt, p->kcL[1]);
+  d->M.assign(half + 1, 0);
+  for (int n = 0; n <= half; ++n) d->M[n] = std::max(d->MT[n], d->MN[n]);
+  // the variable-step ring holds intervals as short as the half steps of an
+  // attempt at dt_min (adaptive plans) or dt itself
+  std::vector<int> Mvar;
+  if (d->var) {
+    const double hmin = p->adaptive ? 0.5 * dt : dt;
+    const std::vector<int> a = window_steps(N, p->L, p->cs, hmin, p->kcL[0]);
+    const std::vector<int> b = window_steps(N, p->L, p->cs, hmin, p->kcL[1]);
+    Mvar.assign(half + 1, 0);
+    for (int n = 0; n <= half; ++n) Mvar[n] = std::max(a[n], b[n]);
+  }
   d->Rn.assign(half + 1, 0);
   d->ring_off.assign(half + 1, 0);
   long long slots = 0;
+  int Rmax = 0;
   for (int n = 1; n <= half; ++n) {
-    // the learned closure keeps M'_n lags of the modes it closes
-    const int kept = p->closure_on ? closure_kept(d->M[n], p->closure_cut) : d->M[n];
-    d->Rn[n] = kept - 1;
+    if (d->var) {
+      // every interval a step at dt >= dt_min can still reach (M_n), plus
+      // the two a rejected two-half-step attempt writes: the slots they
+      // overwrite then hold intervals strictly past every window
+      d->Rn[n] = Mvar[n] + 2;
+    } else {
+      // the learned closure keeps M'_n lags of the modes it closes
+      const int kept = p->closure_on ? closure_kept(d->M[n], p->closure_cut) : d->M[n];
+      d->Rn[n] = kept - 1;
+    }
     d->ring_off[n] = slots;
     slots += d->Rn[n];
+    Rmax = std::max(Rmax, d->Rn[n]);
   }
   d->ring_slots = slots;
   // conv tiles (one wavefront each) and tasks (one workgroup each): a task
   // holds whole modes up to task_tiles tiles, a longer mode is cut into
   // pieces of task_tiles tiles
   // (FP32 under the learned closure: shorter tiles, most kept windows being
-  // far shorter than a full tile)
-  const bool short_tiles = p->precision == SBIEM_FP32CONV && p->closure_on;
-  const int tile = p->precision == SBIEM_FP32CONV ? (short_tiles ? kTileSlots32s : kTileSlots32)
-                                                  : kTileSlots64;
-  const int task_tiles = p->precision == SBIEM_FP32CONV
-                             ? (short_tiles ? kTaskTiles32s : kTaskTiles32)
-                             : kTaskTiles64;
+  // far shorter than a full tile; the variable-step conv uses FP64 tiles)
+  const bool fp32 = p->precision == SBIEM_FP32CONV && !d->var;
+  const bool short_tiles = fp32 && p->closure_on;
+  const int tile = fp32 ? (short_tiles ? kTileSlots32s : kTileSlots32) : kTileSlots64;
+  const int task_tiles = fp32 ? (short_tiles ? kTaskTiles32s : kTaskTiles32) : kTaskTiles64;
   d->tile_slots = tile;
   const long double th_unit = 3.141592653589793238462643383279502884L * (long double)p->cs *
                               (long double)dt / (long double)p->L / (long double)kTableStep;
@@ -226,7 +301,8 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
       t.len = std::min(tile, d->Rn[n] - k * tile);
       t.Rn = d->Rn[n];
       t.part = part;
-      t.pad0 = t.pad1 = 0;
+      t.MT = d->MT[n];
+      t.MN = d->MN[n];
       t.ring_off = d->ring_off[n];
       t.th = (double)(th_unit * n);
       d->tiles.push_back(t);
@@ -237,30 +313,21 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
     d->nparts[n] = 1 + (extra - extra0);
   }
   const int parts = extra;
-  // per-mode constants
-  const long double cs = p->cs, cp = p->cp;
-  const long double theta_unit = kPiL * cs * (long double)dt / (long double)p->L;  // c_s k_1 dt / 2
+  // per-mode constants: lags 0 and 1 of the plan's rule (the variable-step
+  // engine recomputes lag 0 per step and keeps lag 1 in its sums)
   std::vector<ModeCoef> coef(half + 1);
   const double c1 = 1.0 - p->r;
-  // two extended-precision kernel evaluations per mode: spread over threads
-  // for large N (each mode writes its own entry)
   auto mode_coef = [&](int n) {
     const double kabs = 2.0 * M_PI * (double)n / p->L;
-    const long double theta = theta_unit * n;  // c_s |k_n| dt / 2
-    long double CT, CN;
-    kernel_values(theta, cs, cp, &CT, &CN, nullptr, nullptr);
+    std::vector<long double> wT, wN;
+    lag_weights(p, n, dt, d->MT[n], d->MN[n], 0, 2, &wT, &wN);
     ModeCoef& c = coef[mode_pos(n, p->log2P, p->log2Q)];
     c.mk = -p->mu * kabs;
     c.ms = (n == 0 || 2 * n == N) ? 0.0 : p->mu;
-    c.aT = c1 * dt + (double)(dt * CT);
-    c.aN = c1 * dt + (double)(dt * CN);
-    if (d->M[n] >= 2) {
-      kernel_values(3.0L * theta, cs, cp, &CT, &CN, nullptr, nullptr);
-      c.w1T = (double)(dt * CT);
-      c.w1N = (double)(dt * CN);
-    } else {
-      c.w1T = c.w1N = 0.0;
-    }
+    c.aT = c1 * dt + (double)wT[0];
+    c.aN = c1 * dt + (double)wN[0];
+    c.w1T = d->var ? 0.0 : (double)wT[1];
+    c.w1N = d->var ? 0.0 : (double)wN[1];
     c.ring_off = d->ring_off[n];
     c.Rn = d->Rn[n];
     c.part0 = d->part0[n];
@@ -326,27 +393,38 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
     if (!d->ring) e = hipErrorOutOfMemory;
     else e = hipMemsetAsync(d->ring, 0, (size_t)std::max<long long>(slots, 1) * rec, s);
   }
-  if (!e && p->precision == SBIEM_FP64) {
+  if (!e && p->precision == SBIEM_FP64 && !d->var) {
     // FP64 weights in ring order: slot q of mode n holds the weights of lag
     // j = R_n - q + 1 (q >= 1); q = 0 is the lag-1 slot, weight 0.
     std::vector<double2> w(std::max<long long>(slots, 1));
-    for (int n = 1; n <= half; ++n) {
+    auto fill = [&](int n) {
       const int Rn = d->Rn[n];
-      if (Rn <= 0) continue;
+      if (Rn <= 0) return;
       const long long off = d->ring_off[n];
       w[off] = make_double2(0.0, 0.0);
+      if (Rn < 2) return;
+      // lags 2..Rn in one pass
+      std::vector<long double> wT, wN;
+      lag_weights(p, n, dt, d->MT[n], d->MN[n], 2, Rn - 1, &wT, &wN);
       for (int q = 1; q < Rn; ++q) {
         const int j = Rn - q + 1;
-        long double CT, CN;
-        kernel_values(theta_unit * (long double)n * (long double)(2 * j + 1), cs, cp, &CT, &CN,
-                      nullptr, nullptr);
-        w[off + q] = make_double2((double)(dt * CT), (double)(dt * CN));
+        w[off + q] = make_double2((double)wT[j - 2], (double)wN[j - 2]);
       }
-    }
+    };
+    const int nth = slots >= (1 << 20) ? 8 : 1;
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nth; ++t)
+      pool.emplace_back([&, t]() {
+        for (int n = 1 + t; n <= half; n += nth) fill(n);
+      });
+    for (int n = 1; n <= half; n += nth) fill(n);
+    for (auto& th : pool) th.join();
     d->wrev = upload(d->mem, w, s, &e);
   }
-  if (!e && p->precision == SBIEM_FP32CONV) {
+  const long double cs = p->cs, cp = p->cp;
+  if (!e && p->precision == SBIEM_FP32CONV && !d->var) {
     // Hermite table on T = i h covering every lag (plus the skipped slot).
+    const long double theta_unit = kPiL * cs * (long double)dt / (long double)p->L;
     double Tmax = 0.0;
     for (int n = 1; n <= half; ++n)
       Tmax = std::max(Tmax, (double)(theta_unit * n) * (2.0 * (d->Rn[n] + 1) + 3.0));
@@ -363,6 +441,39 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
       }
       d->table_len = K;
       d->table = upload(d->mem, tab, s, &e);
+    }
+  }
+  if (!e && d->var) {
+    // primitive table: the largest argument is the largest window end,
+    // c_s |k| T_w = min(|k| L, k_c L) <= min(pi N, max k_c L)
+    const double Tmax = std::min(M_PI * (double)N, std::max(p->kcL[0], p->kcL[1]));
+    const double h = 1.0 / 32.0;
+    const int K = (int)std::ceil(Tmax / h) + 3;
+    std::vector<double> tab(6 * (size_t)K);
+    auto node = [&](int i) {
+      long double PT, PN, CT, CN, dCT, dCN;
+      const long double T = (long double)i * (long double)h;
+      kernel_primitives(T, cs, cp, &PT, &PN);
+      kernel_values(T, cs, cp, &CT, &CN, &dCT, &dCN);
+      double* q = &tab[6 * (size_t)i];
+      q[0] = (double)PT;
+      q[1] = (double)CT;
+      q[2] = (double)dCT;
+      q[3] = (double)PN;
+      q[4] = (double)CN;
+      q[5] = (double)dCN;
+    };
+    for (int i = 0; i < K; ++i) node(i);
+    d->ptab_len = K;
+    d->ptab_h = h;
+    d->ptab = upload(d->mem, tab, s, &e);
+    // the log entries of every referenced interval survive the two entries
+    // a rejected attempt writes
+    d->tlog_cap = Rmax + 2;
+    if (!e) {
+      d->tlog = (double2*)d->mem.get(sizeof(double2) * d->tlog_cap);
+      if (!d->tlog) e = hipErrorOutOfMemory;
+      else e = hipMemsetAsync(d->tlog, 0, sizeof(double2) * d->tlog_cap, s);
     }
   }
   if (!e) e = hipStreamSynchronize(s);
@@ -565,6 +676,15 @@ FaultDev make_fault_desc(sbiem_plan* p, DtData* dtd, DynData* dyn, double V_pl, 
     f.wrev = dtd->wrev;
   }
   f.twiddle = p->twiddle;
+  f.kcT = p->kcL[0];
+  f.kcN = p->kcL[1];
+  if (dtd && dtd->var) {
+    f.ptab = dtd->ptab;
+    f.ptab_len = dtd->ptab_len;
+    f.ptab_h = dtd->ptab_h;
+    f.tlog = dtd->tlog;
+    f.tlog_cap = dtd->tlog_cap;
+  }
   f.step = dyn->step;
   f.err = dyn->err;
   f.err_count = dyn->err_count;
@@ -758,6 +878,7 @@ int sbiem_plan_destroy(sbiem_plan* p) {
   delete p->exec;
   delete p->dtd;
   delete p->dyn;
+  delete p->snap;
   delete p;
   return SBIEM_OK;
 }
@@ -778,6 +899,56 @@ int sbiem_set_theta_mode(sbiem_plan* p, int mode) {
   if (mode != SBIEM_THETA_PAPER && mode != SBIEM_THETA_EXP) return fail(p, SBIEM_EINVAL, "unknown theta mode");
   p->theta_mode = mode;
   return refresh_desc(p);
+}
+
+int sbiem_set_rule(sbiem_plan* p, int rule) {
+  if (int s = check_plan(p)) return s;
+  if (rule != SBIEM_RULE_MIDPOINT && rule != SBIEM_RULE_INTERVAL)
+    return fail(p, SBIEM_EINVAL, "set_rule: unknown rule");
+  if (p->dtd) return fail(p, SBIEM_EINVAL, "set_rule: the rule must be chosen before the time step");
+  if (p->adaptive && rule != SBIEM_RULE_INTERVAL)
+    return fail(p, SBIEM_EINVAL, "set_rule: variable steps use the interval rule");
+  if (p->closure_on && rule != SBIEM_RULE_MIDPOINT)
+    return fail(p, SBIEM_EINVAL, "set_rule: the learned closure uses the midpoint rule");
+  p->rule = rule;
+  return SBIEM_OK;
+}
+
+int sbiem_set_cutoffs(sbiem_plan* p, double kcL_shear, double kcL_normal) {
+  if (int s = check_plan(p)) return s;
+  if (!(kcL_shear >= 1.0 && kcL_shear <= 1e6) || !(kcL_normal >= 1.0 && kcL_normal <= 1e6))
+    return fail(p, SBIEM_EINVAL, "set_cutoffs: need 1 <= k_c L <= 1e6");
+  if (p->dtd) return fail(p, SBIEM_EINVAL, "set_cutoffs: the cut-offs must be chosen before the time step");
+  if (p->closure_on && kcL_shear != kcL_normal)
+    return fail(p, SBIEM_EINVAL, "set_cutoffs: the learned closure needs equal cut-offs");
+  p->kcL[0] = kcL_shear;
+  p->kcL[1] = kcL_normal;
+  return refresh_desc(p);
+}
+
+int sbiem_set_adaptive(sbiem_plan* p, int on) {
+  if (int s = check_plan(p)) return s;
+  if (p->dtd) return fail(p, SBIEM_EINVAL, "set_adaptive: must precede the time step");
+  if (on && p->closure_on) return fail(p, SBIEM_EINVAL, "set_adaptive: not with the learned closure");
+  if (on && p->batch_refs > 0) return fail(p, SBIEM_EINVAL, "set_adaptive: plan is used by a batch");
+  p->adaptive = on != 0;
+  if (p->adaptive) p->rule = SBIEM_RULE_INTERVAL;
+  return SBIEM_OK;
+}
+
+int sbiem_kernel_primitive_eval(double cs, double cp, const double* T, int64_t n, double* PT,
+                                double* PN) {
+  if (!(cs > 0) || !(cp > cs) || n < 0 || (n > 0 && !T))
+    return fail_global(SBIEM_EINVAL, "kernel_primitive_eval: need 0 < cs < cp and T");
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(T[i] >= 0) || !std::isfinite(T[i]))
+      return fail_global(SBIEM_EINVAL, "kernel_primitive_eval: T must be finite and >= 0");
+    long double a, b;
+    kernel_primitives(T[i], cs, cp, &a, &b);
+    if (PT) PT[i] = (double)a;
+    if (PN) PN[i] = (double)b;
+  }
+  return SBIEM_OK;
 }
 
 int sbiem_set_newton_limit(sbiem_plan* p, int max_iterations) {
@@ -862,6 +1033,7 @@ int sbiem_set_state(sbiem_plan* p, const double* slip, const double* V, const do
   if (!e) e = hipStreamSynchronize(s);
   if (e) return hip_fail(p, e, "set_state");
   p->t0 = t;
+  p->t_var = t;
   p->state_set = true;
   p->last_fail_count = 0;
   p->last_fail_index = -1;
@@ -885,7 +1057,7 @@ int sbiem_get_state(sbiem_plan* p, double* slip, double* V, double* theta, doubl
   for (int k = 0; k < 5 && !e; ++k)
     if (dst[k]) e = download_elems(p, src[k], dst[k]);
   if (e) return hip_fail(p, e, "get_state");
-  if (t) *t = p->t0 + (double)step * (p->dtd ? p->dtd->dt : 0.0);
+  if (t) *t = (p->dtd && p->dtd->var) ? p->t_var : p->t0 + (double)step * (p->dtd ? p->dtd->dt : 0.0);
   return SBIEM_OK;
 }
 
@@ -899,7 +1071,7 @@ int sbiem_get_curvature(const sbiem_plan* p, double* kappa) {
 int sbiem_window_lengths(const sbiem_plan* p, double dt, int64_t* M) {
   if (!p) return fail_global(SBIEM_EINVAL, "NULL plan");
   if (!(dt > 0) || !M) return fail(const_cast<sbiem_plan*>(p), SBIEM_EINVAL, "window_lengths: need dt > 0");
-  std::vector<int> m = window_steps(p->N, p->L, p->cs, dt);
+  std::vector<int> m = window_steps(p->N, p->L, p->cs, dt, std::max(p->kcL[0], p->kcL[1]));
   for (int64_t n = 1; n <= p->N / 2; ++n) M[n - 1] = m[n];
   return SBIEM_OK;
 }
@@ -935,6 +1107,9 @@ int sbiem_set_closure(sbiem_plan* p, const float* params_shear, const float* par
   if (on && p->precision != SBIEM_FP32CONV)
     return fail(p, SBIEM_EINVAL, "set_closure: the closure runs with SBIEM_FP32CONV");
   if (on && !(cut > 0.0 && cut < 1.0)) return fail(p, SBIEM_EINVAL, "set_closure: need 0 < cut < 1");
+  if (on && (p->adaptive || p->rule != SBIEM_RULE_MIDPOINT || p->kcL[0] != p->kcL[1]))
+    return fail(p, SBIEM_EINVAL,
+                "set_closure: needs fixed steps, the midpoint rule and equal cut-offs");
   if (p->batch_refs > 0) return fail(p, SBIEM_EINVAL, "set_closure: plan is used by a batch");
   if (on) {
     for (int k = 0; k < 2; ++k) {

@@ -82,3 +82,16 @@ def test_extended_precision_kernels_match_golden_table():
     ct, cn, _, _ = pkg.kernel_eval(p * float(z["delta"]), CS, CP)
     assert np.abs(ct - z["CT"][p]).max() < 3e-15
     assert np.abs(cn - z["CN"][p]).max() < 3e-15
+
+
+@pytest.mark.parametrize("T", [0.0, 1e-5, 0.4, 3.0, 12.5, 49.9, 50.1, 120.0, 199.9])
+def test_extended_precision_primitives_match_oracle(T):
+    """P^T, P^N of the library (host, long double) against the oracle's
+    30-digit closed form, and P(0) = 0."""
+    from oracle.kernels import primitives_mp
+    import paper_2107_03550_amd as pkg
+    pt, pn = (v[0] for v in pkg.kernel_primitive_eval([T], CS, CP))
+    with mp.workdps(30):
+        rt, rn = primitives_mp(T, CS, CP)
+    tol = 2e-15 * max(1.0, T) ** 1.5
+    assert abs(pt - float(rt)) < tol and abs(pn - float(rn)) < tol, (pt - float(rt), pn - float(rn))
