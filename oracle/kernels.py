@@ -40,8 +40,9 @@ Two evaluators:
         B ~ sum_{k>=1} (-1)^(k+1) ((2k-1)!!)^2 / x^(2k)
           = 1/x^2 - 9/x^4 + 225/x^6 - ...,
       summed while their terms decrease (error far below 1e-16 W here);
-    - in between: W(x) = W(35) + integral_x^35 J1(t)/t dt by composite
-      8-point Gauss-Legendre quadrature on panels no wider than 1/2.
+    - in between: W(x) = W(x_a) + integral_x^{x_a} J1(t)/t dt by 8-point
+      Gauss-Legendre quadrature, x_a the next of the anchors 5, 5.5, ..., 35,
+      whose values come from W(35) by the same quadrature panel by panel.
   W is then within 1e-16 absolute (2e-16 relative at large x) of the
   30-digit value, and C^T, C^N within about 1e-14 for T <= 250 (pinned in
   the tests against the 30-digit evaluator).
@@ -152,18 +153,35 @@ def _W_fp(x):
     mid = ~big & ~small
     if mid.any():
         xm = x[mid]
-        w35 = _W_asymptotic(np.array([_W_ASYM]))[0]
-        npan = np.maximum(1, np.ceil((_W_ASYM - xm) / 0.5).astype(np.int64))
-        res = np.empty_like(xm)
-        for m in np.unique(npan):
-            sel = npan == m
-            lo = xm[sel]
-            h = (_W_ASYM - lo) / m
-            left = lo[:, None] + h[:, None] * np.arange(m)[None, :]
-            t = left[:, :, None] + 0.5 * h[:, None, None] * (1.0 + _GL8_X[None, None, :])
-            res[sel] = 0.5 * h * np.einsum("ipq,q->i", _j1(t) / t, _GL8_W)
-        out[mid] = w35 + res
+        anchors = _W_anchors()
+        ia = np.minimum(np.ceil((xm - _W_SERIES) / 0.5).astype(np.int64), len(anchors) - 1)
+        xa = _W_SERIES + 0.5 * ia
+        out[mid] = anchors[ia] + _j1_over_t_integral(xm, xa)
     return out
+
+
+def _j1_over_t_integral(a, b):
+    """integral_a^b J1(t)/t dt, one 8-point Gauss-Legendre panel (b - a <= 1/2)."""
+    h = b - a
+    t = a[:, None] + 0.5 * h[:, None] * (1.0 + _GL8_X[None, :])
+    return 0.5 * h * ((_j1(t) / t) @ _GL8_W)
+
+
+_W_ANCHORS = None
+
+
+def _W_anchors():
+    """W at 5, 5.5, ..., 35: W(35) from the large-argument form, then one
+    quadrature panel at a time towards 5."""
+    global _W_ANCHORS
+    if _W_ANCHORS is None:
+        xs = _W_SERIES + 0.5 * np.arange(int(round((_W_ASYM - _W_SERIES) / 0.5)) + 1)
+        w = np.empty_like(xs)
+        w[-1] = _W_asymptotic(np.array([_W_ASYM]))[0]
+        for i in range(len(xs) - 2, -1, -1):
+            w[i] = w[i + 1] + _j1_over_t_integral(xs[i:i + 1], xs[i + 1:i + 2])[0]
+        _W_ANCHORS = w
+    return _W_ANCHORS
 
 
 def kernels_fp(T, cs, cp):
