@@ -406,6 +406,27 @@ int sbiem_closure_train(const float* X, const float* Y, int64_t n, int64_t batch
                         double lr, float* params, float* adam_m, float* adam_v, int64_t* adam_t,
                         double* losses);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training loops, harnesses that forbid hipMalloc): the same
+ * Adam updates as sbiem_closure_train, with every array in the caller's
+ * device memory and the per-block gradient rows in a fixed workspace that
+ * the library holds on each GPU it runs on (about 3.3 MB, kept until the
+ * process ends).  It calls no allocator.
+ *   X[n][33], Y[n][2]     device, the pairs (read)
+ *   params, adam_m, adam_v  device, SBIEM_CLOSURE_PARAMS floats each (updated)
+ *   adam_t                host, the update count (updated)
+ *   losses                device, [steps] doubles, or NULL
+ *   hip_stream            hipStream_t the updates are enqueued on (NULL: the
+ *                         null stream); the call returns once they are
+ *                         enqueued, the caller synchronises.
+ * 1 <= batch <= SBIEM_CLOSURE_TRAIN_MAX_BATCH, else EINVAL.  Calls that
+ * overlap on one GPU (two streams, two threads) share its workspace and race;
+ * calls in sequence on one stream do not.  Errors: EINVAL, EDEVICE. */
+#define SBIEM_CLOSURE_TRAIN_MAX_BATCH 4096
+int sbiem_closure_train_noalloc(const float* X, const float* Y, int64_t n, int64_t batch,
+                                int64_t steps, double lr, float* params, float* adam_m,
+                                float* adam_v, int64_t* adam_t, double* losses, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -92,6 +92,8 @@ _SIGS = {
     "sbiem_closure_sample": (_int, [_PLAN, _dbl, _F, _F, _D]),
     "sbiem_closure_eval": (_int, [_F, _F, _i64, _F]),
     "sbiem_closure_train": (_int, [_F, _F, _i64, _i64, _i64, _dbl, _F, _F, _F, _I64, _D]),
+    "sbiem_closure_train_noalloc": (_int, [_VP, _VP, _i64, _i64, _i64, _dbl, _VP, _VP, _VP, _I64,
+                                           _VP, _VP]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -182,6 +184,22 @@ class ClosureTrainer:
                                        _fptr(self.params), _fptr(self.m), _fptr(self.v),
                                        ctypes.byref(self.t), losses.ctypes.data_as(_D)))
         return losses
+
+
+CLOSURE_TRAIN_MAX_BATCH = 4096
+
+
+def closure_train_noalloc(X, Y, n, batch, steps, lr, params, adam_m, adam_v, adam_t, losses=None,
+                          stream=None):
+    """sbiem_closure_train_noalloc on device pointers (ints, e.g. a torch
+    tensor's data_ptr()); ``adam_t`` is a ctypes.c_int64, updated.  Returns
+    the status (0 when the updates were enqueued)."""
+    return lib.sbiem_closure_train_noalloc(
+        ctypes.c_void_p(int(X)), ctypes.c_void_p(int(Y)), int(n), int(batch), int(steps),
+        float(lr), ctypes.c_void_p(int(params)), ctypes.c_void_p(int(adam_m)),
+        ctypes.c_void_p(int(adam_v)), ctypes.byref(adam_t),
+        None if losses is None else ctypes.c_void_p(int(losses)),
+        None if stream is None else ctypes.c_void_p(int(stream)))
 
 
 _torch_alloc_refs = []

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 namespace sbiem {
@@ -495,6 +496,44 @@ int dev_err(hipError_t e, const char* what) {
   return fail_global(e == hipErrorOutOfMemory ? SBIEM_ENOMEM : SBIEM_EDEVICE,
                      std::string(what) + ": " + hipGetErrorString(e));
 }
+
+// Workspace of sbiem_closure_train_noalloc: the per-block gradient rows and
+// losses of k_train_grad for a minibatch of at most
+// SBIEM_CLOSURE_TRAIN_MAX_BATCH samples, and one double that takes the loss
+// when the caller keeps none.  A file-scope device array: each GPU the
+// library runs on holds its own copy until the process ends.  Host code
+// never uses the array's name as an address: the device address of this
+// GPU's copy comes from hipGetSymbolAddress, taken once per device with that
+// device current and kept in scratch_dev.  Every launch writes the rows it
+// reads next, so nothing needs clearing between calls.
+constexpr int kNoAllocParts = SBIEM_CLOSURE_TRAIN_MAX_BATCH / kTrainS;
+static_assert(kNoAllocParts * kTrainS == SBIEM_CLOSURE_TRAIN_MAX_BATCH, "whole blocks");
+constexpr size_t kScratchLossOff = 0;         // double
+constexpr size_t kScratchRowLossOff = 256;    // float[kNoAllocParts]
+constexpr size_t kScratchRowsOff = 256 + ((sizeof(float) * kNoAllocParts + 255) / 256) * 256;
+constexpr size_t kScratchBytes = kScratchRowsOff + sizeof(float) * (size_t)kNoAllocParts * kClosureParams;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's workspace (taken on first use).
+hipError_t scratch_address(unsigned char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e) return e;
+    scratch_dev[dev] = (unsigned char*)ptr;
+  }
+  *out = scratch_dev[dev];
+  return hipSuccess;
+}
 }  // namespace
 
 extern "C" {
@@ -632,6 +671,43 @@ int sbiem_closure_sample(sbiem_plan* p, double cut, float* X, float* Y, double* 
   if (!e) e = hipMemcpyAsync(R, dR, rows * sizeof(double), hipMemcpyDeviceToHost, s);
   if (!e) e = hipStreamSynchronize(s);
   if (e) return hip_fail(p, e, "closure_sample");
+  return SBIEM_OK;
+}
+
+int sbiem_closure_train_noalloc(const float* X, const float* Y, int64_t n, int64_t batch,
+                                int64_t steps, double lr, float* params, float* adam_m,
+                                float* adam_v, int64_t* adam_t, double* losses, void* hip_stream) {
+  if (!X || !Y || !params || !adam_m || !adam_v || !adam_t || n <= 0 || batch <= 0 ||
+      steps < 0 || !(lr > 0))
+    return fail_global(SBIEM_EINVAL, "closure_train_noalloc: bad arguments");
+  if (batch > SBIEM_CLOSURE_TRAIN_MAX_BATCH)
+    return fail_global(SBIEM_EINVAL, "closure_train_noalloc: batch " + std::to_string(batch) +
+                                         " exceeds the workspace limit of " +
+                                         std::to_string(SBIEM_CLOSURE_TRAIN_MAX_BATCH) + " samples");
+  if (steps == 0) return SBIEM_OK;
+  unsigned char* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e) return dev_err(e, "closure_train_noalloc: workspace address");
+  float* rows = (float*)(base + kScratchRowsOff);
+  float* row_loss = (float*)(base + kScratchRowLossOff);
+  double* sink = (double*)(base + kScratchLossOff);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int nparts = (int)((batch + kTrainS - 1) / kTrainS);
+  int64_t t = *adam_t;
+  for (int64_t k = 0; k < steps && !e; ++k) {
+    const long long start = (long long)((t * batch) % n);
+    hipLaunchKernelGGL(k_train_grad, dim3(nparts), dim3(256), 0, s, params, X, Y, (long long)n,
+                       start, (int)batch, rows, row_loss);
+    ++t;
+    const float bc1 = (float)(1.0 - std::pow(0.9, (double)t));
+    const float bc2 = (float)(1.0 - std::pow(0.999, (double)t));
+    hipLaunchKernelGGL(k_train_adam, dim3((kClosureParams + 255) / 256), dim3(256), 0, s, params,
+                       adam_m, adam_v, rows, row_loss, nparts, (int)batch, (float)lr, bc1, bc2,
+                       losses ? losses + k : sink);
+    e = hipGetLastError();
+  }
+  if (e) return dev_err(e, "closure_train_noalloc");
+  *adam_t = t;
   return SBIEM_OK;
 }
 
