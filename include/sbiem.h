@@ -201,10 +201,26 @@ int sbiem_step_var(sbiem_plan* p, double dt);
  * log_cap records of 4 doubles (t at the attempt's start, dt, eps or -1
  * for a failed attempt, outcome from sbiem_adapt_outcome); *log_len (may be
  * NULL) receives the number of attempts (records past log_cap are counted,
- * not written).  eps0 > 0, dt_max >= dt_min.  Errors: EINVAL, ENOTREADY, the
- * stopping step's status. */
+ * not written).  eps0 > 0, dt_max >= dt_min.  On SBIEM_FP32CONV plans the
+ * spectral slip of the static term, integrated from FP32 rate spectra, is
+ * recomputed from the FP64 slip after every 32nd accepted step (counted
+ * from sbiem_set_state), so its rounding does not accumulate over long
+ * runs.  Errors: EINVAL, ENOTREADY, the stopping step's status. */
 int sbiem_adapt(sbiem_plan* p, double eps0, double dt_max, double t_end, int64_t max_accepted,
                 double* dt_io, double* log, int64_t log_cap, int64_t* log_len);
+
+/* sbiem_adapt for event-driven runs (seismic cycles, section 6): the same
+ * controller, and the run also ends after the first accepted step whose
+ * maximum slip rate lies on the other side of v_cross [m/s] than the
+ * maximum slip rate before it (v_cross <= 0: no such stop; the first
+ * comparison is with the state the call starts from).  log records hold
+ * 5 doubles: those of sbiem_adapt, then the maximum slip rate of the
+ * attempt's two-half-step solution (-1 for a failed attempt).  *crossed
+ * (may be NULL) is 1 if the run ended at such a crossing, else 0.  Errors
+ * as sbiem_adapt; EINVAL for a non-finite v_cross. */
+int sbiem_adapt_until(sbiem_plan* p, double eps0, double dt_max, double t_end,
+                      int64_t max_accepted, double v_cross, double* dt_io, double* log,
+                      int64_t log_cap, int64_t* log_len, int* crossed);
 
 /* Rate-and-state friction and loading (section 3, eq. momentum; aging law).
  *   a, b         [N] direct and evolution effects (a > 0)
@@ -218,10 +234,22 @@ int sbiem_set_friction(sbiem_plan* p, const double* a, const double* b, double D
                        double V_ref, double f0, const double* sigma_load,
                        const double* tau_load, double tau_load_rate, double V_pl);
 
+/* Constrained elements (the fault-benchmark section holds the periodic line
+ * outside the fault at null slip rate): mask [N], nonzero = constrained.
+ * A constrained element slides at exactly V_pl (zero slip rate in the
+ * loading frame of eq. momentum): no friction solve, no failure, state and
+ * thetadot frozen (thetadot = 0), V = V_pl.  NULL or an all-zero mask frees
+ * every element.  Needs sbiem_set_friction first (ENOTREADY); a later
+ * set_friction frees every element.  Both calls clear the state when a mask
+ * was or is in force: sbiem_set_state must follow (ENOTREADY until then). */
+int sbiem_set_constrained(sbiem_plan* p, const uint8_t* mask);
+
 /* Set slip [m], slip rate [m/s] (> 0) and state [s] (> 0) at time t and
  * clear the slip-rate history (rates before t are V_pl).  thetadot is set
  * from the aging law, 1 - theta V / Dc, so set_friction must come first
- * (else ENOTREADY).  Clears a pending failure. */
+ * (else ENOTREADY).  At constrained elements the V given is replaced by V_pl
+ * (any finite value is accepted there) and thetadot is 0.  Clears a pending
+ * failure. */
 int sbiem_set_state(sbiem_plan* p, const double* slip, const double* V,
                     const double* theta, double t);
 
@@ -304,6 +332,18 @@ int sbiem_kernel_eval(double cs, double cp, const double* T, int64_t n, double* 
  * verification. */
 int sbiem_kernel_primitive_eval(double cs, double cp, const double* T, int64_t n, double* PT,
                                 double* PN);
+
+/* Slip/curvature scaling diagnostic (section 5: the scaled slip gradient
+ * (1/(f du)) d(du)/dy equals -kappa away from the fault's edges).  For a
+ * slip profile du [N] on the periodic grid x_i = i L/N (host arrays,
+ * natural order) writes ratio[i] = (du[i+1] - du[i-1]) / (2 dx f du[i]),
+ * dx = L/N, indices mod N (second-order centred difference; along-fault
+ * distance is x to first order in the slope), NaN where |du[i]| <=
+ * slip_floor.  Compare with -kappa from sbiem_get_curvature.  Host only;
+ * no plan.  Errors: EINVAL (N < 3, L <= 0, f = 0 or non-finite, NULL,
+ * slip_floor < 0). */
+int sbiem_slip_scaling(int64_t N, double L, double f, const double* slip, double slip_floor,
+                       double* ratio);
 
 /* Per-launch timing of the history-convolution kernel with HIP events on
  * the stream it runs on.  While on, sbiem_run launches one step in every 33

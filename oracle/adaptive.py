@@ -43,10 +43,10 @@ from __future__ import annotations
 
 import numpy as np
 
-from .friction import solve_newton
+from .friction import ElementFailure, predict_state, update_elements
 from .kernels import kernel_integrals_fp
 from .spectral import curvature, curvature_fft, odd_sign, transforms, wavenumbers
-from .stepper import ERR_NEWTON, ERR_OPEN, ERR_STATE, OracleStepError
+from .stepper import FAILURE_CODES, OracleStepError
 from .windows import ETA_TRUNC, KC_TIMES_L
 
 
@@ -84,15 +84,17 @@ class VariableStepFault:
         self.tau_load = np.asarray(f["tau_load"], float)
         self.tau_rate = float(f.get("tau_load_rate", 0.0))
         self.V_pl = float(f["V_pl"])
+        # constrained elements (optional "constrained" mask) slide at V_pl
+        self.free = ~np.asarray(f.get("constrained", np.zeros(N, dtype=bool)), dtype=bool)
         self.eta_rad = mu / (2.0 * cs)
         self.theta_mode = theta_mode
         self.set_state(f["slip0"], f["V0"], f["theta0"], 0.0)
 
     def set_state(self, slip, V, theta, t):
         self.slip = np.array(slip, dtype=np.float64)
-        self.V = np.array(V, dtype=np.float64)
+        self.V = np.where(self.free, np.asarray(V, dtype=np.float64), self.V_pl)
         self.theta = np.array(theta, dtype=np.float64)
-        self.thetadot = 1.0 - self.theta * self.V / self.Dc
+        self.thetadot = np.where(self.free, 1.0 - self.theta * self.V / self.Dc, 0.0)
         self.t = float(t)
         self.intervals = []          # (t_start, t_end, F[V - V_pl], F[kappa (V - V_pl)])
         self.tau_el = np.zeros(self.N)
@@ -147,11 +149,7 @@ class VariableStepFault:
     def _pass(self, dt, V_c, thd_c, ST, SN, w0):
         t_new = self.t + dt
         slip_p = self.slip + dt * V_c
-        if self.theta_mode == "exp":
-            ss = self.Dc / V_c
-            theta_p = ss + (self.theta - ss) * np.exp(-V_c * dt / self.Dc)
-        else:
-            theta_p = self.theta + dt * thd_c
+        theta_p = predict_state(self.theta, V_c, thd_c, dt, self.Dc, self.theta_mode)
         u = slip_p - self.V_pl * t_new
         v = V_c - self.V_pl
         U, G = self._fwd(u), self._fwd(self.kappa * u)
@@ -161,15 +159,12 @@ class VariableStepFault:
         tau_el, sig_el = self._inv(tau_hat), self._inv(sig_hat)
         tau = self.tau_load + self.tau_rate * t_new + tau_el
         sig = self.sigma_load + sig_el
-        if np.any(sig <= 0):
-            raise OracleStepError(ERR_OPEN, "normal traction not compressive")
-        if np.any(theta_p <= 0) or not np.all(np.isfinite(theta_p)):
-            raise OracleStepError(ERR_STATE, "state variable not positive")
-        V_p, ok = solve_newton(tau, sig, theta_p, self.a, self.b, self.f0, self.V_ref,
-                               self.Dc, self.eta_rad, V_guess=V_c)
-        if not np.all(ok) or not np.all(np.isfinite(V_p)):
-            raise OracleStepError(ERR_NEWTON, "Newton solve did not converge")
-        thd_p = 1.0 - theta_p * V_p / self.Dc
+        try:
+            theta_p, V_p, thd_p = update_elements(
+                tau, sig, self.theta, theta_p, V_c, self.a, self.b, self.f0, self.V_ref, self.Dc,
+                self.eta_rad, self.free, self.V_pl)
+        except ElementFailure as e:
+            raise OracleStepError(FAILURE_CODES[e.kind], str(e)) from None
         return slip_p, theta_p, V_p, thd_p, tau_el, sig_el, Vh, GV
 
     def step(self, dt):
@@ -193,9 +188,12 @@ class VariableStepFault:
 
 
 def error_measure(V1, theta1, V2, theta2):
-    """max over elements of |ln V1 - ln V2| and |ln theta1 - ln theta2|."""
-    return float(max(np.max(np.abs(np.log(V1) - np.log(V2))),
-                     np.max(np.abs(np.log(theta1) - np.log(theta2)))))
+    """max over elements of |ln V1 - ln V2| and |ln theta1 - ln theta2|;
+    equal values (constrained elements, where V may be 0) count 0."""
+    def logdiff(x, y):
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return np.where(x == y, 0.0, np.abs(np.log(x) - np.log(y)))
+    return float(max(np.max(logdiff(V1, V2)), np.max(logdiff(theta1, theta2))))
 
 
 class AdaptiveController:

@@ -83,3 +83,45 @@ def solve_bisection(tau, sigma, theta, a, b, f0, V_ref, Dc, eta_rad, iters=200):
         lo = np.where(g > 0, mid, lo)
         hi = np.where(g > 0, hi, mid)
     return np.exp(0.5 * (lo + hi))
+
+
+class ElementFailure(Exception):
+    """A pass's element update failed: ``kind`` is "open", "state" or
+    "newton"."""
+
+    def __init__(self, kind, message):
+        super().__init__(message)
+        self.kind = kind
+
+
+def predict_state(theta, V_c, thd_c, dt, Dc, theta_mode):
+    """State at the step's end: the paper's forward step theta + dt thetadot
+    ("paper"), or the aging law integrated exactly at constant V_c ("exp")."""
+    if theta_mode == "exp":
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ss = Dc / V_c
+            return ss + (theta - ss) * np.exp(-V_c * dt / Dc)
+    return theta + dt * thd_c
+
+
+def update_elements(tau, sig, theta, theta_p, V_c, a, b, f0, V_ref, Dc, eta_rad, free, V_pl):
+    """Momentum balance and aging law of one pass at the free elements.
+
+    Constrained elements (``free`` False; the null-slip-rate part of the
+    periodic line outside the fault) keep V = V_pl, their state frozen
+    (theta unchanged, thetadot = 0) and take no part in the failure checks.
+    Returns (theta_p, V_p, thetadot_p); raises ElementFailure."""
+    theta_p = np.where(free, theta_p, theta)
+    if np.any(sig[free] <= 0):
+        raise ElementFailure("open", "normal traction not compressive")
+    tf = theta_p[free]
+    if np.any(tf <= 0) or not np.all(np.isfinite(tf)):
+        raise ElementFailure("state", "state variable not positive")
+    V_p = np.full(tau.shape, float(V_pl))
+    Vf, ok = solve_newton(tau[free], sig[free], tf, a[free], b[free], f0, V_ref, Dc, eta_rad,
+                          V_guess=V_c[free])
+    if not np.all(ok) or not np.all(np.isfinite(Vf)):
+        raise ElementFailure("newton", "Newton solve did not converge")
+    V_p[free] = Vf
+    thd_p = np.where(free, 1.0 - theta_p * V_p / Dc, 0.0)
+    return theta_p, V_p, thd_p

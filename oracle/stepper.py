@@ -35,13 +35,14 @@ from __future__ import annotations
 
 import numpy as np
 
-from .friction import solve_newton
+from .friction import ElementFailure, predict_state, update_elements
 from .spectral import curvature, curvature_fft, odd_sign, transforms, wavenumbers
 from .windows import KC_TIMES_L, KernelTable, interval_weights, midpoint_weights
 
 ERR_NEWTON = -4
 ERR_STATE = -5
 ERR_OPEN = -6
+FAILURE_CODES = {"newton": ERR_NEWTON, "state": ERR_STATE, "open": ERR_OPEN}
 
 
 class OracleStepError(RuntimeError):
@@ -87,6 +88,8 @@ class OracleFault:
         self.tau_load = np.asarray(f["tau_load"], float)
         self.tau_rate = float(f.get("tau_load_rate", 0.0))
         self.V_pl = float(f["V_pl"])
+        # constrained elements (optional "constrained" mask) slide at V_pl
+        self.free = ~np.asarray(f.get("constrained", np.zeros(N, dtype=bool)), dtype=bool)
         self.eta_rad = mu / (2.0 * cs)
         self.theta_mode = theta_mode
         # history of lags j = 1..M_n-1 (M'_n - 1 with the closure), newest
@@ -120,9 +123,9 @@ class OracleFault:
     # ------------------------------------------------------------------
     def set_state(self, slip, V, theta, t):
         self.slip = np.array(slip, dtype=np.float64)
-        self.V = np.array(V, dtype=np.float64)
+        self.V = np.where(self.free, np.asarray(V, dtype=np.float64), self.V_pl)
         self.theta = np.array(theta, dtype=np.float64)
-        self.thetadot = 1.0 - self.theta * self.V / self.Dc
+        self.thetadot = np.where(self.free, 1.0 - self.theta * self.V / self.Dc, 0.0)
         self.t = float(t)
         self.HT[:] = 0
         self.HN[:] = 0
@@ -236,23 +239,16 @@ class OracleFault:
         dt = self.dt
         t_new = self.t + dt
         slip_p = self.slip + dt * V_c
-        if self.theta_mode == "exp":
-            ss = self.Dc / V_c
-            theta_p = ss + (self.theta - ss) * np.exp(-V_c * dt / self.Dc)
-        else:
-            theta_p = self.theta + dt * thd_c
+        theta_p = predict_state(self.theta, V_c, thd_c, dt, self.Dc, self.theta_mode)
         tau_el, sig_el, Vh, GV = self.tractions(slip_p, V_c, t_new, ST, SN)
         tau = self.tau_load + self.tau_rate * t_new + tau_el
         sig = self.sigma_load + sig_el
-        if np.any(sig <= 0):
-            raise OracleStepError(ERR_OPEN, "normal traction not compressive")
-        if np.any(theta_p <= 0) or not np.all(np.isfinite(theta_p)):
-            raise OracleStepError(ERR_STATE, "state variable not positive")
-        V_p, ok = solve_newton(tau, sig, theta_p, self.a, self.b, self.f0, self.V_ref,
-                               self.Dc, self.eta_rad, V_guess=V_c)
-        if not np.all(ok) or not np.all(np.isfinite(V_p)):
-            raise OracleStepError(ERR_NEWTON, "Newton solve did not converge")
-        thd_p = 1.0 - theta_p * V_p / self.Dc
+        try:
+            theta_p, V_p, thd_p = update_elements(
+                tau, sig, self.theta, theta_p, V_c, self.a, self.b, self.f0, self.V_ref, self.Dc,
+                self.eta_rad, self.free, self.V_pl)
+        except ElementFailure as e:
+            raise OracleStepError(FAILURE_CODES[e.kind], str(e)) from None
         return slip_p, theta_p, V_p, thd_p, tau_el, sig_el, Vh, GV
 
     def step(self):

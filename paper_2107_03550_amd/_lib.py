@@ -64,6 +64,10 @@ _SIGS = {
     "sbiem_set_adaptive": (_int, [_PLAN, _int]),
     "sbiem_step_var": (_int, [_PLAN, _dbl]),
     "sbiem_adapt": (_int, [_PLAN, _dbl, _dbl, _dbl, _i64, _D, _D, _i64, _I64]),
+    "sbiem_adapt_until": (_int, [_PLAN, _dbl, _dbl, _dbl, _i64, _dbl, _D, _D, _i64, _I64,
+                                 ctypes.POINTER(ctypes.c_int)]),
+    "sbiem_set_constrained": (_int, [_PLAN, ctypes.POINTER(ctypes.c_uint8)]),
+    "sbiem_slip_scaling": (_int, [_i64, _dbl, _dbl, _D, _dbl, _D]),
     "sbiem_kernel_primitive_eval": (_int, [_dbl, _dbl, _D, _i64, _D, _D]),
     "sbiem_set_friction": (_int, [_PLAN, _D, _D, _dbl, _dbl, _dbl, _D, _D, _dbl, _dbl]),
     "sbiem_set_state": (_int, [_PLAN, _D, _D, _D, _dbl]),
@@ -145,6 +149,15 @@ def kernel_primitive_eval(T, cs, cp):
     outs = [np.empty(T.size) for _ in range(2)]
     _check(lib.sbiem_kernel_primitive_eval(cs, cp, _ptr(T), T.size, *[_ptr(o) for o in outs]))
     return tuple(outs)
+
+
+def slip_scaling(slip, L, f, slip_floor=0.0):
+    """sbiem_slip_scaling: (1/(f du)) d(du)/dx per element (NaN below the floor)."""
+    u = _arr(slip)
+    out = np.empty(u.size)
+    _check(lib.sbiem_slip_scaling(u.size, float(L), float(f), _ptr(u), float(slip_floor),
+                                  _ptr(out)))
+    return out
 
 
 def _f32(x, n=None, name="array"):
@@ -286,6 +299,33 @@ class Plan:
         if st not in (0, -4, -5, -6):
             _check(st, self.handle)
         return st, d.value, log[:min(n.value, int(log_cap))]
+
+    def adapt_until(self, eps0, dt_max, dt, max_accepted, v_cross, t_end=float("inf"),
+                    log_cap=None):
+        """sbiem_adapt_until: (status, next dt, log [attempts x 5], crossed)."""
+        if log_cap is None:
+            log_cap = 64 * int(max_accepted) + 64
+        d = ctypes.c_double(float(dt))
+        log = np.zeros((int(log_cap), 5))
+        n = ctypes.c_int64()
+        crossed = ctypes.c_int()
+        st = lib.sbiem_adapt_until(self.handle, float(eps0), float(dt_max), float(t_end),
+                                   int(max_accepted), float(v_cross), ctypes.byref(d), _ptr(log),
+                                   int(log_cap), ctypes.byref(n), ctypes.byref(crossed))
+        if st not in (0, -4, -5, -6):
+            _check(st, self.handle)
+        return st, d.value, log[:min(n.value, int(log_cap))], bool(crossed.value)
+
+    def set_constrained(self, mask):
+        """Elements held at V_pl (None frees all); set_state must follow."""
+        if mask is None:
+            self._c(lib.sbiem_set_constrained(self.handle, None))
+            return
+        m = np.ascontiguousarray(np.asarray(mask).astype(np.uint8).reshape(-1))
+        if m.size != self.N:
+            raise ValueError(f"mask: expected {self.N} values, got {m.size}")
+        self._c(lib.sbiem_set_constrained(self.handle,
+                                          m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
 
     def set_friction(self, a, b, Dc, V_ref, f0, sigma_load, tau_load, tau_load_rate=0.0, V_pl=0.0):
         n = self.N

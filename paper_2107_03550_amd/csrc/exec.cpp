@@ -397,7 +397,7 @@ int snap_alloc(sbiem_plan* p) {
   ok = ok && (v->step = (long long*)v->mem.get(sizeof(long long)));
   ok = ok && (v->Vf = (double*)v->mem.get(N * sizeof(double)));
   ok = ok && (v->thf = (double*)v->mem.get(N * sizeof(double)));
-  ok = ok && (v->eps = (unsigned long long*)v->mem.get(sizeof(unsigned long long)));
+  ok = ok && (v->eps = (unsigned long long*)v->mem.get(2 * sizeof(unsigned long long)));
   if (!ok) {
     delete v;
     return fail(p, SBIEM_ENOMEM, "adaptive stepping: snapshot allocation failed");
@@ -695,8 +695,16 @@ int sbiem_step_var(sbiem_plan* p, double dt) {
   return sbiem_run(p, dt, 1);
 }
 
-int sbiem_adapt(sbiem_plan* p, double eps0, double dt_max, double t_end, int64_t max_accepted,
-                double* dt_io, double* log, int64_t log_cap, int64_t* log_len) {
+namespace {
+
+constexpr int64_t kResync = 32;  // FP32 plans: accepted steps between spectral-slip refreshes
+
+// The controller behind sbiem_adapt and sbiem_adapt_until: log records of
+// `stride` doubles (4, or 5 with the maximum slip rate after the attempt);
+// v_cross > 0 also ends the run after the first accepted step across it.
+int adapt_impl(sbiem_plan* p, double eps0, double dt_max, double t_end, int64_t max_accepted,
+               double v_cross, double* dt_io, double* log, int64_t log_cap, int stride,
+               int64_t* log_len, int* crossed) {
   if (!p) return fail_global(SBIEM_EINVAL, "NULL plan");
   if (!p->adaptive || !p->dtd)
     return fail(p, SBIEM_EINVAL, "adapt: needs sbiem_set_adaptive(1) and sbiem_set_dt(dt_min)");
@@ -720,16 +728,35 @@ int sbiem_adapt(sbiem_plan* p, double eps0, double dt_max, double t_end, int64_t
   if (!e) e = hipMemcpy(&s0, d->step, sizeof(s0), hipMemcpyDeviceToHost);
   if (e) return hip_fail(p, e, "adapt");
   int64_t nlog = 0;
-  auto record = [&](double t, double dt, double eps, int outcome) {
+  auto record = [&](double t, double dt, double eps, int outcome, double vmax) {
     if (nlog < log_cap) {
-      double* r = log + 4 * nlog;
+      double* r = log + stride * nlog;
       r[0] = t;
       r[1] = dt;
       r[2] = eps;
       r[3] = (double)outcome;
+      if (stride > 4) r[4] = vmax;
     }
     ++nlog;
   };
+  auto read_norms = [&](double* eps, double* vmax) {
+    unsigned long long bits[2] = {0, 0};
+    hipError_t err = hipMemcpyAsync(bits, v->eps, sizeof(bits), hipMemcpyDeviceToHost, s);
+    if (!err) err = hipStreamSynchronize(s);
+    std::memcpy(eps, &bits[0], sizeof(double));
+    std::memcpy(vmax, &bits[1], sizeof(double));
+    return err;
+  };
+  if (crossed) *crossed = 0;
+  // maximum slip rate of the state the run starts from
+  double v_prev = 0.0;
+  if (v_cross > 0) {
+    const int c = (int)(s0 & 1);
+    double unused;
+    e = launch_err_norm(d->V[c], d->theta[c], d->V[c], d->theta[c], (int)p->N, v->eps, s);
+    if (!e) e = read_norms(&unused, &v_prev);
+    if (e) return hip_fail(p, e, "adapt: maximum slip rate");
+  }
   const double growth = 5.0, safety = 0.9;
   auto next_dt = [&](double dt, double eps) {
     const double g = eps > 0 ? safety * std::pow(eps0 / eps, 1.0 / 3.0) * dt : growth * dt;
@@ -741,7 +768,8 @@ int sbiem_adapt(sbiem_plan* p, double eps0, double dt_max, double t_end, int64_t
   double dt = std::min(std::max(*dt_io, dt_min), dt_max);
   int64_t accepted = 0;
   int status = SBIEM_OK;
-  while (accepted < max_accepted && p->t_var < t_end && status == SBIEM_OK) {
+  bool crossing = false;
+  while (accepted < max_accepted && p->t_var < t_end && status == SBIEM_OK && !crossing) {
     for (;;) {
       const double t_start = p->t_var;
       e = snap_copy(p, true);
@@ -768,30 +796,38 @@ int sbiem_adapt(sbiem_plan* p, double eps0, double dt_max, double t_end, int64_t
         p->t_var = t_start;
         d->primed = false;
         if (dt <= dt_min) {
-          record(t_start, dt, -1.0, SBIEM_ADAPT_STOP);
+          record(t_start, dt, -1.0, SBIEM_ADAPT_STOP, -1.0);
           status = st;
           break;
         }
-        record(t_start, dt, -1.0, SBIEM_ADAPT_FAIL);
+        record(t_start, dt, -1.0, SBIEM_ADAPT_FAIL, -1.0);
         dt = std::max(0.5 * dt, dt_min);
         continue;
       }
       const int c = (int)(s0 & 1);  // two steps after s0
-      unsigned long long bits = 0;
+      double eps, vmax;
       e = launch_err_norm(v->Vf, v->thf, d->V[c], d->theta[c], (int)p->N, v->eps, s);
-      if (!e) e = hipMemcpyAsync(&bits, v->eps, sizeof(bits), hipMemcpyDeviceToHost, s);
-      if (!e) e = hipStreamSynchronize(s);
+      if (!e) e = read_norms(&eps, &vmax);
       if (e) return hip_fail(p, e, "adapt: error measure");
-      double eps;
-      std::memcpy(&eps, &bits, sizeof(eps));
       if (eps <= eps0 || dt <= dt_min) {
-        record(t_start, dt, eps, eps <= eps0 ? SBIEM_ADAPT_ACCEPT : SBIEM_ADAPT_FLOOR);
+        record(t_start, dt, eps, eps <= eps0 ? SBIEM_ADAPT_ACCEPT : SBIEM_ADAPT_FLOOR, vmax);
         s0 += 2;
         ++accepted;
         dt = next_dt(dt, eps);
+        if (v_cross > 0 && (v_prev < v_cross) != (vmax < v_cross)) {
+          if (crossed) *crossed = 1;
+          crossing = true;
+        }
+        v_prev = vmax;
+        // FP32 rate spectra feed the FP64 spectral slip through the commit's
+        // integration; recompute it from the FP64 slip every kResync
+        // accepted steps so that its rounding does not accumulate over a run
+        if (p->precision == SBIEM_FP32CONV && ++p->var_accepted % kResync == 0) {
+          if (int rs = spectral_state_from_device(p)) return rs;
+        }
         break;
       }
-      record(t_start, dt, eps, SBIEM_ADAPT_REJECT);
+      record(t_start, dt, eps, SBIEM_ADAPT_REJECT, vmax);
       e = snap_copy(p, false);
       if (!e) e = hipStreamSynchronize(s);
       if (e) return hip_fail(p, e, "adapt: snapshot");
@@ -805,6 +841,25 @@ int sbiem_adapt(sbiem_plan* p, double eps0, double dt_max, double t_end, int64_t
   if (status != SBIEM_OK)
     return fail(p, status, "adapt: a step failed with dt at its minimum: " + p->last_error);
   return SBIEM_OK;
+}
+
+}  // namespace
+
+int sbiem_adapt(sbiem_plan* p, double eps0, double dt_max, double t_end, int64_t max_accepted,
+                double* dt_io, double* log, int64_t log_cap, int64_t* log_len) {
+  return adapt_impl(p, eps0, dt_max, t_end, max_accepted, 0.0, dt_io, log, log_cap, 4, log_len,
+                    nullptr);
+}
+
+int sbiem_adapt_until(sbiem_plan* p, double eps0, double dt_max, double t_end,
+                      int64_t max_accepted, double v_cross, double* dt_io, double* log,
+                      int64_t log_cap, int64_t* log_len, int* crossed) {
+  if (!std::isfinite(v_cross)) {
+    if (!p) return fail_global(SBIEM_EINVAL, "NULL plan");
+    return fail(p, SBIEM_EINVAL, "adapt_until: v_cross must be finite");
+  }
+  return adapt_impl(p, eps0, dt_max, t_end, max_accepted, v_cross, dt_io, log, log_cap, 5,
+                    log_len, crossed);
 }
 
 int sbiem_steps_done(const sbiem_plan* p, int64_t* nsteps) {

@@ -341,10 +341,13 @@ struct sbiem_plan {
   double kcL[2] = {200.0, 200.0};      // k_c L of the shear and normal windows
   bool adaptive = false;               // variable steps (dt of set_dt = dt_min)
   double t_var = 0.0;                  // committed time on the variable-step engine
+  int64_t var_accepted = 0;            // steps accepted by sbiem_adapt since set_state
   sbiem::VarSnap* snap = nullptr;      // step-doubling snapshot buffers
 
   bool friction_set = false, state_set = false;
   double Dc = 0, V_ref = 0, f0 = 0, tau_rate = 0, V_pl = 0, t0 = 0;
+  std::vector<double> a_host;          // direct effect a as set (natural order)
+  std::vector<uint8_t> constrained;    // elements held at V_pl (empty: none)
 
   sbiem::DevArena mem;                 // per-element constants, twiddles
   double *a = nullptr, *b = nullptr, *sigma_load = nullptr, *tau_load = nullptr,
@@ -428,7 +431,8 @@ hipError_t launch_elems(const Exec& ex, int kind, hipStream_t s,
 hipError_t launch_conv_var(const Exec& ex, const VarArgs& va, hipStream_t s);
 // balance cells of every fault to "no maximum yet"
 hipError_t launch_reset_cells(const Exec& ex, hipStream_t s);
-// *out = bits of max_i max(|ln Va - ln Vb|, |ln tha - ln thb|) (zeroed first)
+// out[0] = bits of max_i max(|ln Va - ln Vb|, |ln tha - ln thb|) (equal
+// values count 0), out[1] = bits of max_i Vb (both zeroed first)
 hipError_t launch_err_norm(const double* Va, const double* tha, const double* Vb,
                            const double* thb, int n, unsigned long long* out, hipStream_t s);
 // one fault: spectra A (of a) and B (of kappa a) at mode_pos for count real

@@ -24,6 +24,7 @@
 #include "internal.h"
 
 #include <cmath>
+#include <limits>
 
 namespace sbiem {
 
@@ -195,3 +196,23 @@ void kernel_primitives(long double T, long double cs, long double cp, long doubl
 }
 
 }  // namespace sbiem
+
+// Slip/curvature scaling diagnostic of section 5: the scaled slip gradient
+// (1/(f du)) d(du)/dx by second-order centred differences on the periodic
+// element grid (x_i = i L/N; along-fault distance equals x to first order in
+// the slope).  Elements with |du| <= slip_floor give NaN.
+int sbiem_slip_scaling(int64_t N, double L, double f, const double* slip, double slip_floor,
+                       double* ratio) {
+  if (N < 3 || !(L > 0) || !std::isfinite(L) || !(f != 0) || !std::isfinite(f) || !slip ||
+      !ratio || !(slip_floor >= 0))
+    return sbiem::fail_global(SBIEM_EINVAL,
+                              "slip_scaling: need N >= 3, L > 0, finite f != 0, slip_floor >= 0");
+  const double inv2dx = (double)N / (2.0 * L);
+  for (int64_t i = 0; i < N; ++i) {
+    const double u = slip[i];
+    const double up = slip[i + 1 < N ? i + 1 : 0], um = slip[i > 0 ? i - 1 : N - 1];
+    ratio[i] = std::fabs(u) > slip_floor ? (up - um) * inv2dx / (f * u)
+                                         : std::numeric_limits<double>::quiet_NaN();
+  }
+  return SBIEM_OK;
+}

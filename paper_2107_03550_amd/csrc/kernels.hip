@@ -1143,6 +1143,20 @@ __device__ __forceinline__ double friction_element(const FaultDev& fd, const Fri
   const double V0 = cur ? in.V[1] : in.V[0], Vb = cur ? in.V[0] : in.V[1];
   const double thd0 = cur ? in.thd[1] : in.thd[0], th0 = cur ? in.th[1] : in.th[0];
   const double dt = k.dt;
+  if (in.a < 0.0) {
+    // constrained element (stored with a negated): slides at exactly V_pl,
+    // state frozen, no friction solve and no failure
+    if (PASS == 1) {
+      o.V1[pe] = k.V_pl;
+      o.thd1[pe] = 0.0;
+    } else {
+      o.slip[pe] = (cur ? in.slip[1] : in.slip[0]) + dt * k.V_pl;
+      o.V[pe] = k.V_pl;
+      o.theta[pe] = th0;
+      o.thd[pe] = 0.0;
+    }
+    return 0.0;
+  }
   double Vc, thdc, guess;
   if (PASS == 1) {
     Vc = V0;
@@ -1376,6 +1390,7 @@ k_conv_var(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
           if (I < 0) continue;
           const double2 iv = fd.tlog[I % fd.tlog_cap];
           const double Ta = csk * (va.t_new - iv.y), Tb = csk * (va.t_new - iv.x);
+          if (Ta >= cutT && Ta >= cutN) continue;   // past both windows: weight 0
           double pTa, pNa, pTb, pNb;
           ptab_eval(fd.ptab, fd.ptab_len, fd.ptab_h, fmin(Ta, cutT), &pTa, &pNa);
           ptab_eval(fd.ptab, fd.ptab_len, fd.ptab_h, fmin(Tb, cutT), &pTb, &pNb);
@@ -1425,20 +1440,29 @@ __global__ void k_reset_cells(const FaultDev* __restrict__ faults, int nfaults) 
   c[3] = kNoExp;
 }
 
-// max_i max(|ln Va_i - ln Vb_i|, |ln tha_i - ln thb_i|), folded into *out as
-// the bit pattern of a non-negative double (which orders like its bits).
+// out[0] = max_i max(|ln Va_i - ln Vb_i|, |ln tha_i - ln thb_i|) and
+// out[1] = max_i Vb_i, each folded in as the bit pattern of a non-negative
+// double (which orders like its bits).
 __global__ void k_err_norm(const double* __restrict__ Va, const double* __restrict__ tha,
                            const double* __restrict__ Vb, const double* __restrict__ thb, int n,
                            unsigned long long* __restrict__ out) {
-  double m = 0.0;
+  double m = 0.0, vm = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const double e1 = fabs(log(Va[i]) - log(Vb[i]));
-    const double e2 = fabs(log(tha[i]) - log(thb[i]));
+    vm = fmax(vm, Vb[i]);
+    // equal values (constrained elements, where V may be 0) contribute 0
+    const double e1 = Va[i] == Vb[i] ? 0.0 : fabs(log(Va[i]) - log(Vb[i]));
+    const double e2 = tha[i] == thb[i] ? 0.0 : fabs(log(tha[i]) - log(thb[i]));
     m = fmax(m, fmax(e1, e2));
   }
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+  for (int off = 32; off >= 1; off >>= 1) {
+    m = fmax(m, __shfl_xor(m, off));
+    vm = fmax(vm, __shfl_xor(vm, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(out, (unsigned long long)__double_as_longlong(m));
+    atomicMax(out + 1, (unsigned long long)__double_as_longlong(vm));
+  }
 }
 
 hipError_t launch_conv_var(const Exec& ex, const VarArgs& va, hipStream_t s) {
@@ -1461,7 +1485,7 @@ hipError_t launch_reset_cells(const Exec& ex, hipStream_t s) {
 
 hipError_t launch_err_norm(const double* Va, const double* tha, const double* Vb,
                            const double* thb, int n, unsigned long long* out, hipStream_t s) {
-  hipError_t e = hipMemsetAsync(out, 0, sizeof(unsigned long long), s);
+  hipError_t e = hipMemsetAsync(out, 0, 2 * sizeof(unsigned long long), s);
   if (e) return e;
   const int blocks = std::max(1, std::min((n + 255) / 256, 1024));
   hipLaunchKernelGGL(k_err_norm, dim3(blocks), dim3(256), 0, s, Va, tha, Vb, thb, n, out);

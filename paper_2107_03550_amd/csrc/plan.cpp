@@ -986,6 +986,9 @@ int sbiem_set_friction(sbiem_plan* p, const double* a, const double* b, double D
     if (!e) e = hipMemcpy(p->tau_load, x.data(), bytes, hipMemcpyHostToDevice);
   }
   if (e) return hip_fail(p, e, "set_friction");
+  p->a_host.assign(a, a + N);
+  if (!p->constrained.empty()) p->state_set = false;  // its V_pl elements become free
+  p->constrained.clear();
   p->Dc = Dc;
   p->V_ref = V_ref;
   p->f0 = f0;
@@ -999,18 +1002,52 @@ int sbiem_set_friction(sbiem_plan* p, const double* a, const double* b, double D
   return SBIEM_OK;
 }
 
-int sbiem_set_state(sbiem_plan* p, const double* slip, const double* V, const double* theta, double t) {
+int sbiem_set_constrained(sbiem_plan* p, const uint8_t* mask) {
+  if (int s = check_plan(p)) return s;
+  if (!p->friction_set) return fail(p, SBIEM_ENOTREADY, "set_constrained: set_friction first");
+  const int64_t N = p->N;
+  std::vector<uint8_t> m;
+  if (mask) {
+    m.assign(mask, mask + N);
+    bool any = false;
+    for (uint8_t& x : m) any = any || (x = x != 0);
+    if (!any) m.clear();
+  }
+  if (int s = ensure_device(p)) return s;
+  // the device copy of a carries the mask as its sign
+  std::vector<double> a = p->a_host;
+  for (size_t i = 0; i < m.size(); ++i)
+    if (m[i]) a[i] = -a[i];
+  std::vector<double> x = to_elem_order(p, a.data());
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (!e) e = hipMemcpy(p->a, x.data(), (size_t)N * sizeof(double), hipMemcpyHostToDevice);
+  if (e) return hip_fail(p, e, "set_constrained");
+  p->constrained = std::move(m);
+  p->state_set = false;
+  return SBIEM_OK;
+}
+
+int sbiem_set_state(sbiem_plan* p, const double* slip, const double* V_in, const double* theta,
+                    double t) {
   if (int s = check_plan(p)) return s;
   if (!p->friction_set) return fail(p, SBIEM_ENOTREADY, "set_state: set_friction first");
   const int64_t N = p->N;
-  if (!slip || !V || !theta) return fail(p, SBIEM_EINVAL, "set_state: NULL array");
-  if (!all_finite(slip, N) || !all_finite(V, N) || !all_finite(theta, N) || !std::isfinite(t))
+  if (!slip || !V_in || !theta) return fail(p, SBIEM_EINVAL, "set_state: NULL array");
+  if (!all_finite(slip, N) || !all_finite(V_in, N) || !all_finite(theta, N) || !std::isfinite(t))
     return fail(p, SBIEM_EINVAL, "set_state: values must be finite");
+  const bool held = !p->constrained.empty();
   for (int64_t i = 0; i < N; ++i)
-    if (!(V[i] > 0) || !(theta[i] > 0)) return fail(p, SBIEM_EINVAL, "set_state: V and theta must be > 0");
+    if ((!(V_in[i] > 0) && !(held && p->constrained[i])) || !(theta[i] > 0))
+      return fail(p, SBIEM_EINVAL, "set_state: V and theta must be > 0");
   if (int s = ensure_device(p)) return s;
+  // constrained elements slide at V_pl with a frozen state
+  std::vector<double> Vh(V_in, V_in + N);
   std::vector<double> thd(N);
-  for (int64_t i = 0; i < N; ++i) thd[i] = 1.0 - theta[i] * V[i] / p->Dc;
+  for (int64_t i = 0; i < N; ++i) {
+    if (held && p->constrained[i]) Vh[i] = p->V_pl;
+    thd[i] = (held && p->constrained[i]) ? 0.0 : 1.0 - theta[i] * Vh[i] / p->Dc;
+  }
+  const double* V = Vh.data();
   DynData* d = p->dyn;
   const size_t bytes = (size_t)N * sizeof(double);
   hipStream_t s = p->stream;
@@ -1034,6 +1071,7 @@ int sbiem_set_state(sbiem_plan* p, const double* slip, const double* V, const do
   if (e) return hip_fail(p, e, "set_state");
   p->t0 = t;
   p->t_var = t;
+  p->var_accepted = 0;
   p->state_set = true;
   p->last_fail_count = 0;
   p->last_fail_index = -1;

@@ -18,7 +18,17 @@ rough-N65536           one rough fault, N = 65536, L = 600 km, alpha = 5e-3,
                        seed 3000 (plain and learned-closure forms)
 ensemble16-N262144     16 rough faults, N = 262144, L = 2400 km,
                        alpha ~ U[1e-3, 1e-2] (seed 4999), seeds 4000 + i
+sine-cycle-N4096       seismic cycle on a sinusoidal fault: N = 4096,
+                       L = 40.96 km (dx = 10 m), the central 10.24 km free,
+                       h = 80 sin(2 pi (x - L/2) / 5.12 km) m, Table 1
+                       parameters (mu = 40 GPa), 0.01 Pa/s shear loading;
+                       adaptive steps, dt_min = 0.25 dx / c_s; FP64
 =====================  =========================================================
+
+The seismic-cycle workload gives the elastic medium of Table 1 (mu = 40 GPa)
+and a ``cycle`` dict: eps0 (error target of the step-size control on ln V
+and ln theta), dt_max, v_event (a seismic event is a time span with maximum
+slip rate above it), t_end.
 """
 
 from __future__ import annotations
@@ -27,8 +37,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .friction import FrictionSpec
-from .geometry import rough_fault, seamount
+from .friction import TABLE1_CYCLE, FrictionSpec
+from .geometry import rough_fault, seamount, sinusoid
 
 MU = 30e9
 NU = 0.25
@@ -51,6 +61,7 @@ class Workload:
     cs: float = CS
     cp: float = CP
     friction: FrictionSpec = field(default_factory=FrictionSpec)
+    cycle: dict | None = None
 
     @property
     def dx(self) -> float:
@@ -62,7 +73,9 @@ class Workload:
 
 
 WORKLOAD_NAMES = ("rough-N256-fp64", "seamount-N8192", "ensemble64",
-                  "rough-N65536", "ensemble16-N262144")
+                  "rough-N65536", "ensemble16-N262144", "sine-cycle-N4096")
+
+YEAR = 365.25 * 86400.0
 
 
 def ensemble_members(name: str) -> list[Workload]:
@@ -99,4 +112,9 @@ def workload(name: str) -> Workload:
     if name == "rough-N65536":
         N, L = 65536, 600e3
         return Workload(name, N, L, rough_fault(N, L, 5e-3, 3000), precision="fp32conv", steps=2000)
+    if name == "sine-cycle-N4096":
+        N, L = 4096, 40960.0
+        return Workload(name, N, L, sinusoid(N, L, 80.0, 5120.0), precision="fp64", steps=0,
+                        beta=0.25, mu=40e9, friction=TABLE1_CYCLE,
+                        cycle=dict(eps0=1e-3, dt_max=1e7, v_event=1e-3, t_end=200.0 * YEAR))
     raise KeyError(name)

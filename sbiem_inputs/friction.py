@@ -14,6 +14,13 @@ The fields made here are plain inputs:
   radiation-damping term at the plate rate, so that with no overstress a fault
   sliding uniformly at V_pl is an exact steady state in the backslip frame;
 * initial slip 0, slip rate V_init, state theta = Dc / V_init (steady state).
+
+With ``constrained_outside`` the part of the periodic line outside the
+velocity-weakening zone is not velocity-strengthening but constrained (a
+"constrained" mask: those elements slide at V_pl, i.e. null slip rate when
+V_pl = 0, as the fault-benchmark section does outside its fault).  With
+V_pl = 0 (no backslip) the steady shear traction is taken at V_init:
+sigma*(f0 + (a - b) ln(V_init/V_ref)) + mu*V_init/(2 c_s).
 """
 
 from __future__ import annotations
@@ -41,6 +48,17 @@ class FrictionSpec:
     w_nuc: float = 1000.0
     x_nuc: float | None = None      # None: L/2
     tau_load_rate: float = 0.0
+    constrained_outside: bool = False
+
+
+# Table 1 with the seismic-cycle section's loading: a = 0.012, b = 0.015,
+# Dc = 1 cm, reference velocity 1e-9 m/s, f0 = 0.6, sigma = 100 MPa; a
+# constant shear-traction rate of 0.01 Pa/s, no backslip, no nucleation
+# overstress; the 10.24 km fault is the central quarter of the periodic line
+# (the sBIEM line is four times the fault length), constrained outside.
+TABLE1_CYCLE = FrictionSpec(a_vw=0.012, a_vs=0.012, vw_half_width=0.125, b=0.015, Dc=0.01,
+                            V_ref=1e-9, f0=0.6, sigma=100e6, V_pl=0.0, V_init=1e-9,
+                            overstress=0.0, tau_load_rate=0.01, constrained_outside=True)
 
 
 def friction_fields(N: int, L: float, mu: float, cs: float,
@@ -54,13 +72,19 @@ def friction_fields(N: int, L: float, mu: float, cs: float,
     sigma = np.full(N, spec.sigma)
     xn = centre if spec.x_nuc is None else spec.x_nuc
     d_n = ((x - xn + L / 2.0) % L) - L / 2.0
-    steady = sigma * (spec.f0 + (a - b) * np.log(spec.V_pl / spec.V_ref)) \
-        + mu * spec.V_pl / (2.0 * cs)
+    V_ss = spec.V_pl if spec.V_pl > 0 else spec.V_init
+    steady = sigma * (spec.f0 + (a - b) * np.log(V_ss / spec.V_ref)) \
+        + mu * V_ss / (2.0 * cs)
     tau_load = steady + spec.overstress * np.exp(-(d_n / spec.w_nuc) ** 2)
-    return dict(
+    out = dict(
         a=a, b=b, Dc=spec.Dc, V_ref=spec.V_ref, f0=spec.f0,
         sigma_load=sigma, tau_load=tau_load, tau_load_rate=spec.tau_load_rate,
         V_pl=spec.V_pl,
         slip0=np.zeros(N), V0=np.full(N, spec.V_init),
         theta0=np.full(N, spec.Dc / spec.V_init),
     )
+    if spec.constrained_outside:
+        held = d_vw >= spec.vw_half_width * L
+        out["constrained"] = held
+        out["V0"] = np.where(held, spec.V_pl, out["V0"])
+    return out

@@ -7,6 +7,8 @@
   paper prints for its alpha values (about 48*alpha at L = 10.24 km with a
   200 m minimum wavelength).
 * Seamount: a Gaussian bump A*exp(-(x - x0)^2 / w^2) ("The seamount case").
+* Sinusoid: A*sin(2 pi (x - x0) / lambda), the fault of the seismic-cycle
+  section (its amplitude and wavelength are shown only in a figure).
 
 Elements sit at x_i = i*L/N on the periodic domain [0, L).
 """
@@ -66,3 +68,16 @@ def seamount(N: int, L: float, A: float, w: float, x0: float | None = None) -> n
     c = L / 2.0 if x0 is None else float(x0)
     d = (x - c + L / 2.0) % L - L / 2.0
     return A * np.exp(-(d / w) ** 2)
+
+
+def sinusoid(N: int, L: float, A: float, wavelength: float, x0: float | None = None) -> np.ndarray:
+    """h = A sin(2 pi (x - x0) / wavelength), x0 = L/2 by default.
+
+    The wavelength must divide L (a periodic profile): the curvature then
+    vanishes at x0, where the fault is locally flat."""
+    n = L / wavelength
+    if abs(n - round(n)) > 1e-9 * max(1.0, n) or round(n) < 1:
+        raise ValueError("the wavelength must divide L")
+    x = element_positions(N, L)
+    c = L / 2.0 if x0 is None else float(x0)
+    return A * np.sin(2.0 * np.pi * (x - c) / wavelength)

@@ -95,3 +95,28 @@ def test_extended_precision_primitives_match_oracle(T):
         rt, rn = primitives_mp(T, CS, CP)
     tol = 2e-15 * max(1.0, T) ** 1.5
     assert abs(pt - float(rt)) < tol and abs(pn - float(rn)) < tol, (pt - float(rt), pn - float(rn))
+
+
+def test_slip_scaling_matches_the_oracle_diagnostic():
+    """sbiem_slip_scaling (host C++) against the oracle's element-by-element
+    centred difference on the same slip profiles, NaNs in the same places."""
+    import paper_2107_03550_amd as pkg
+    from oracle.scaling import scaled_slip_gradient
+    rng = np.random.default_rng(11)
+    for N, L, f in ((3, 30.0, 0.6), (257, 2570.0, 0.3), (4096, 40960.0, 0.6)):
+        u = np.abs(rng.standard_normal(N)) + 0.05
+        u[rng.integers(0, N, size=max(1, N // 50))] = 0.0
+        got = pkg.slip_scaling(u, L, f, slip_floor=0.01)
+        ref = scaled_slip_gradient(u, L, f, slip_floor=0.01)
+        assert np.array_equal(np.isnan(got), np.isnan(ref))
+        m = np.isfinite(ref)
+        assert np.all(np.abs(got[m] - ref[m]) <= 4e-16 * np.abs(ref[m]) + 1e-300)
+
+
+@pytest.mark.parametrize("args", [(2, 10.0, 0.6, 0.0), (8, 0.0, 0.6, 0.0), (8, 10.0, 0.0, 0.0),
+                                  (8, 10.0, float("nan"), 0.0), (8, 10.0, 0.6, -1.0)])
+def test_slip_scaling_rejects_bad_arguments(args):
+    import paper_2107_03550_amd as pkg
+    N, L, f, floor = args
+    with pytest.raises(pkg.SbiemError):
+        pkg.slip_scaling(np.ones(N), L, f, floor)

@@ -142,12 +142,12 @@ def test_variable_steps_of_constant_length_equal_the_interval_rule_stepper():
 
 
 def _prescribed_rate(monkeypatch, fault, V_of_step):
-    import oracle.adaptive as ad
+    import oracle.friction as fm
 
     def prescribed(tau, sig, theta, a, b, f0, V_ref, Dc, eta, V_guess=None):
         return V_of_step(fault.nsteps + 1), np.ones(fault.N, dtype=bool)
 
-    monkeypatch.setattr(ad, "solve_newton", prescribed)
+    monkeypatch.setattr(fm, "solve_newton", prescribed)
 
 
 def test_constant_rate_under_variable_steps_is_exact(monkeypatch):
@@ -297,7 +297,8 @@ def test_separate_cutoffs_truncate_each_kind_at_its_own_window(monkeypatch):
         s = f.nsteps + 1
         return fr["V_pl"] + (shape if s < pulse else np.zeros(N)), np.ones(N, dtype=bool)
 
-    monkeypatch.setattr(stepper, "solve_newton", prescribed)
+    import oracle.friction as fm
+    monkeypatch.setattr(fm, "solve_newton", prescribed)
     k = np.abs(wavenumbers(N, L))
 
     def gaps():

@@ -149,7 +149,8 @@ def _kinematic_fault(monkeypatch, N, L, beta, pulse_steps, amp, seed=3):
     def prescribed(tau, sig, theta, a, b, f0, V_ref, Dc, eta, V_guess=None):
         return rate_after(f.nsteps + 1), np.ones(N, dtype=bool)
 
-    monkeypatch.setattr(stepper, "solve_newton", prescribed)
+    import oracle.friction as fm
+    monkeypatch.setattr(fm, "solve_newton", prescribed)
     return f, dt
 
 
