@@ -1,4 +1,6 @@
-"""Real-space space-time evaluation of the stress functional, tiny N only.
+"""Real-space evaluation of the stress functional, tiny N only (a check of
+the FFT route and the lag bookkeeping, not of the kernels: the influence
+kernels below are built from the same spectral multipliers and weights).
 
 The spectral functional of ``oracle.stress`` is a circular convolution in
 space and a truncated convolution in time.  Here the same tractions are

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <utility>
 
 #include "internal.h"
@@ -232,6 +233,7 @@ int reset_history(sbiem_plan* p) {
   }
   if (!e) e = hipStreamSynchronize(s);
   if (e) return hip_fail(p, e, "resetting the history");
+  p->var_b = -1;
   return SBIEM_OK;
 }
 
@@ -323,26 +325,32 @@ int spectral_state_from_device(sbiem_plan* p) {
 
 namespace {
 
-int check_failure(sbiem_plan* p) {
+// Record the failure flags read back from the device (status, failing
+// elements, first failing element) and clear them there.
+int note_failure(sbiem_plan* p, int status, int count, int index) {
   DynData* d = p->dyn;
-  int h[3];
-  hipError_t e = hipMemcpy(h, d->err, sizeof(h), hipMemcpyDeviceToHost);
-  if (e) return hip_fail(p, e, "reading the failure flag");
-  if (h[0] == 0) {
+  if (status == 0) {
     p->last_fail_count = 0;
     p->last_fail_index = -1;
     return SBIEM_OK;
   }
-  p->last_fail_count = h[1];
-  p->last_fail_index = h[2];
+  p->last_fail_count = count;
+  p->last_fail_index = index;
   d->primed = false;
   const int init[3] = {0, 0, 0x7fffffff};
-  e = hipMemcpy(d->err, init, sizeof(init), hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy(d->err, init, sizeof(init), hipMemcpyHostToDevice);
   if (e) return hip_fail(p, e, "clearing the failure flag");
-  const char* what = h[0] == SBIEM_EOPEN ? "normal traction not compressive"
-                     : h[0] == SBIEM_ESTATE ? "state variable not positive"
-                                            : "momentum balance did not converge";
-  return fail(p, h[0], std::string("step failed: ") + what + " at element " + std::to_string(h[2]));
+  const char* what = status == SBIEM_EOPEN ? "normal traction not compressive"
+                     : status == SBIEM_ESTATE ? "state variable not positive"
+                                              : "momentum balance did not converge";
+  return fail(p, status, std::string("step failed: ") + what + " at element " + std::to_string(index));
+}
+
+int check_failure(sbiem_plan* p) {
+  int h[3];
+  hipError_t e = hipMemcpy(h, p->dyn->err, sizeof(h), hipMemcpyDeviceToHost);
+  if (e) return hip_fail(p, e, "reading the failure flag");
+  return note_failure(p, h[0], h[1], h[2]);
 }
 
 int ready(sbiem_plan* p, double dt) {
@@ -367,23 +375,54 @@ int ready(sbiem_plan* p, double dt) {
 // sums at the step's end time, pass-1 maxima and assembly, the two passes,
 // the commit (which logs the interval's times).
 // ---------------------------------------------------------------------------
-int var_step(sbiem_plan* p, double dt) {
+// The launches of one step from t_old to t_new (no synchronisation; after a
+// failure every later launch of the fault returns without effect until the
+// flag is cleared).
+// newest_end: end time of the newest stored interval (-inf: none).  When it
+// lies at least the longest window L/c_s before t_new (with a margin far
+// above rounding), every stored interval weighs exactly 0 for every mode:
+// the conv launch is skipped and the mode stage takes zero history sums.
+hipError_t var_launch(sbiem_plan* p, double dt, double t_old, double t_new, double newest_end) {
   Exec& ex = *p->exec;
   hipStream_t s = p->stream;
-  const VarArgs va{dt, p->t_var, p->t_var + dt, 1, 0};
+  const int nohist = (t_new - newest_end) >= (p->L / p->cs) * (1.0 + 1e-9) ? 1 : 0;
+  const VarArgs va{dt, t_old, t_new, 1, nohist};
   hipError_t e = launch_reset_cells(ex, s);
-  if (!e) e = launch_conv_var(ex, va, s);
+  if (!e && !nohist) e = launch_conv_var(ex, va, s);
   if (!e) e = launch_modes(ex, 0, 1, s, va);
   if (!e) e = launch_modes(ex, 0, 0, s, va);
   if (!e) e = launch_elems(ex, 1, s, va);
   if (!e) e = launch_modes(ex, 1, 0, s, va);
   if (!e) e = launch_elems(ex, 2, s, va);
   if (!e) e = launch_modes(ex, 2, 0, s, va);
-  if (!e) e = hipStreamSynchronize(s);
+  return e;
+}
+
+// End time of the newest committed interval (-inf: none yet).
+double var_newest_end(const sbiem_plan* p) {
+  if (p->var_b < 0 || p->var_tend.empty()) return -std::numeric_limits<double>::infinity();
+  return p->var_tend[(size_t)(p->var_b % (long long)p->var_tend.size())];
+}
+
+// Record a committed interval ending at t_end in the host copy.
+void var_commit(sbiem_plan* p, double t_end) {
+  if (p->var_tend.size() != (size_t)p->dtd->tlog_cap)
+    p->var_tend.assign((size_t)std::max(p->dtd->tlog_cap, 1), 0.0);
+  ++p->var_b;
+  p->var_tend[(size_t)(p->var_b % (long long)p->var_tend.size())] = t_end;
+}
+
+int var_step(sbiem_plan* p, double dt) {
+  const double t_new = p->t_var + dt;
+  hipError_t e = var_launch(p, dt, p->t_var, t_new, var_newest_end(p));
+  if (!e) e = hipStreamSynchronize(p->stream);
   if (e) return hip_fail(p, e, "variable step");
   p->dyn->primed = false;
   const int st = check_failure(p);
-  if (st == SBIEM_OK) p->t_var = va.t_new;
+  if (st == SBIEM_OK) {
+    p->t_var = t_new;
+    var_commit(p, t_new);
+  }
   return st;
 }
 
@@ -397,36 +436,39 @@ int snap_alloc(sbiem_plan* p) {
   ok = ok && (v->step = (long long*)v->mem.get(sizeof(long long)));
   ok = ok && (v->Vf = (double*)v->mem.get(N * sizeof(double)));
   ok = ok && (v->thf = (double*)v->mem.get(N * sizeof(double)));
-  ok = ok && (v->eps = (unsigned long long*)v->mem.get(2 * sizeof(unsigned long long)));
+  ok = ok && (v->eps = (unsigned long long*)v->mem.get(4 * sizeof(unsigned long long)));
   if (!ok) {
     delete v;
     return fail(p, SBIEM_ENOMEM, "adaptive stepping: snapshot allocation failed");
   }
-  p->snap = v;
-  return SBIEM_OK;
-}
-
-// Committed state <-> snapshot (to = 1: save).
-hipError_t snap_copy(sbiem_plan* p, bool save) {
   DynData* d = p->dyn;
-  VarSnap* v = p->snap;
-  hipStream_t s = p->stream;
-  const size_t N = (size_t)p->N, M = (size_t)(p->N / 2 + 1);
   double* el[12] = {d->slip[0], d->slip[1], d->V[0], d->V[1], d->theta[0], d->theta[1],
                     d->thd[0], d->thd[1], d->tau_el[0], d->tau_el[1], d->sigma_el[0],
                     d->sigma_el[1]};
   double2* sp[6] = {d->u_hat, d->g_hat, d->v_hat0, d->gv_hat0, d->hprev_v, d->hprev_g};
-  hipError_t e = hipSuccess;
-  for (int k = 0; k < 12 && !e; ++k)
-    e = hipMemcpyAsync(save ? v->el[k] : el[k], save ? el[k] : v->el[k], N * sizeof(double),
-                       hipMemcpyDeviceToDevice, s);
-  for (int k = 0; k < 6 && !e; ++k)
-    e = hipMemcpyAsync(save ? v->sp[k] : sp[k], save ? sp[k] : v->sp[k], M * sizeof(double2),
-                       hipMemcpyDeviceToDevice, s);
-  if (!e)
-    e = hipMemcpyAsync(save ? v->step : d->step, save ? d->step : v->step, sizeof(long long),
-                       hipMemcpyDeviceToDevice, s);
-  return e;
+  for (int k = 0; k < 12; ++k) {
+    v->save.add(el[k], v->el[k], N * sizeof(double));
+    v->restore.add(v->el[k], el[k], N * sizeof(double));
+  }
+  for (int k = 0; k < 6; ++k) {
+    v->save.add(sp[k], v->sp[k], M * sizeof(double2));
+    v->restore.add(v->sp[k], sp[k], M * sizeof(double2));
+  }
+  v->save.add(d->step, v->step, sizeof(long long));
+  v->restore.add(v->step, d->step, sizeof(long long));
+  v->restore.add(nullptr, v->eps, 2 * sizeof(unsigned long long));
+  p->snap = v;
+  return SBIEM_OK;
+}
+
+// Largest list entry in 8-byte words (the copy launch's x extent).
+int snap_words(const sbiem_plan* p) { return (int)std::max<int64_t>(p->N, 2 * (p->N / 2 + 1)); }
+
+// Committed state <-> snapshot (save = true: state -> snapshot), one launch;
+// a restore also clears the error-measure cells.
+hipError_t snap_copy(sbiem_plan* p, bool save) {
+  VarSnap* v = p->snap;
+  return launch_copy_many(save ? v->save : v->restore, snap_words(p), p->stream);
 }
 
 // One step in steady state: the next step's history sums on the second
@@ -772,29 +814,38 @@ int adapt_impl(sbiem_plan* p, double eps0, double dt_max, double t_end, int64_t 
   while (accepted < max_accepted && p->t_var < t_end && status == SBIEM_OK && !crossing) {
     for (;;) {
       const double t_start = p->t_var;
+      const double t_half = t_start + 0.5 * dt;
+      // one step of dt, then two of dt/2 from the same state, launched back
+      // to back: after a failure the remaining launches do nothing, and the
+      // flags come back with the error measure in one read
+      CopyList keep;
+      const int cf = (int)((s0 + 1) & 1);  // the full step's solution buffer
+      keep.add(d->V[cf], v->Vf, (size_t)p->N * sizeof(double));
+      keep.add(d->theta[cf], v->thf, (size_t)p->N * sizeof(double));
+      const int c = (int)(s0 & 1);         // two steps after s0
+      const double newest = var_newest_end(p);
       e = snap_copy(p, true);
-      if (e) return hip_fail(p, e, "adapt: snapshot");
-      // one step of dt, then two of dt/2 from the same state
-      int st = var_step(p, dt);
-      if (st == SBIEM_OK) {
-        const int c = (int)((s0 + 1) & 1);
-        e = hipMemcpyAsync(v->Vf, d->V[c], (size_t)p->N * sizeof(double), hipMemcpyDeviceToDevice, s);
-        if (!e)
-          e = hipMemcpyAsync(v->thf, d->theta[c], (size_t)p->N * sizeof(double),
-                             hipMemcpyDeviceToDevice, s);
-        if (!e) e = snap_copy(p, false);
-        if (e) return hip_fail(p, e, "adapt: snapshot");
-        p->t_var = t_start;
-        st = var_step(p, 0.5 * dt);
-        if (st == SBIEM_OK) st = var_step(p, 0.5 * dt);
-      }
+      if (!e) e = var_launch(p, dt, t_start, t_start + dt, newest);
+      if (!e) e = launch_copy_many(keep, (int)p->N, s);
+      if (!e) e = snap_copy(p, false);
+      if (!e) e = var_launch(p, 0.5 * dt, t_start, t_half, newest);
+      if (!e) e = var_launch(p, 0.5 * dt, t_half, t_half + 0.5 * dt, t_half);
+      if (!e)
+        e = launch_err_norm(v->Vf, v->thf, d->V[c], d->theta[c], (int)p->N, v->eps, s, d->err,
+                            true);
+      unsigned long long r[4] = {0, 0, 0, 0};
+      if (!e) e = hipMemcpyAsync(r, v->eps, sizeof(r), hipMemcpyDeviceToHost, s);
+      if (!e) e = hipStreamSynchronize(s);
+      if (e) return hip_fail(p, e, "adapt: attempt");
+      d->primed = false;
+      const int st = (int)(unsigned)r[2];
       if (st != SBIEM_OK) {
+        note_failure(p, st, (int)(r[3] >> 32), (int)(unsigned)(r[3] & 0xffffffffULL));
         if (!physics(st)) return st;
         e = snap_copy(p, false);
         if (!e) e = hipStreamSynchronize(s);
         if (e) return hip_fail(p, e, "adapt: snapshot");
         p->t_var = t_start;
-        d->primed = false;
         if (dt <= dt_min) {
           record(t_start, dt, -1.0, SBIEM_ADAPT_STOP, -1.0);
           status = st;
@@ -804,13 +855,16 @@ int adapt_impl(sbiem_plan* p, double eps0, double dt_max, double t_end, int64_t 
         dt = std::max(0.5 * dt, dt_min);
         continue;
       }
-      const int c = (int)(s0 & 1);  // two steps after s0
+      p->last_fail_count = 0;
+      p->last_fail_index = -1;
+      p->t_var = t_half + 0.5 * dt;
       double eps, vmax;
-      e = launch_err_norm(v->Vf, v->thf, d->V[c], d->theta[c], (int)p->N, v->eps, s);
-      if (!e) e = read_norms(&eps, &vmax);
-      if (e) return hip_fail(p, e, "adapt: error measure");
+      std::memcpy(&eps, &r[0], sizeof(double));
+      std::memcpy(&vmax, &r[1], sizeof(double));
       if (eps <= eps0 || dt <= dt_min) {
         record(t_start, dt, eps, eps <= eps0 ? SBIEM_ADAPT_ACCEPT : SBIEM_ADAPT_FLOOR, vmax);
+        var_commit(p, t_half);
+        var_commit(p, p->t_var);
         s0 += 2;
         ++accepted;
         dt = next_dt(dt, eps);

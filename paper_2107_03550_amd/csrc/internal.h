@@ -162,7 +162,7 @@ struct VarArgs {
   double t_old;   // committed time at the start of the step
   double t_new;   // t_old + dt
   int on;
-  int pad;
+  int nohist;     // every stored interval is past every window: history sums are 0
 };
 
 // Quintic Hermite evaluation of the primitive table at T >= 0 (clamped to
@@ -254,13 +254,33 @@ struct DtData {
 // Device snapshot of the committed state for step doubling (variable-step
 // engine): both state buffers, the spectral slip and rate accumulators and
 // the step counter; the full step's rate and state for the error measure.
+// Up to kMaxCopies device copies (or zero fills: src null) in one launch;
+// sizes in 8-byte words.
+constexpr int kMaxCopies = 24;
+struct CopyList {
+  int n = 0;
+  const void* src[kMaxCopies] = {};
+  void* dst[kMaxCopies] = {};
+  long long words[kMaxCopies] = {};
+  void add(const void* from, void* to, size_t bytes) {
+    src[n] = from;
+    dst[n] = to;
+    words[n] = (long long)(bytes / 8);
+    ++n;
+  }
+};
+
 struct VarSnap {
   DevArena mem;
   double* el[12] = {};
   double2* sp[6] = {};
   long long* step = nullptr;
   double *Vf = nullptr, *thf = nullptr;
+  // [0] error measure bits, [1] maximum slip rate bits, [2] failure status,
+  // [3] failing elements << 32 | first failing element
   unsigned long long* eps = nullptr;
+  CopyList save, restore, keep_full;  // snapshot save / restore (+ clear eps[0..1]),
+                                      // full-step solution -> Vf, thf
 };
 
 // Dynamic state of one fault.
@@ -342,6 +362,10 @@ struct sbiem_plan {
   bool adaptive = false;               // variable steps (dt of set_dt = dt_min)
   double t_var = 0.0;                  // committed time on the variable-step engine
   int64_t var_accepted = 0;            // steps accepted by sbiem_adapt since set_state
+  // host copy of the committed intervals' end times on the variable-step
+  // engine: interval l at l mod tlog_cap, the last one var_b (-1: none)
+  std::vector<double> var_tend;
+  long long var_b = -1;
   sbiem::VarSnap* snap = nullptr;      // step-doubling snapshot buffers
 
   bool friction_set = false, state_set = false;
@@ -432,9 +456,13 @@ hipError_t launch_conv_var(const Exec& ex, const VarArgs& va, hipStream_t s);
 // balance cells of every fault to "no maximum yet"
 hipError_t launch_reset_cells(const Exec& ex, hipStream_t s);
 // out[0] = bits of max_i max(|ln Va - ln Vb|, |ln tha - ln thb|) (equal
-// values count 0), out[1] = bits of max_i Vb (both zeroed first)
+// values count 0), out[1] = bits of max_i Vb (both zeroed first unless
+// zeroed = true); with err (the fault's failure flags), out[2..3] receive
+// them (status; count << 32 | index)
 hipError_t launch_err_norm(const double* Va, const double* tha, const double* Vb,
-                           const double* thb, int n, unsigned long long* out, hipStream_t s);
+                           const double* thb, int n, unsigned long long* out, hipStream_t s,
+                           const int* err = nullptr, bool zeroed = false);
+hipError_t launch_copy_many(const CopyList& c, int max_words, hipStream_t s);
 // one fault: spectra A (of a) and B (of kappa a) at mode_pos for count real
 // signals a (natural element order, stride N); gF holds count * N complex
 hipError_t launch_forward(const FaultDev* d_fault, const FaultDev& h_fault, int precision,

@@ -898,10 +898,10 @@ k_modes(const FaultDev* __restrict__ faults, const int2* __restrict__ map, int m
     if (va.on) var_lag0(fd, sl.n, dt, c1, &cf.aT, &cf.aN);
     double4 S = in.S0;
     if (KIND != 1) {
-      if (cf.nparts == 0) {  // no ring records: only a closure tail (none for such modes)
-        S = make_double4(0.0, 0.0, 0.0, 0.0);
-      }
-      for (int j = 1; j < cf.nparts; ++j) {  // further pieces of a long window
+      // no ring records (only a closure tail, none for such modes), or no
+      // stored interval inside any window (the conv launch was skipped)
+      if (cf.nparts == 0 || va.nohist) S = make_double4(0.0, 0.0, 0.0, 0.0);
+      for (int j = 1; j < cf.nparts && !va.nohist; ++j) {  // further pieces of a long window
         const double4 b = mp.parts[cf.part0 + j - 1];
         S.x += b.x;
         S.y += b.y;
@@ -1382,10 +1382,25 @@ k_conv_var(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
         const double cutT = fmin(kL, fd.kcT), cutN = fmin(kL, fd.kcN);
         const Rec* __restrict__ ring = (const Rec*)fd.ring + tl.ring_off;
         const int end = tl.p0 + tl.len;
+        // The tile's newest interval sits in its last slot, or in the slot of
+        // interval b when the tile holds it; every other slot of the tile
+        // holds an older one.  When that interval is past both windows (or
+        // none is stored yet) the whole tile weighs 0: one log read instead
+        // of one per slot.
+        const int pb = mod_pos(b, Rn);
+        const long long In = (pb >= tl.p0 && pb < end)
+                                 ? b
+                                 : b - (long long)mod_pos(b - (end - 1) + (long long)Rn * 4, Rn);
+        bool live = In >= 0;
+        if (live) {
+          const double Tn = csk * (va.t_new - fd.tlog[In % fd.tlog_cap].y);
+          live = Tn < cutT || Tn < cutN;
+        }
+        // (a dead tile still reduces and records its zero partial below)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int p = tl.p0 + lane + 64 * u;
-          if (p >= end) continue;
+          if (!live || p >= end) continue;
           const long long I = b - (long long)mod_pos(b - p + (long long)Rn * 4, Rn);
           if (I < 0) continue;
           const double2 iv = fd.tlog[I % fd.tlog_cap];
@@ -1445,7 +1460,11 @@ __global__ void k_reset_cells(const FaultDev* __restrict__ faults, int nfaults) 
 // double (which orders like its bits).
 __global__ void k_err_norm(const double* __restrict__ Va, const double* __restrict__ tha,
                            const double* __restrict__ Vb, const double* __restrict__ thb, int n,
-                           unsigned long long* __restrict__ out) {
+                           unsigned long long* __restrict__ out, const int* __restrict__ err) {
+  if (err && blockIdx.x == 0 && threadIdx.x == 0) {
+    out[2] = (unsigned long long)(unsigned)err[0];
+    out[3] = ((unsigned long long)(unsigned)err[1] << 32) | (unsigned)err[2];
+  }
   double m = 0.0, vm = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     vm = fmax(vm, Vb[i]);
@@ -1484,11 +1503,32 @@ hipError_t launch_reset_cells(const Exec& ex, hipStream_t s) {
 }
 
 hipError_t launch_err_norm(const double* Va, const double* tha, const double* Vb,
-                           const double* thb, int n, unsigned long long* out, hipStream_t s) {
-  hipError_t e = hipMemsetAsync(out, 0, 2 * sizeof(unsigned long long), s);
-  if (e) return e;
+                           const double* thb, int n, unsigned long long* out, hipStream_t s,
+                           const int* err, bool zeroed) {
+  if (!zeroed) {
+    hipError_t e = hipMemsetAsync(out, 0, 2 * sizeof(unsigned long long), s);
+    if (e) return e;
+  }
   const int blocks = std::max(1, std::min((n + 255) / 256, 1024));
-  hipLaunchKernelGGL(k_err_norm, dim3(blocks), dim3(256), 0, s, Va, tha, Vb, thb, n, out);
+  hipLaunchKernelGGL(k_err_norm, dim3(blocks), dim3(256), 0, s, Va, tha, Vb, thb, n, out, err);
+  return hipGetLastError();
+}
+
+// Entry blockIdx.y of the list: copy (or zero-fill) its words.
+__global__ void __launch_bounds__(256) k_copy_many(CopyList c) {
+  const int k = blockIdx.y;
+  if (k >= c.n) return;
+  const long long w = c.words[k];
+  unsigned long long* __restrict__ d = (unsigned long long*)c.dst[k];
+  const unsigned long long* __restrict__ sr = (const unsigned long long*)c.src[k];
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < w; i += 256LL * gridDim.x)
+    d[i] = sr ? sr[i] : 0ULL;
+}
+
+hipError_t launch_copy_many(const CopyList& c, int max_words, hipStream_t s) {
+  if (c.n == 0) return hipSuccess;
+  const int bx = std::max(1, std::min((max_words + 255) / 256, 64));
+  hipLaunchKernelGGL(k_copy_many, dim3(bx, c.n), dim3(256), 0, s, c);
   return hipGetLastError();
 }
 

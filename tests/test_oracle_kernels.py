@@ -161,3 +161,61 @@ def test_fp64_w_and_kernels_match_the_30_digit_evaluator():
             a, b = kernels_mp(t, CS, CP)
         tol = 1e-15 * max(1.0, t * t)       # the T^2 W terms amplify the rounding of W
         assert abs(ct[i] - float(a)) < tol and abs(cn[i] - float(b)) < tol, t
+
+
+def _normal_step_response_space_time(T, cs, cp, mu=1.0):
+    """sigma_22(0, t) for kappa*du = H(t) sin(k y), by quadrature of the
+    flat-fault space-time normal-traction kernel of section 2.4 in the form
+    of appendix B (kernels acting on the rate kappa*du_dot, so a step in
+    kappa*du gives the bracket itself at lag t):
+
+      P part, |xi| < c_p t:  4 c_s^2 mu t sqrt(t^2 - xi^2/c_p^2) / (2 pi xi^3)
+                             + c_s^2 lam^2 t / (2 pi mu c_p^2 xi sqrt(t^2 - xi^2/c_p^2))
+      S part, |xi| < c_s t:  -[4 c_s^2 mu t sqrt(t^2 - xi^2/c_s^2) / (2 pi xi^3)
+                               + (lam + 2 mu) t / (2 pi xi sqrt(t^2 - xi^2/c_s^2))]
+
+    (Readings: the P coefficient c_s^2 lam^2 / mu of appendix B, whose
+    main-text copy lost the 1/mu; the sign of the last term from appendix B's
+    bracketed S part.)  sigma(0, t) = -int B(xi, t) sin(k xi) dxi (B is odd,
+    the integrand even).  The two xi^-3 terms are combined near xi = 0, where
+    their difference is O(1/xi); tanh-sinh quadrature takes the inverse
+    square roots at the wave fronts.  Units: k = 1, so c_s t = T."""
+    mp.mp.dps = 30
+    cs, cp, mu = mp.mpf(cs), mp.mpf(cp), mp.mpf(mu)
+    lam = mu * (cp ** 2 / cs ** 2 - 2)
+    s = mp.mpf(T) / cs
+    A = lambda x: s * s - x * x / cp ** 2
+    B = lambda x: s * s - x * x / cs ** 2
+    p3 = lambda x: 4 * cs ** 2 * mu * s * mp.sqrt(A(x)) / (2 * mp.pi * x ** 3)
+    s3 = lambda x: -4 * cs ** 2 * mu * s * mp.sqrt(B(x)) / (2 * mp.pi * x ** 3)
+    p1 = lambda x: cs ** 2 * lam ** 2 * s / (2 * mp.pi * mu * cp ** 2 * x * mp.sqrt(A(x)))
+    s1 = lambda x: -(lam + 2 * mu) * s / (2 * mp.pi * x * mp.sqrt(B(x)))
+    # p3 + s3 without cancellation: sqrt(A) - sqrt(B) = x^2 (1/cs^2 - 1/cp^2) / (sqrt A + sqrt B)
+    ps3 = lambda x: (4 * cs ** 2 * mu * s * (1 / cs ** 2 - 1 / cp ** 2)
+                     / (2 * mp.pi * x * (mp.sqrt(A(x)) + mp.sqrt(B(x)))))
+    a = cs * s / 2
+    I = mp.quad(lambda x: (ps3(x) + p1(x) + s1(x)) * mp.sin(x), [0, a])
+    I += mp.quad(lambda x: (p3(x) + s3(x) + p1(x) + s1(x)) * mp.sin(x), [a, cs * s])
+    I += mp.quad(lambda x: (p3(x) + p1(x)) * mp.sin(x), [cs * s, cp * s])
+    return -2 * I
+
+
+@pytest.mark.parametrize("cs,cp", [(CS, CP), (3000.0, 6000.0)])
+def test_normal_kernel_is_the_transform_of_the_space_time_kernel(cs, cp):
+    """Sections 2.4 / appendix B: the normal-traction response to a step of
+    kappa*du = sin(k y) from the printed space-time kernel is
+    sigma_22 = mu [(1 - r) + C^N_II(c_s k t)] cos(k x) (tension positive),
+    so sigma_22(0, t) = mu [(1 - r) + C^N_II].  The oracle's
+    compression-positive reading, multiplier -i sgn(k), gives the negative
+    of this.  A pin of the dynamic normal operator that does not go through
+    the spectral multipliers."""
+    r = (cs / cp) ** 2
+    for T in ("0.05", "0.5", "2", "7", "20", "60"):
+        st = mp.re(_normal_step_response_space_time(mp.mpf(T), cs, cp))
+        with mp.workdps(30):
+            cn = mp.re(kernels_mp(mp.mpf(T), cs, cp)[1])
+            want = (1 - (mp.mpf(cs) / mp.mpf(cp)) ** 2) + cn
+        assert abs(st - want) < mp.mpf("1e-15"), (T, st, want)
+        fp = kernels_fp(np.array([float(T)]), cs, cp)[1][0]
+        # the FP64 evaluator's own bound (its pin above): 1e-15 max(1, T^2)
+        assert abs(float(st) - (1 - r) - fp) < 1e-15 * max(1.0, float(T) ** 2), (T, float(st), fp)
