@@ -349,10 +349,15 @@ int sbiem_slip_scaling(int64_t N, double L, double f, const double* slip, double
  * the stream it runs on.  While on, sbiem_run launches one step in every 33
  * directly, its convolution bracketed by two events, and replays the other
  * steps from the step graph (results are identical either way).
- * sbiem_profile returns the accumulated
- * milliseconds and launch count, the algorithmic bytes one launch reads
- * and writes (ring records of lags 2..M_n-1, partial sums) and resets the
- * counters. */
+ * On the variable-step engine (sbiem_step_var, sbiem_adapt,
+ * sbiem_adapt_until) every convolution launch is timed instead, by events
+ * that the launch itself stamps with its start and end.
+ * sbiem_profile returns the accumulated milliseconds and launch count, the
+ * algorithmic bytes one launch reads and writes (ring records of lags
+ * 2..M_n-1, partial sums; on the variable-step engine the average over
+ * the evented launches of the records inside each mode's window at the
+ * launch's time, the interval-log entries they use and the partial sums)
+ * and resets the counters. */
 int sbiem_set_profiling(sbiem_plan* p, int on);
 int sbiem_profile(sbiem_plan* p, double* conv_ms, int64_t* conv_launches,
                   double* conv_bytes_per_launch);

@@ -90,8 +90,12 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
     for (ConvTask k : d->tasks) tasks.push_back(ConvTask{k.t0 + base, k.t1 + base});
     // algorithmic bytes: ring records of lags 2..M_n-1 read, one history sum
     // (2 complex FP64) written per mode
+    // (variable-step engine: every slot of R_n, plus the interval log, once
+    // every slot holds an interval inside its window)
+    const bool var = d->var;
     for (size_t n = 1; n < d->Rn.size(); ++n)
-      if (d->Rn[n] > 1) bytes += rec * (d->Rn[n] - 1) + 32.0;
+      if (d->Rn[n] > 1) bytes += rec * (d->Rn[n] - (var ? 0 : 1)) + 32.0;
+    if (var) bytes += 16.0 * d->tlog_cap;
     for (ClosureMode c : d->closure) {
       c.fault = f;
       cmodes.push_back(c);
@@ -378,6 +382,38 @@ int ready(sbiem_plan* p, double dt) {
 // The launches of one step from t_old to t_new (no synchronisation; after a
 // failure every later launch of the fault returns without effect until the
 // flag is cleared).
+// Algorithmic bytes of a variable-step conv launch ending at t_new from the
+// host copy of the interval log: per mode, the stored intervals inside the
+// longer of its two windows (their records are loaded), the log entries
+// they touch, one partial sum written per mode.
+double var_conv_bytes(const sbiem_plan* p, double t_new) {
+  const DtData* d = p->dtd;
+  if (p->var_b < 0 || p->var_tend.empty()) return 0.0;
+  const long long cap = (long long)p->var_tend.size();
+  const double rec = p->precision == SBIEM_FP32CONV ? 16.0 : 32.0;
+  const double kc = std::max(p->kcL[0], p->kcL[1]);
+  double bytes = 0.0;
+  long long most = 0;
+  for (size_t n = 1; n < d->Rn.size(); ++n) {
+    const long long Rn = d->Rn[n];
+    if (Rn <= 0) continue;
+    const double kL = 2.0 * M_PI * (double)n;
+    const double window = std::min(kL, kc) / (p->cs * kL / p->L);
+    // the oldest interval that both the ring and the log still hold, then
+    // the first one inside the window (end times increase with l)
+    long long lo = std::max(0LL, p->var_b - std::min(Rn, cap) + 1), hi = p->var_b + 1;
+    while (lo < hi) {
+      const long long mid = (lo + hi) / 2;
+      if (t_new - p->var_tend[(size_t)(mid % cap)] < window) hi = mid;
+      else lo = mid + 1;
+    }
+    const long long live = p->var_b + 1 - lo;
+    bytes += rec * (double)live + 32.0;
+    most = std::max(most, live);
+  }
+  return bytes + 16.0 * (double)most;
+}
+
 // newest_end: end time of the newest stored interval (-inf: none).  When it
 // lies at least the longest window L/c_s before t_new (with a margin far
 // above rounding), every stored interval weighs exactly 0 for every mode:
@@ -388,13 +424,42 @@ hipError_t var_launch(sbiem_plan* p, double dt, double t_old, double t_new, doub
   const int nohist = (t_new - newest_end) >= (p->L / p->cs) * (1.0 + 1e-9) ? 1 : 0;
   const VarArgs va{dt, t_old, t_new, 1, nohist};
   hipError_t e = launch_reset_cells(ex, s);
-  if (!e && !nohist) e = launch_conv_var(ex, va, s);
+  if (!e && !nohist) {
+    // while profiling, the launch stamps two events of the plan's pool with
+    // its own start and end (read back by var_prof_collect after the next
+    // synchronisation)
+    const bool prof = p->profiling && p->events.ensure(2 * (size_t)(p->var_prof_pending + 1)) == hipSuccess;
+    if (prof) {
+      p->prof_bytes += var_conv_bytes(p, t_new);
+      e = launch_conv_var(ex, va, s, p->events.ev[2 * p->var_prof_pending],
+                          p->events.ev[2 * p->var_prof_pending + 1]);
+      if (!e) ++p->var_prof_pending;
+    } else {
+      e = launch_conv_var(ex, va, s);
+    }
+  }
   if (!e) e = launch_modes(ex, 0, 1, s, va);
   if (!e) e = launch_modes(ex, 0, 0, s, va);
   if (!e) e = launch_elems(ex, 1, s, va);
   if (!e) e = launch_modes(ex, 1, 0, s, va);
   if (!e) e = launch_elems(ex, 2, s, va);
   if (!e) e = launch_modes(ex, 2, 0, s, va);
+  return e;
+}
+
+// Add the evented conv launches of the last synchronised work to the
+// profile counters.
+hipError_t var_prof_collect(sbiem_plan* p) {
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < p->var_prof_pending && !e; ++k) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, p->events.ev[2 * k], p->events.ev[2 * k + 1]);
+    if (!e) {
+      p->prof_ms += ms;
+      p->prof_launches += 1;
+    }
+  }
+  p->var_prof_pending = 0;
   return e;
 }
 
@@ -416,6 +481,7 @@ int var_step(sbiem_plan* p, double dt) {
   const double t_new = p->t_var + dt;
   hipError_t e = var_launch(p, dt, p->t_var, t_new, var_newest_end(p));
   if (!e) e = hipStreamSynchronize(p->stream);
+  if (!e) e = var_prof_collect(p);
   if (e) return hip_fail(p, e, "variable step");
   p->dyn->primed = false;
   const int st = check_failure(p);
@@ -836,6 +902,7 @@ int adapt_impl(sbiem_plan* p, double eps0, double dt_max, double t_end, int64_t 
       unsigned long long r[4] = {0, 0, 0, 0};
       if (!e) e = hipMemcpyAsync(r, v->eps, sizeof(r), hipMemcpyDeviceToHost, s);
       if (!e) e = hipStreamSynchronize(s);
+      if (!e) e = var_prof_collect(p);
       if (e) return hip_fail(p, e, "adapt: attempt");
       d->primed = false;
       const int st = (int)(unsigned)r[2];
@@ -938,6 +1005,7 @@ int sbiem_set_profiling(sbiem_plan* p, int on) {
   p->profiling = on != 0;
   p->prof_ms = 0.0;
   p->prof_launches = 0;
+  p->prof_bytes = 0.0;
   return SBIEM_OK;
 }
 
@@ -946,9 +1014,15 @@ int sbiem_profile(sbiem_plan* p, double* conv_ms, int64_t* conv_launches,
   if (!p) return fail_global(SBIEM_EINVAL, "NULL plan");
   if (conv_ms) *conv_ms = p->prof_ms;
   if (conv_launches) *conv_launches = p->prof_launches;
-  if (conv_bytes_per_launch) *conv_bytes_per_launch = p->exec ? p->exec->conv_bytes : 0.0;
+  if (conv_bytes_per_launch) {
+    if (p->dtd && p->dtd->var)
+      *conv_bytes_per_launch = p->prof_launches ? p->prof_bytes / (double)p->prof_launches : 0.0;
+    else
+      *conv_bytes_per_launch = p->exec ? p->exec->conv_bytes : 0.0;
+  }
   p->prof_ms = 0.0;
   p->prof_launches = 0;
+  p->prof_bytes = 0.0;
   return SBIEM_OK;
 }
 

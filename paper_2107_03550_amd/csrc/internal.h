@@ -366,6 +366,8 @@ struct sbiem_plan {
   // engine: interval l at l mod tlog_cap, the last one var_b (-1: none)
   std::vector<double> var_tend;
   long long var_b = -1;
+  int var_prof_pending = 0;            // evented conv launches not yet read
+  double prof_bytes = 0.0;             // algorithmic bytes of the evented var conv launches
   sbiem::VarSnap* snap = nullptr;      // step-doubling snapshot buffers
 
   bool friction_set = false, state_set = false;
@@ -452,7 +454,9 @@ hipError_t launch_modes(const Exec& ex, int kind, int measure, hipStream_t s,
 hipError_t launch_elems(const Exec& ex, int kind, hipStream_t s,
                         const VarArgs& va = VarArgs{0.0, 0.0, 0.0, 0, 0});
 // variable steps: history sums over every stored interval at time va.t_new
-hipError_t launch_conv_var(const Exec& ex, const VarArgs& va, hipStream_t s);
+// e0, e1 (optional): stamped with the kernel's start and end
+hipError_t launch_conv_var(const Exec& ex, const VarArgs& va, hipStream_t s,
+                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // balance cells of every fault to "no maximum yet"
 hipError_t launch_reset_cells(const Exec& ex, hipStream_t s);
 // out[0] = bits of max_i max(|ln Va - ln Vb|, |ln tha - ln thb|) (equal

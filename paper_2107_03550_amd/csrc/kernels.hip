@@ -14,6 +14,8 @@
 //              assembly of the next step with the sums k_conv produced
 // The transforms are four-step FFTs split between element and mode
 // workgroups (see the index maps in internal.h).
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 
 #include <algorithm>
@@ -1397,25 +1399,52 @@ k_conv_var(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
           live = Tn < cutT || Tn < cutN;
         }
         // (a dead tile still reduces and records its zero partial below)
+        //
+        // Interval I + 1 starts where I ends (the log holds the same double),
+        // so the primitive at the end of slot p's interval is the primitive at
+        // the start of slot p + 1's: each lane evaluates P at its interval's
+        // start only and takes the end value from the next lane.  Chunks run
+        // newest last, so lane 63 takes it from lane 0 of the chunk after;
+        // only the tile's last slot and the slot of the newest interval b
+        // (whose successor slot holds the oldest one) evaluate it directly.
+        double nxT = 0.0, nxN = 0.0;  // P at lane 0's start in the chunk after
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = U - 1; u >= 0; --u) {
           const int p = tl.p0 + lane + 64 * u;
-          if (!live || p >= end) continue;
-          const long long I = b - (long long)mod_pos(b - p + (long long)Rn * 4, Rn);
-          if (I < 0) continue;
-          const double2 iv = fd.tlog[I % fd.tlog_cap];
+          bool valid = live && p < end;
+          const long long I =
+              valid ? b - (long long)mod_pos(b - p + (long long)Rn * 4, Rn) : -1;
+          valid = valid && I >= 0;
+          const double2 iv = valid ? fd.tlog[I % fd.tlog_cap] : make_double2(0.0, 0.0);
           const double Ta = csk * (va.t_new - iv.y), Tb = csk * (va.t_new - iv.x);
-          if (Ta >= cutT && Ta >= cutN) continue;   // past both windows: weight 0
-          double pTa, pNa, pTb, pNb;
-          ptab_eval(fd.ptab, fd.ptab_len, fd.ptab_h, fmin(Ta, cutT), &pTa, &pNa);
-          ptab_eval(fd.ptab, fd.ptab_len, fd.ptab_h, fmin(Tb, cutT), &pTb, &pNb);
-          const double wT = (pTb - pTa) * inv;
-          if (cutN != cutT) {
-            double x;
-            ptab_eval(fd.ptab, fd.ptab_len, fd.ptab_h, fmin(Ta, cutN), &x, &pNa);
-            ptab_eval(fd.ptab, fd.ptab_len, fd.ptab_h, fmin(Tb, cutN), &x, &pNb);
+          double pTb = 0.0, pNb = 0.0, qNb = 0.0;  // q: the normal kind's own cut
+          if (valid) {
+            ptab_eval(fd.ptab, fd.ptab_len, fd.ptab_h, fmin(Tb, cutT), &pTb, &pNb);
+            if (cutN != cutT) {
+              double x;
+              ptab_eval(fd.ptab, fd.ptab_len, fd.ptab_h, fmin(Tb, cutN), &x, &qNb);
+            } else {
+              qNb = pNb;
+            }
           }
-          const double wN = (pNb - pNa) * inv;
+          // end values from the next slot (lane + 1, or lane 0 of chunk u + 1)
+          double pTa = __shfl_down(pTb, 1), qNa = __shfl_down(qNb, 1);
+          if (lane == 63) {
+            pTa = nxT;
+            qNa = nxN;
+          }
+          nxT = __shfl(pTb, 0);
+          nxN = __shfl(qNb, 0);
+          const bool inwin = valid && !(Ta >= cutT && Ta >= cutN);
+          const bool shared = (lane < 63 || u < U - 1) && p + 1 < end && p != pb;
+          if (inwin && !shared) {
+            double x;
+            ptab_eval(fd.ptab, fd.ptab_len, fd.ptab_h, fmin(Ta, cutT), &pTa, &qNa);
+            if (cutN != cutT) ptab_eval(fd.ptab, fd.ptab_len, fd.ptab_h, fmin(Ta, cutN), &x, &qNa);
+          }
+          if (!inwin) continue;
+          const double wT = (pTb - pTa) * inv;
+          const double wN = (qNb - qNa) * inv;
           const Rec r = ring[p];
           if constexpr (sizeof(R) == 4) {
             ax = fma(wT, (double)r.x, ax);
@@ -1484,15 +1513,17 @@ __global__ void k_err_norm(const double* __restrict__ Va, const double* __restri
   }
 }
 
-hipError_t launch_conv_var(const Exec& ex, const VarArgs& va, hipStream_t s) {
+hipError_t launch_conv_var(const Exec& ex, const VarArgs& va, hipStream_t s, hipEvent_t e0,
+                           hipEvent_t e1) {
   if (ex.ntasks == 0) return hipSuccess;
   const int grid = std::min(ex.ntasks, 4096);
+  // with events: stamped by the kernel's own dispatch (its execution alone)
   if (ex.precision == SBIEM_FP32CONV)
-    hipLaunchKernelGGL(k_conv_var<float>, dim3(grid), dim3(kConvThreads), 0, s, ex.d_faults,
-                       ex.d_tiles, ex.d_tasks, ex.ntasks, va);
+    hipExtLaunchKernelGGL(k_conv_var<float>, dim3(grid), dim3(kConvThreads), 0, s, e0, e1, 0,
+                          ex.d_faults, ex.d_tiles, ex.d_tasks, ex.ntasks, va);
   else
-    hipLaunchKernelGGL(k_conv_var<double>, dim3(grid), dim3(kConvThreads), 0, s, ex.d_faults,
-                       ex.d_tiles, ex.d_tasks, ex.ntasks, va);
+    hipExtLaunchKernelGGL(k_conv_var<double>, dim3(grid), dim3(kConvThreads), 0, s, e0, e1, 0,
+                          ex.d_faults, ex.d_tiles, ex.d_tasks, ex.ntasks, va);
   return hipGetLastError();
 }
 
