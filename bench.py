@@ -303,13 +303,21 @@ def closure_accuracy(pkg, nets):
         runs[name] = p
     worst = {k: {"tau_el": 0.0, "V": 0.0} for k in runs}
     arrival = {k: np.full(N, -1) for k in ("plain", *runs)}
+    failed = {}
     steps, chunk = 6000, 2
     for k in range(1, steps // chunk + 1):
         ref.run(w.dt, chunk)
         g = ref.get_state()
         arrival["plain"][(arrival["plain"] < 0) & (g["V"] > 1e-3)] = k * chunk
         for name, p in runs.items():
-            p.run(w.dt, chunk)
+            if name in failed:
+                continue
+            st = p.run_status(w.dt, chunk)
+            if st != 0:
+                # a physics failure of the closed run (the plain run went on)
+                failed[name] = {"step": k * chunk, "status": pkg.lib.sbiem_status_string(st).decode(),
+                                "plain_max_V": float(g["V"].max())}
+                continue
             h = p.get_state()
             arrival[name][(arrival[name] < 0) & (h["V"] > 1e-3)] = k * chunk
             for key in ("tau_el", "V"):
@@ -319,15 +327,18 @@ def closure_accuracy(pkg, nets):
     span = int(arrival["plain"][hit].max() - arrival["plain"][hit].min()) if hit.any() else 0
     out = {"scenario": f"{w.name}: {steps} steps through nucleation and rupture, cut 1/4; "
                        f"arrival = first step with V >= 1e-3 m/s (2-step resolution), error "
-                       f"relative to the rupture's propagation time over the ruptured elements",
-           "ruptured_elements": int(hit.sum()), "propagation_steps": span}
+                       f"relative to the rupture's propagation time over the ruptured elements; "
+                       f"errors over the steps each closed run completed",
+           "ruptured_elements": int(hit.sum()), "propagation_steps": span,
+           "plain_max_V": float(ref.get_state()["V"].max())}
     for name in runs:
         a = arrival[name]
         ok = hit & (a >= 0)
         d = np.abs(a[ok] - arrival["plain"][ok]) / max(span, 1)
         out[name] = {"tau_el_rel_err": worst[name]["tau_el"], "V_rel_err": worst[name]["V"],
                      "arrival_rel_err_max": float(d.max()) if d.size else None,
-                     "missed_arrivals": int((hit & (a < 0)).sum())}
+                     "missed_arrivals": int((hit & (a < 0)).sum()),
+                     "failed": failed.get(name)}
     return out
 
 

@@ -150,10 +150,13 @@ def test_trained_closure_against_plain_and_constant_extrapolation():
     runs of four rough faults (two slow, two nucleating) close a held-out
     nucleating fault; the run is compared with the plain full-window run, and
     so is the same closure with zero networks (the constant extrapolation
-    alone).  The closure must keep the rupture arrival times within 1 % of
-    the plain run's; the stress and slip-rate errors of both forms are
-    reported.  Training must not leave the networks worse than zero networks
-    on their own pairs."""
+    alone).  The trained networks must beat zero networks on pairs of the
+    held-out fault and in slip rate against the plain run; the closure must
+    keep the rupture arrival times within 1 % of the plain run's and the
+    shear traction within 1e-2 of it (measured about 7e-3: the 1e-3 target
+    is not met; the 16 kept amplitudes carry little information about the
+    discarded history beyond the constant extrapolation, which is what the
+    traction error is made of)."""
     from paper_2107_03550_amd.closure_train import collect_pairs, train_networks
     pkg = _pkg()
     N, steps = 2048, 3000
@@ -161,12 +164,13 @@ def test_trained_closure_against_plain_and_constant_extrapolation():
     plans = [make_plan(sc, pkg.SBIEM_FP32CONV) for sc in train]
     pairs = collect_pairs(plans, train[0].dt, steps=steps, every=50)
     pT, pN, _, _ = train_networks(pairs, steps=2000, batch=2048, lr=1e-3)
-    for (X, Y), p in zip(pairs, (pT, pN)):
-        fit = np.mean(np.sum((pkg.closure_eval(p, X) - Y) ** 2, axis=1))
-        zero = np.mean(np.sum(Y.astype(np.float64) ** 2, axis=1))
-        print("closure training: loss", fit, "zero network", zero)
-        assert fit <= 1.05 * zero
     ev = _nucleating(N, 777, 6e6)
+    held_out = collect_pairs([make_plan(ev, pkg.SBIEM_FP32CONV)], ev.dt, steps=steps, every=50)
+    for kind, (X, Y), p in zip(("shear", "normal"), held_out, (pT, pN)):
+        fit = np.mean(np.sum((pkg.closure_eval(p, X).astype(np.float64) - Y) ** 2, axis=1))
+        zero = np.mean(np.sum(Y.astype(np.float64) ** 2, axis=1))
+        print(f"closure {kind}: held-out pairs {len(X)}, loss {fit:.5g}, zero network {zero:.5g}")
+        assert fit < zero
     ref = make_plan(ev, pkg.SBIEM_FP32CONV)
     runs = {"trained": make_plan(ev, pkg.SBIEM_FP32CONV), "zero": make_plan(ev, pkg.SBIEM_FP32CONV)}
     runs["trained"].set_closure(pT, pN, 0.25)
@@ -195,4 +199,5 @@ def test_trained_closure_against_plain_and_constant_extrapolation():
               f"arrival max {d.max():.3e} mean {d.mean():.3e}")
         if name == "trained":
             assert d.max() <= 0.01
-            assert worst[name][0] < 5e-2
+            assert worst[name][0] < 1e-2
+    assert worst["trained"][1] < worst["zero"][1], worst
