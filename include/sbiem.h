@@ -386,13 +386,31 @@ int sbiem_batch_profile(sbiem_batch* b, double* conv_ms, int64_t* conv_launches,
  * convolution or before the first element launch, steps_per_trial steps
  * each (rounded up to the 16-step graph, plus one settling graph), and the
  * fastest is kept until the plan's tables are rebuilt (sbiem_set_dt,
- * sbiem_set_precision, sbiem_set_closure).  The trial steps are ordinary
- * steps: results do not depend on the launch shape or order, and the state
- * advances by about (steps_per_trial + 16) times the number of candidates
- * (at most 10, 20 with the closure).  *conv_workgroups (may be NULL) receives
- * the chosen grid.  FP64 plans have nothing to tune (OK).  Errors as
- * sbiem_run; a plan used by a batch is tuned through the batch. */
+ * sbiem_set_precision, sbiem_set_closure).  Unless a member's tile was set
+ * with sbiem_set_conv_tile, all of this is repeated for each FP32 tile
+ * shape (256, 512 and 1024 ring records per tile; the ring itself does not
+ * change) and the fastest tile is kept with its grid and order.  The trial
+ * steps are ordinary steps: results do not depend on the launch shape or
+ * order, and a tile change alters only the FP32 summation order of the
+ * history sums; the state advances by about (steps_per_trial + 16) times the
+ * number of candidates (at most 10, 20 with the closure, per tile).
+ * *conv_workgroups (may be NULL) receives the chosen grid
+ * (sbiem_get_conv_tile the tile).  FP64 plans have nothing to tune (OK).
+ * Errors as sbiem_run; a plan used by a batch is tuned through the batch. */
 int sbiem_tune(sbiem_plan* p, double dt, int64_t steps_per_trial, int32_t* conv_workgroups);
+
+/* FP32 convolution tile: records = 256, 512 or 1024 ring records per
+ * wavefront tile (16 rows of 64 records in flight per wave either way, so a
+ * workgroup task stays 8192 records), or 0 for the default by window length
+ * (512; 256 under the learned closure, whose kept windows are short).  A
+ * non-zero tile is kept by sbiem_tune.  The tiling is the summation order
+ * of the FP32 history sums, so runs on different tiles agree to FP32
+ * rounding, runs on one tile bit for bit.  Applies to FP32 fixed-step plans
+ * (others keep 256 FP64 slots); takes effect at once (pending sums are
+ * recomputed).  Errors: EINVAL (other sizes, a plan used by a batch). */
+int sbiem_set_conv_tile(sbiem_plan* p, int records);
+/* The tile in use (records per tile). */
+int sbiem_get_conv_tile(const sbiem_plan* p, int* records);
 int sbiem_batch_tune(sbiem_batch* b, int64_t steps_per_trial, int32_t* conv_workgroups);
 
 /* ---------------------------------------------------------------------------

@@ -67,6 +67,8 @@ _SIGS = {
     "sbiem_adapt_until": (_int, [_PLAN, _dbl, _dbl, _dbl, _i64, _dbl, _D, _D, _i64, _I64,
                                  ctypes.POINTER(ctypes.c_int)]),
     "sbiem_set_constrained": (_int, [_PLAN, ctypes.POINTER(ctypes.c_uint8)]),
+    "sbiem_set_conv_tile": (_int, [_PLAN, _int]),
+    "sbiem_get_conv_tile": (_int, [_PLAN, ctypes.POINTER(ctypes.c_int)]),
     "sbiem_slip_scaling": (_int, [_i64, _dbl, _dbl, _D, _dbl, _D]),
     "sbiem_kernel_primitive_eval": (_int, [_dbl, _dbl, _D, _i64, _D, _D]),
     "sbiem_set_friction": (_int, [_PLAN, _D, _D, _dbl, _dbl, _dbl, _D, _D, _dbl, _dbl]),
@@ -398,6 +400,15 @@ class Plan:
         ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
         self._c(lib.sbiem_profile(self.handle, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
         return ms.value, n.value, b.value
+
+    def set_conv_tile(self, records):
+        """FP32 conv tile (256, 512, 1024 records; 0 = default by window)."""
+        self._c(lib.sbiem_set_conv_tile(self.handle, int(records)))
+
+    def conv_tile(self):
+        r = ctypes.c_int()
+        self._c(lib.sbiem_get_conv_tile(self.handle, ctypes.byref(r)))
+        return r.value
 
     def tune(self, dt, steps_per_trial=64):
         """Autotune the convolution grid on ordinary steps; returns the

@@ -699,8 +699,9 @@ hipError_t run_steps(Exec* ex, int64_t nsteps, hipStream_t s, bool profile, Even
 // sums, and the dependencies are the same), so the trial steps are ordinary
 // steps of the simulation.
 hipError_t tune_conv(Exec* ex, int64_t steps_per_trial, hipStream_t s, int* chosen,
-                     const char** what) {
+                     const char** what, float* best_ms_out = nullptr) {
   *chosen = ex->conv_grid;
+  if (best_ms_out) *best_ms_out = 0.f;
   if (ex->precision != SBIEM_FP32CONV || ex->ntasks == 0) return hipSuccess;
   *what = "running the prologue launches";
   hipError_t e = prologue(*ex, s);
@@ -757,7 +758,76 @@ hipError_t tune_conv(Exec* ex, int64_t steps_per_trial, hipStream_t s, int* chos
   ex->stages_first = best.first;
   ex->closure_main = best.cmain;
   *chosen = best.grid;
+  if (best_ms_out) *best_ms_out = best_ms;
   return e;
+}
+
+// Tile shapes of the FP32 conv to try: the one in use first, then the
+// others (none when a member's tile was set explicitly).
+std::vector<int> tile_candidates(const std::vector<sbiem_plan*>& plans) {
+  const DtData* d = plans[0]->dtd;
+  std::vector<int> c{d->tile_slots};
+  if (d->var || plans[0]->precision != SBIEM_FP32CONV) return c;
+  for (const sbiem_plan* p : plans)
+    if (p->conv_tile_set) return c;
+  for (int t : {kTileSlots32, kTileSlots32s, kTileSlots32l})
+    if (t != c[0]) c.push_back(t);
+  return c;
+}
+
+// Autotuning over tile shapes: for each candidate the members are re-cut
+// (retile), the execution context rebuilt by `rebuild` and tune_conv run on
+// it; the fastest tile with its grid and launch order is kept.  Every trial
+// step is an ordinary step (a tile change alters only the FP32 summation
+// order of the sums).
+template <typename Rebuild, typename GetExec>
+int tune_tiles(const std::vector<sbiem_plan*>& plans, int64_t steps_per_trial, hipStream_t s,
+               Rebuild rebuild, GetExec get_exec, int* chosen, int* tile_out, std::string* err) {
+  const std::vector<int> cand = tile_candidates(plans);
+  struct Best {
+    int tile = 0, grid = 0;
+    bool first = false, cmain = false;
+    float ms = 0.f;
+  } best;
+  const char* what = "";
+  for (size_t c = 0; c < cand.size(); ++c) {
+    if (c > 0) {
+      for (sbiem_plan* p : plans)
+        if (int st = retile(p, cand[c])) return st;
+      if (int st = rebuild()) return st;
+      for (sbiem_plan* p : plans) p->dyn->primed = false;
+    }
+    Exec* ex = get_exec();
+    int g = 0;
+    float ms = 0.f;
+    hipError_t e = tune_conv(ex, steps_per_trial, s, &g, &what, &ms);
+    if (!e) e = hipStreamSynchronize(s);
+    if (e) {
+      *err = std::string(what) + ": " + hipGetErrorString(e);
+      return SBIEM_EDEVICE;
+    }
+    if (c == 0 || ms < best.ms) {
+      best.tile = cand[c];
+      best.grid = ex->conv_grid;
+      best.first = ex->stages_first;
+      best.cmain = ex->closure_main;
+      best.ms = ms;
+    }
+  }
+  if (cand.size() > 1) {
+    for (sbiem_plan* p : plans)
+      if (int st = retile(p, best.tile)) return st;
+    if (int st = rebuild()) return st;
+    for (sbiem_plan* p : plans) p->dyn->primed = false;
+    Exec* ex = get_exec();
+    ex->conv_grid = best.grid;
+    ex->stages_first = best.first;
+    ex->closure_main = best.cmain;
+    for (sbiem_plan* p : plans) p->conv_tile = best.tile;
+  }
+  *chosen = best.grid;
+  *tile_out = best.tile;
+  return SBIEM_OK;
 }
 
 }  // namespace
@@ -1208,14 +1278,13 @@ int sbiem_tune(sbiem_plan* p, double dt, int64_t steps_per_trial, int32_t* conv_
     if (conv_workgroups) *conv_workgroups = std::min(p->exec->ntasks, 4096);
     return SBIEM_OK;
   }
-  const char* what = "";
-  int chosen = 0;
-  e = tune_conv(p->exec, steps_per_trial, p->stream, &chosen, &what);
-  if (!e) {
-    what = "waiting for the tuning steps";
-    e = hipStreamSynchronize(p->stream);
-  }
-  if (e) return hip_fail(p, e, what);
+  int chosen = 0, tile = 0;
+  std::string err;
+  const int st = tune_tiles(
+      {p}, steps_per_trial, p->stream, [&]() { return rebuild_exec(p); },
+      [&]() { return p->exec; }, &chosen, &tile, &err);
+  if (st == SBIEM_EDEVICE && !err.empty()) return fail(p, st, "tune: " + err);
+  if (st) return st;
   if (conv_workgroups) *conv_workgroups = chosen;
   return check_failure(p);
 }
@@ -1223,15 +1292,32 @@ int sbiem_tune(sbiem_plan* p, double dt, int64_t steps_per_trial, int32_t* conv_
 int sbiem_batch_tune(sbiem_batch* b, int64_t steps_per_trial, int32_t* conv_workgroups) {
   if (!b || steps_per_trial < 1) return fail_global(SBIEM_EINVAL, "batch_tune: bad arguments");
   hipError_t e = hipSetDevice(b->device);
-  const char* what = "hipSetDevice";
-  int chosen = 0;
-  if (!e) e = tune_conv(b->exec, steps_per_trial, b->stream, &chosen, &what);
-  if (!e) {
-    what = "waiting for the tuning steps";
-    e = hipStreamSynchronize(b->stream);
-  }
-  if (e)
-    return fail_global(SBIEM_EDEVICE, std::string("batch_tune: ") + what + ": " + hipGetErrorString(e));
+  if (e) return fail_global(SBIEM_EDEVICE, std::string("batch_tune: hipSetDevice: ") + hipGetErrorString(e));
+  int chosen = 0, tile = 0;
+  std::string err;
+  auto rebuild = [&]() -> int {
+    std::vector<DtData*> dts;
+    std::vector<DynData*> dyns;
+    std::vector<FaultDev> descs;
+    for (sbiem_plan* p : b->plans) {
+      dts.push_back(p->dtd);
+      dyns.push_back(p->dyn);
+      descs.push_back(make_fault_desc(p, p->dtd, p->dyn, p->V_pl, p->t0));
+    }
+    (void)hipStreamSynchronize(b->stream);
+    delete b->exec;
+    b->exec = nullptr;
+    std::string why;
+    Exec* ex = nullptr;
+    const int st = build_exec(b->plans, dts, dyns, descs, b->plans[0]->precision, &ex, &why);
+    if (st) return fail_global(st, "batch_tune: " + why);
+    b->exec = ex;
+    return (int)SBIEM_OK;
+  };
+  const int st = tune_tiles(b->plans, steps_per_trial, b->stream, rebuild,
+                            [&]() { return b->exec; }, &chosen, &tile, &err);
+  if (st == SBIEM_EDEVICE && !err.empty()) return fail_global(st, "batch_tune: " + err);
+  if (st) return st;
   if (conv_workgroups) *conv_workgroups = chosen;
   int first = SBIEM_OK;
   for (sbiem_plan* p : b->plans) {

@@ -145,6 +145,9 @@ constexpr int kTaskTiles32 = kWaveTiles32 * (kConvThreads / 64);
 constexpr int kTileSlots32s = 256;
 constexpr int kWaveTiles32s = 4;
 constexpr int kTaskTiles32s = kWaveTiles32s * (kConvThreads / 64);
+// FP32 tile shapes the conv can take (records per tile; 16 rows in flight per
+// wave, so every task is 8192 records): 256 (short windows), 512, 1024
+constexpr int kTileSlots32l = 1024;
 constexpr int kTileSlots64 = 256;   // FP64 records per wavefront tile
 constexpr int kTaskTiles64 = 16;
 constexpr int kTaskTiles = kTaskTiles32s > kTaskTiles64 ? kTaskTiles32s : kTaskTiles64;  // at most
@@ -232,6 +235,8 @@ struct DtData {
   int tile_slots = 0;            // records per tile
   std::vector<ConvTask> tasks;   // this fault's tasks (tile indices local)
   std::vector<int> part0, nparts;
+  int parts_cap = 0;             // partial sums the parts buffer holds
+  std::vector<ModeCoef> coef_host;  // host copy of coef (retiling rewrites part0, nparts)
   int table_len = 0;             // FP32 table nodes
   DevArena mem;
   ModeCoef* coef = nullptr;      // at mode_pos
@@ -372,6 +377,8 @@ struct sbiem_plan {
 
   bool friction_set = false, state_set = false;
   double Dc = 0, V_ref = 0, f0 = 0, tau_rate = 0, V_pl = 0, t0 = 0;
+  int conv_tile = 0;                   // FP32 conv tile records (0: by window length)
+  bool conv_tile_set = false;          // set by sbiem_set_conv_tile: tuning keeps it
   std::vector<double> a_host;          // direct effect a as set (natural order)
   std::vector<uint8_t> constrained;    // elements held at V_pl (empty: none)
 
@@ -434,6 +441,13 @@ bool var_engine(const sbiem_plan* p);
 FaultDev make_fault_desc(sbiem_plan* p, DtData* dtd, DynData* dyn, double V_pl, double t0);
 // Allocate tables/ring for dt (host side computations + uploads).
 int build_dt_data(sbiem_plan* p, double dt, DtData** out);
+// Re-cut an FP32 fixed-step plan's conv work into tiles of `tile` records
+// (256, 512, 1024): tiles, tasks, partial indices and per-mode constants;
+// the ring is untouched.  The caller rebuilds the execution context and
+// clears `primed` (the pending sums are laid out by tile).
+int retile(sbiem_plan* p, int tile);
+// Rewrite the plan's device fault descriptor (and its launch context's).
+int refresh_desc(sbiem_plan* p);
 // Allocate the dynamic state buffers.
 int build_dyn_data(sbiem_plan* p, DynData** out);
 // Build an execution context over faults (tiles, partials, Newton map).

@@ -1664,6 +1664,9 @@ hipError_t setup_kernel_attributes(int precision) {
   if (!e && idx)
     e = hipFuncSetAttribute((const void*)k_conv32<4, 4>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+  if (!e && idx)
+    e = hipFuncSetAttribute((const void*)k_conv32<16, 1>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
   if (!e) done[idx] = true;
   return e;
 }
@@ -1698,8 +1701,13 @@ hipError_t launch_conv(const Exec& ex, int ahead, hipStream_t s) {
     const size_t lds = (size_t)ex.table_len * sizeof(float4);
     static_assert(kTileSlots32 == 8 * 64 && kWaveTiles32 == 2, "tile shape");
     static_assert(kTileSlots32s == 4 * 64 && kWaveTiles32s == 4, "short tile shape");
+    static_assert(kTileSlots32l == 16 * 64, "long tile shape");
     if (ex.tile_rows == 4)
       hipLaunchKernelGGL((k_conv32<4, 4>), dim3(ex.conv_grid), dim3(kConvThreads), lds, s,
+                         ex.d_faults, ex.d_tiles, ex.d_tasks, ex.ntasks, ex.table, ex.table_len,
+                         ahead, ex.conv_ctr);
+    else if (ex.tile_rows == 16)
+      hipLaunchKernelGGL((k_conv32<16, 1>), dim3(ex.conv_grid), dim3(kConvThreads), lds, s,
                          ex.d_faults, ex.d_tiles, ex.d_tasks, ex.ntasks, ex.table, ex.table_len,
                          ahead, ex.conv_ctr);
     else

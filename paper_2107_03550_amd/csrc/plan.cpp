@@ -220,6 +220,59 @@ void lag_weights(const sbiem_plan* p, int n, double dt, int MT, int MN, int j0, 
 
 }  // namespace
 
+// Tiles (one wavefront each) and tasks (one workgroup each) of a fault's
+// ring: a task holds whole modes up to task_tiles tiles, a longer mode is
+// cut into pieces of task_tiles tiles, each with its own partial sum (the
+// first piece of mode n at parts[mode_pos(n)], further pieces from N/2 + 1
+// on).  FP32 tiles keep 16 rows of 64 records in flight per wave, so a task
+// is 8192 records whatever the tile.  Returns the number of partial sums.
+int build_tiles(const sbiem_plan* p, DtData* d, int tile, long double th_unit) {
+  const int half = (int)(p->N / 2);
+  const bool fp32 = p->precision == SBIEM_FP32CONV && !d->var;
+  const int task_tiles = fp32 ? (16 / (tile / 64)) * (kConvThreads / 64) : kTaskTiles64;
+  d->tile_slots = tile;
+  d->tiles.clear();
+  d->tasks.clear();
+  d->part0.assign(half + 1, 0);
+  d->nparts.assign(half + 1, 0);
+  int extra = half + 1;
+  int cur_tiles = 0;
+  auto open_task = [&]() {
+    d->tasks.push_back(ConvTask{(int)d->tiles.size(), (int)d->tiles.size()});
+    cur_tiles = 0;
+  };
+  for (int n = 1; n <= half; ++n) {
+    const int count = (d->Rn[n] + tile - 1) / tile;
+    if (count == 0) continue;
+    if (d->tasks.empty() || cur_tiles + std::min(count, task_tiles) > task_tiles) open_task();
+    const int extra0 = extra;
+    int part = mode_pos(n, p->log2P, p->log2Q);
+    for (int k = 0; k < count; ++k) {
+      if (cur_tiles == task_tiles) {  // a long mode continues in a new task
+        open_task();
+        part = extra++;
+      }
+      Tile t;
+      t.fault = 0;
+      t.mode = n;
+      t.p0 = k * tile;
+      t.len = std::min(tile, d->Rn[n] - k * tile);
+      t.Rn = d->Rn[n];
+      t.part = part;
+      t.MT = d->MT[n];
+      t.MN = d->MN[n];
+      t.ring_off = d->ring_off[n];
+      t.th = (double)(th_unit * n);
+      d->tiles.push_back(t);
+      d->tasks.back().t1 = (int)d->tiles.size();
+      ++cur_tiles;
+    }
+    d->part0[n] = extra0;
+    d->nparts[n] = 1 + (extra - extra0);
+  }
+  return extra;
+}
+
 int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
   *out = nullptr;
   DtData* d = new DtData();
@@ -261,58 +314,16 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
     Rmax = std::max(Rmax, d->Rn[n]);
   }
   d->ring_slots = slots;
-  // conv tiles (one wavefront each) and tasks (one workgroup each): a task
-  // holds whole modes up to task_tiles tiles, a longer mode is cut into
-  // pieces of task_tiles tiles
+  // conv tiles (one wavefront each) and tasks (one workgroup each)
   // (FP32 under the learned closure: shorter tiles, most kept windows being
   // far shorter than a full tile; the variable-step conv uses FP64 tiles)
   const bool fp32 = p->precision == SBIEM_FP32CONV && !d->var;
-  const bool short_tiles = fp32 && p->closure_on;
-  const int tile = fp32 ? (short_tiles ? kTileSlots32s : kTileSlots32) : kTileSlots64;
-  const int task_tiles = fp32 ? (short_tiles ? kTaskTiles32s : kTaskTiles32) : kTaskTiles64;
-  d->tile_slots = tile;
+  const int tile = fp32 ? (p->conv_tile ? p->conv_tile
+                                        : (p->closure_on ? kTileSlots32s : kTileSlots32))
+                        : kTileSlots64;
   const long double th_unit = 3.141592653589793238462643383279502884L * (long double)p->cs *
                               (long double)dt / (long double)p->L / (long double)kTableStep;
-  d->part0.assign(half + 1, 0);
-  d->nparts.assign(half + 1, 0);
-  // conv partials: the first piece of mode n is parts[mode_pos(n)]; further
-  // pieces of a mode longer than one task follow from index N/2 + 1 on
-  int extra = half + 1;
-  int cur_tiles = 0;
-  auto open_task = [&]() {
-    d->tasks.push_back(ConvTask{(int)d->tiles.size(), (int)d->tiles.size()});
-    cur_tiles = 0;
-  };
-  for (int n = 1; n <= half; ++n) {
-    const int count = (d->Rn[n] + tile - 1) / tile;
-    if (count == 0) continue;
-    if (d->tasks.empty() || cur_tiles + std::min(count, task_tiles) > task_tiles) open_task();
-    const int extra0 = extra;
-    int part = mode_pos(n, p->log2P, p->log2Q);
-    for (int k = 0; k < count; ++k) {
-      if (cur_tiles == task_tiles) {  // a long mode continues in a new task
-        open_task();
-        part = extra++;
-      }
-      Tile t;
-      t.fault = 0;
-      t.mode = n;
-      t.p0 = k * tile;
-      t.len = std::min(tile, d->Rn[n] - k * tile);
-      t.Rn = d->Rn[n];
-      t.part = part;
-      t.MT = d->MT[n];
-      t.MN = d->MN[n];
-      t.ring_off = d->ring_off[n];
-      t.th = (double)(th_unit * n);
-      d->tiles.push_back(t);
-      d->tasks.back().t1 = (int)d->tiles.size();
-      ++cur_tiles;
-    }
-    d->part0[n] = extra0;
-    d->nparts[n] = 1 + (extra - extra0);
-  }
-  const int parts = extra;
+  const int parts = build_tiles(p, d, tile, th_unit);
   // per-mode constants: lags 0 and 1 of the plan's rule (the variable-step
   // engine recomputes lag 0 per step and keeps lag 1 in its sums)
   std::vector<ModeCoef> coef(half + 1);
@@ -347,6 +358,7 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
   hipError_t e = hipSuccess;
   hipStream_t s = p->stream;
   d->coef = upload(d->mem, coef, s, &e);
+  d->coef_host = coef;
   d->th_mode.assign(half + 1, 0.0);
   for (int n = 0; n <= half; ++n) d->th_mode[n] = (double)(th_unit * n);
   if (!e && p->closure_on) {
@@ -383,6 +395,7 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
   }
   if (!e) {
     d->parts = (double4*)d->mem.get(sizeof(double4) * std::max(1, parts));
+    d->parts_cap = std::max(1, parts);
     if (!d->parts) e = hipErrorOutOfMemory;
     else e = hipMemsetAsync(d->parts, 0, sizeof(double4) * std::max(1, parts), s);
   }
@@ -483,6 +496,38 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
   }
   *out = d;
   return SBIEM_OK;
+}
+
+int retile(sbiem_plan* p, int tile) {
+  DtData* d = p->dtd;
+  if (!d || d->var || p->precision != SBIEM_FP32CONV || d->tile_slots == tile) return SBIEM_OK;
+  const int half = (int)(p->N / 2);
+  const long double th_unit = 3.141592653589793238462643383279502884L * (long double)p->cs *
+                              (long double)d->dt / (long double)p->L / (long double)kTableStep;
+  const int parts = build_tiles(p, d, tile, th_unit);
+  hipStream_t s = p->stream;
+  hipError_t e = hipStreamSynchronize(s);
+  if (!e && parts > d->parts_cap) {
+    double4* np = (double4*)d->mem.get(sizeof(double4) * parts);
+    if (!np) return fail(p, SBIEM_ENOMEM, "retile: partial sums");
+    d->parts = np;
+    d->parts_cap = parts;
+  }
+  if (!e) e = hipMemsetAsync(d->parts, 0, sizeof(double4) * d->parts_cap, s);
+  for (int n = 1; n <= half; ++n) {
+    ModeCoef& c = d->coef_host[mode_pos(n, p->log2P, p->log2Q)];
+    c.part0 = d->part0[n];
+    c.nparts = d->nparts[n];
+  }
+  if (!e)
+    e = hipMemcpyAsync(d->coef, d->coef_host.data(), sizeof(ModeCoef) * d->coef_host.size(),
+                       hipMemcpyHostToDevice, s);
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return hip_fail(p, e, "retile");
+  // the plan's own launch context holds the old tiles: rebuilt on next use
+  delete p->exec;
+  p->exec = nullptr;
+  return refresh_desc(p);
 }
 
 void discarded_weights(double cs, double cp, double L, double dt, const std::vector<int>& n,
@@ -948,6 +993,32 @@ int sbiem_kernel_primitive_eval(double cs, double cp, const double* T, int64_t n
     if (PT) PT[i] = (double)a;
     if (PN) PN[i] = (double)b;
   }
+  return SBIEM_OK;
+}
+
+int sbiem_set_conv_tile(sbiem_plan* p, int records) {
+  if (int s = check_plan(p)) return s;
+  if (records != 0 && records != kTileSlots32s && records != kTileSlots32 &&
+      records != kTileSlots32l)
+    return fail(p, SBIEM_EINVAL, "set_conv_tile: records must be 0, 256, 512 or 1024");
+  if (p->batch_refs > 0) return fail(p, SBIEM_EINVAL, "set_conv_tile: plan is used by a batch");
+  p->conv_tile = records;
+  p->conv_tile_set = records != 0;
+  if (!p->dtd || p->dtd->var || p->precision != SBIEM_FP32CONV) return SBIEM_OK;
+  const int tile = records ? records : (p->closure_on ? kTileSlots32s : kTileSlots32);
+  if (tile == p->dtd->tile_slots) return SBIEM_OK;
+  if (int st = retile(p, tile)) return st;
+  if (p->dyn) p->dyn->primed = false;
+  return SBIEM_OK;
+}
+
+int sbiem_get_conv_tile(const sbiem_plan* p, int* records) {
+  if (!p || !records) return fail_global(SBIEM_EINVAL, "get_conv_tile: NULL argument");
+  if (p->dtd && !p->dtd->var && p->precision == SBIEM_FP32CONV) *records = p->dtd->tile_slots;
+  else if (p->precision == SBIEM_FP32CONV)
+    *records = p->conv_tile ? p->conv_tile : (p->closure_on ? kTileSlots32s : kTileSlots32);
+  else
+    *records = kTileSlots64;
   return SBIEM_OK;
 }
 

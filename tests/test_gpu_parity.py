@@ -56,8 +56,11 @@ def test_stress_fp64_matches_oracle(N, nt):
     assert rel(tau, rt) < 1e-10 and rel(sig, rs) < 1e-10, (rel(tau, rt), rel(sig, rs))
 
 
-@pytest.mark.parametrize("N,nt", [(1024, 300), (512, 1100)])
-def test_stress_fp32_matches_oracle(N, nt):
+@pytest.mark.parametrize("N,nt,tile", [(1024, 300, 0), (512, 1100, 0), (1024, 1500, 256),
+                                        (1024, 1500, 1024)])
+def test_stress_fp32_matches_oracle(N, nt, tile):
+    """FP32 stress path against the oracle; the last two cases put windows of
+    up to 2048 records through tiles of 256 and 1024 records."""
     from oracle.spectral import curvature
     from oracle.stress import stress_from_history
     from oracle.windows import midpoint_weights
@@ -68,6 +71,7 @@ def test_stress_fp32_matches_oracle(N, nt):
     hist = _history(N, nt, seed=nt)
     p = pkg.Plan(N, L, MU, NU, CS, CP, h)
     p.set_precision(pkg.SBIEM_FP32CONV)
+    p.set_conv_tile(tile)
     tau, sig = p.stress(hist, dt)
     w = midpoint_weights(N, L, CS, CP, dt)
     rt, rs = stress_from_history(hist, dt, L, MU, CS, CP, curvature(h, L), w)
@@ -325,15 +329,18 @@ def test_batch_of_full_size_faults_matches_individual_plans_bitwise():
 
 
 def test_tuned_runs_equal_untuned_runs_bitwise():
-    """Autotuning replays ordinary steps with several convolution grids;
-    results do not depend on the grid, so a tuned plan ends where an untuned
-    one run for the same number of steps does (plans and batches)."""
+    """Autotuning replays ordinary steps with several convolution grids and
+    launch orders; with the tile fixed (sbiem_set_conv_tile) results do not
+    depend on them, so a tuned plan ends where an untuned one run for the
+    same number of steps does (plans and batches)."""
     pkg = _pkg()
     sc = Scenario(512, 10e3, 0.5 * (10e3 / 512) / CS, rough_10km(512, seed=6), theta_mode="exp",
                   spec=FrictionSpec(overstress=8e6), consistent_V0=True)
     a = make_plan(sc, pkg.SBIEM_FP32CONV)
     b = make_plan(sc, pkg.SBIEM_FP32CONV)
+    a.set_conv_tile(512)
     grid = a.tune(sc.dt, 16)
+    assert a.conv_tile() == 512
     assert grid >= 1
     a.run(sc.dt, 37)
     done = a.steps_done()
@@ -344,8 +351,10 @@ def test_tuned_runs_equal_untuned_runs_bitwise():
         assert np.array_equal(ga[k], gb[k]), k
     # a batch of two faults against its members stepped alone
     p1, p2 = make_plan(sc, pkg.SBIEM_FP32CONV), make_plan(sc, pkg.SBIEM_FP32CONV)
+    p1.set_conv_tile(512)
     bt = pkg.Batch([p1, p2])
     bt.tune(16)
+    assert p1.conv_tile() == p2.conv_tile() == 512
     n = p1.steps_done()
     assert n == p2.steps_done() > 0
     q = make_plan(sc, pkg.SBIEM_FP32CONV)
@@ -353,6 +362,48 @@ def test_tuned_runs_equal_untuned_runs_bitwise():
     g1, gq = p1.get_state(), q.get_state()
     for k in ("slip", "V", "theta", "tau_el", "sigma_el"):
         assert np.array_equal(g1[k], gq[k]), k
+
+
+def test_tuning_over_tile_shapes():
+    """Automatic tuning also tries the 256-, 512- and 1024-record tiles: the
+    plan and the batch keep one of them, and a run on the chosen tile stays
+    within the FP32 tolerance of untuned runs (a tile only reorders the FP32
+    history sums); a plan set to the chosen tile reproduces the steps after
+    tuning bit for bit."""
+    pkg = _pkg()
+    sc = Scenario(1024, 10e3, 0.5 * (10e3 / 1024) / CS, rough_10km(1024, seed=7), theta_mode="exp",
+                  spec=FrictionSpec(overstress=1e6), consistent_V0=True)
+    a = make_plan(sc, pkg.SBIEM_FP32CONV)
+    a.tune(sc.dt, 16)
+    tile = a.conv_tile()
+    assert tile in (256, 512, 1024)
+    n = a.steps_done()
+    b = make_plan(sc, pkg.SBIEM_FP32CONV)
+    b.run(sc.dt, n)
+    a.run(sc.dt, 40)
+    b.run(sc.dt, 40)
+    ga, gb = a.get_state(), b.get_state()
+    print("tuned tile", tile, "after", n, "tuning steps; tau difference", rel(ga["tau_el"], gb["tau_el"]))
+    assert rel(ga["tau_el"], gb["tau_el"]) < 1e-5 and rel(ga["sigma_el"], gb["sigma_el"]) < 1e-5
+    # the same tile from the start, then the same steps: bit for bit equal
+    c, d = make_plan(sc, pkg.SBIEM_FP32CONV), make_plan(sc, pkg.SBIEM_FP32CONV)
+    c.set_conv_tile(tile)
+    d.set_conv_tile(tile)
+    c.run(sc.dt, 25)
+    d.run(sc.dt, 10)
+    d.run(sc.dt, 15)
+    gc, gd = c.get_state(), d.get_state()
+    for k in ("slip", "V", "tau_el", "sigma_el"):
+        assert np.array_equal(gc[k], gd[k]), k
+    # a batch of two faults
+    p1, p2 = make_plan(sc, pkg.SBIEM_FP32CONV), make_plan(sc, pkg.SBIEM_FP32CONV)
+    bt = pkg.Batch([p1, p2])
+    bt.tune(16)
+    assert p1.conv_tile() == p2.conv_tile() in (256, 512, 1024)
+    bt.run(20)
+    g1, g2 = p1.get_state(), p2.get_state()
+    for k in ("slip", "V", "tau_el", "sigma_el"):
+        assert np.array_equal(g1[k], g2[k]), k
 
 
 # ---------------------------------------------------------------- edge cases
