@@ -85,7 +85,7 @@ class Form:
     """The faults of a workload in one form (plain, or closed by networks),
     stepped together on one stream."""
 
-    def __init__(self, pkg, name, stream, nets=None):
+    def __init__(self, pkg, name, stream, nets=None, tile=0):
         self.members = members_of(name)
         self.plans = []
         for m in self.members:
@@ -93,6 +93,8 @@ class Form:
             p.set_stream(stream)
             if nets is not None:
                 p.set_closure(nets[0], nets[1], 0.25)
+            if tile:
+                p.set_conv_tile(tile)
             self.plans.append(p)
         self.batch = pkg.Batch(self.plans) if len(self.plans) > 1 else None
         self.dt = self.members[0].dt
@@ -150,25 +152,31 @@ def time_form(form, steps, warmup, tune=True):
     out["conv_ms"] = ms / max(n, 1)
     out["conv_launches"] = n
     out["conv_bytes"] = nbytes
+    out["conv_tile"] = form.plans[0].conv_tile()
     return out
+
+
+CONV32_SHAPES = {256: "k_conv32<4,4>", 512: "k_conv32<8,2>", 1024: "k_conv32<16,1>"}
 
 
 def roofline(m, workload, closure, fp64):
     achieved = m["conv_bytes"] / (m["conv_ms"] * 1e-3) / 1e9
+    tile = m.get("conv_tile")
     return {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": traffic_from_profiles(workload, closure, m["conv_bytes"]),
-        "kernel": "k_conv64" if fp64 else ("k_conv32<4,4>" if closure else "k_conv32<8,2>"),
-        "conv_workgroups": m.get("conv_workgroups"), "bytes_per_launch": m["conv_bytes"],
+        "traffic": traffic_from_profiles(workload, closure, m["conv_bytes"], tile),
+        "kernel": "k_conv64" if fp64 else CONV32_SHAPES.get(tile, "k_conv32"),
+        "conv_tile": tile, "conv_workgroups": m.get("conv_workgroups"),
+        "bytes_per_launch": m["conv_bytes"],
         "avg_launch_us": round(m["conv_ms"] * 1e3, 3), "launches": m["conv_launches"],
     }
 
 
-def traffic_from_profiles(workload: str, closure: bool, alg_bytes: float):
+def traffic_from_profiles(workload: str, closure: bool, alg_bytes: float, tile=None):
     """HBM bytes per conv launch from committed rocprofv3 counter summaries,
     if they were taken on the current kernel source and on this very launch
-    (same workload, same form, same algorithmic bytes)."""
+    (same workload, same form, same tile, same algorithmic bytes)."""
     tag = workload + ("-closure" if closure else "")
     path = os.path.join(ROOT, "profiles", f"conv_traffic_{tag}.json")
     if not os.path.exists(path):
@@ -178,6 +186,8 @@ def traffic_from_profiles(workload: str, closure: bool, alg_bytes: float):
     if z.get("kernel_sha256_16") != kernel_hash():
         return None
     if z.get("algorithmic_bytes_per_launch") != alg_bytes:
+        return None
+    if tile is not None and z.get("conv_tile") != tile:
         return None
     return z.get("bytes_per_launch")
 
@@ -426,6 +436,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the closure's accuracy run through a rupture")
+    ap.add_argument("--conv-tile", type=int, default=0, choices=(0, 256, 512, 1024),
+                    help="fix the FP32 conv tile (records); 0: autotuned with the grid")
     ap.add_argument("--cycle-years", type=float, default=35.0,
                     help="simulated years of the sinusoidal-fault cycle measured beside the "
                          "fixed-step forms (0: skip)")
@@ -464,7 +476,8 @@ def main():
     results = {}
     for f in forms:
         log(f"building the {f} form of {args.workload}")
-        form = Form(pkg, args.workload, stream, nets[:2] if f == "closure" else None)
+        form = Form(pkg, args.workload, stream, nets[:2] if f == "closure" else None,
+                    tile=args.conv_tile)
         log(f"timing the {f} form")
         results[f] = time_form(form, args.steps, args.warmup, tune=not args.no_tune)
         results[f]["n_total"] = form.n_total

@@ -42,6 +42,12 @@ def test_traffic_only_for_the_profiled_launch(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "kernel_hash", lambda: "abc")
     _profile(tmp_path, "rough-N65536-closure", "abc", 132453280.0, 140000000)
     assert bench.traffic_from_profiles("rough-N65536", True, 132453280.0) == 140000000
+    # counters taken on one conv tile do not stand for a run on another
+    (tmp_path / "profiles" / "conv_traffic_rough-N65536.json").write_text(json.dumps(
+        {"kernel_sha256_16": "abc", "algorithmic_bytes_per_launch": 5.0,
+         "bytes_per_launch": 6, "conv_tile": 512}))
+    assert bench.traffic_from_profiles("rough-N65536", False, 5.0, 512) == 6
+    assert bench.traffic_from_profiles("rough-N65536", False, 5.0, 1024) is None
 
 
 def test_committed_traffic_profiles_match_their_algorithmic_bytes():
