@@ -402,7 +402,10 @@ int sbiem_tune(sbiem_plan* p, double dt, int64_t steps_per_trial, int32_t* conv_
 /* FP32 convolution tile: records = 256, 512 or 1024 ring records per
  * wavefront tile (16 rows of 64 records in flight per wave either way, so a
  * workgroup task stays 8192 records), or 0 for the default by window length
- * (512; 256 under the learned closure, whose kept windows are short).  A
+ * (512; 256 under the learned closure, whose kept windows are short).
+ * records = 64 selects packed rows: every 64-record row of every mode in
+ * order, 16 to a wave and 128 to a task, so no row lies past a mode's end
+ * (sbiem_tune does not try it: slower on every workload measured).  A
  * non-zero tile is kept by sbiem_tune.  The tiling is the summation order
  * of the FP32 history sums, so runs on different tiles agree to FP32
  * rounding, runs on one tile bit for bit.  Applies to FP32 fixed-step plans

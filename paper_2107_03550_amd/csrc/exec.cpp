@@ -55,6 +55,7 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
   ex->nfaults = (int)plans.size();
   ex->host_faults = descs;
   std::vector<Tile> tiles;
+  std::vector<RowDesc> rows;   // packed FP32 layout: what the conv reads instead of tiles
   std::vector<ConvTask> tasks;
   std::vector<int2> mmap, emap;
   std::vector<ClosureMode> cmodes;
@@ -87,7 +88,23 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
       t.rec = (const char*)d->ring + (size_t)t.ring_off * rec_bytes;
       tiles.push_back(t);
     }
-    for (ConvTask k : d->tasks) tasks.push_back(ConvTask{k.t0 + base, k.t1 + base});
+    if (d->tile_slots == kTileSlots32p && precision == SBIEM_FP32CONV && !d->var)
+      for (size_t i = 0; i < d->tiles.size(); ++i) {
+        const Tile& t = d->tiles[i];
+        const int2 m = d->row_meta[i];
+        RowDesc r;
+        r.rec = (const char*)d->ring + ((size_t)t.ring_off + (size_t)t.p0) * rec_bytes;
+        r.word = (unsigned)t.len | (unsigned)(m.x + 1) << 8 | (unsigned)m.y << 16;
+        r.p0 = t.p0;
+        r.Rn = t.Rn;
+        r.MT = t.MT;
+        r.MN = t.MN;
+        r.part = t.part;
+        r.th = t.th;
+        r.rmagic = t.rmagic;
+        rows.push_back(r);
+      }
+    for (ConvTask k : d->tasks) tasks.push_back(ConvTask{k.t0 + base, k.t1 + base, f, k.nsum});
     // algorithmic bytes: ring records of lags 2..M_n-1 read, one history sum
     // (2 complex FP64) written per mode
     // (variable-step engine: every slot of R_n, plus the interval log, once
@@ -133,6 +150,13 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
       }
     }
   }
+  if (!rows.empty())
+    for (size_t k = 0; k < tasks.size(); ++k)
+      if (tasks[k].t0 != (int)k * kTaskRows || tasks[k].t1 != tasks[k].t0 + kTaskRows) {
+        *err = "packed conv rows: every task must hold 128 rows in order";
+        delete ex;
+        return SBIEM_EINVAL;
+      }
   ex->ntiles = (int)tiles.size();
   ex->ntasks = (int)tasks.size();
   ex->mode_blocks = (int)mmap.size();
@@ -168,7 +192,10 @@ int build_exec(const std::vector<sbiem_plan*>& plans, const std::vector<DtData*>
   }
   hipError_t e = hipMemcpy(ex->d_faults, ex->host_faults.data(), sizeof(FaultDev) * ex->nfaults,
                            hipMemcpyHostToDevice);
-  if (!e && ex->ntiles)
+  static_assert(sizeof(RowDesc) <= sizeof(Tile), "packed rows fit the tile buffer");
+  if (!e && ex->ntiles && !rows.empty())
+    e = hipMemcpy(ex->d_tiles, rows.data(), sizeof(RowDesc) * rows.size(), hipMemcpyHostToDevice);
+  else if (!e && ex->ntiles)
     e = hipMemcpy(ex->d_tiles, tiles.data(), sizeof(Tile) * ex->ntiles, hipMemcpyHostToDevice);
   if (!e && ex->ntasks)
     e = hipMemcpy(ex->d_tasks, tasks.data(), sizeof(ConvTask) * ex->ntasks, hipMemcpyHostToDevice);
@@ -770,6 +797,8 @@ std::vector<int> tile_candidates(const std::vector<sbiem_plan*>& plans) {
   if (d->var || plans[0]->precision != SBIEM_FP32CONV) return c;
   for (const sbiem_plan* p : plans)
     if (p->conv_tile_set) return c;
+  // (packed rows, kTileSlots32p, only when set: slower on every workload
+  // measured, their per-row descriptors costing more than they save)
   for (int t : {kTileSlots32, kTileSlots32s, kTileSlots32l})
     if (t != c[0]) c.push_back(t);
   return c;

@@ -125,7 +125,7 @@ struct Tile {
   long long ring_off;
   double th;       // FP32 weights: c_s |k_n| dt / 2 / table spacing
   const void* rec; // the mode's first ring record (set per execution context)
-  long long pad2;
+  unsigned long long rmagic;  // floor((2^64 - 1) / Rn) + 1: a mod Rn for 32-bit a by multiplication
 };
 
 // A conv task: tiles [t0, t1) of one fault, handled by one workgroup.  A task
@@ -134,6 +134,8 @@ struct Tile {
 // mode's pieces in order.
 struct ConvTask {
   int t0, t1;
+  int fault;       // the fault its tiles belong to (index into the launch's faults)
+  int nsum;        // packed rows: the task's wave sums (LDS slots); else 0
 };
 constexpr int kConvThreads = 512;   // 8 wavefronts
 constexpr int kTileSlots32 = 512;   // FP32 records per wavefront tile
@@ -148,6 +150,27 @@ constexpr int kTaskTiles32s = kWaveTiles32s * (kConvThreads / 64);
 // FP32 tile shapes the conv can take (records per tile; 16 rows in flight per
 // wave, so every task is 8192 records): 256 (short windows), 512, 1024
 constexpr int kTileSlots32l = 1024;
+// The packed FP32 layout: one 64-record row per unit, the rows of one mode
+// and of consecutive modes filling each wave's 16 rows (no row past a mode's
+// end); a task is 128 rows, whatever the modes.
+constexpr int kTileSlots32p = 64;
+constexpr int kConvStaticLds = 6144;  // bound on the FP32 conv's static LDS (task sums)
+constexpr int kPackRows = 16;                               // rows per wave and task
+constexpr int kTaskRows = kPackRows * (kConvThreads / 64);  // rows per task
+// A packed row as the conv reads it (48 B: a wave's 16 rows are 768 B, three
+// words per lane).  word = len | (flush slot + 1) << 8 | run << 16: the row's
+// records, the task's LDS slot of the wave sum that ends at this row (0:
+// none), and at the first slot of a partial sum the number of its slots.
+struct RowDesc {
+  const void* rec;            // the row's first record
+  unsigned word;
+  int p0;                     // mode-local slot of that record
+  int Rn, MT, MN;
+  int part;
+  double th;
+  unsigned long long rmagic;
+};
+static_assert(sizeof(RowDesc) == 48, "packed row descriptor");
 constexpr int kTileSlots64 = 256;   // FP64 records per wavefront tile
 constexpr int kTaskTiles64 = 16;
 constexpr int kTaskTiles = kTaskTiles32s > kTaskTiles64 ? kTaskTiles32s : kTaskTiles64;  // at most
@@ -231,8 +254,9 @@ struct DtData {
   std::vector<int> Rn;           // ring capacity
   std::vector<long long> ring_off;
   long long ring_slots = 0;
-  std::vector<Tile> tiles;       // this fault's tiles (fault field = 0)
-  int tile_slots = 0;            // records per tile
+  std::vector<Tile> tiles;       // this fault's tiles (fault field = 0); packed: its rows
+  std::vector<int2> row_meta;    // packed rows: (flush slot or -1, run length)
+  int tile_slots = 0;            // records per tile (kTileSlots32p: packed rows)
   std::vector<ConvTask> tasks;   // this fault's tasks (tile indices local)
   std::vector<int> part0, nparts;
   int parts_cap = 0;             // partial sums the parts buffer holds

@@ -19,6 +19,8 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <cstdint>
+#include <utility>
 
 #include <hip/hip_runtime.h>
 
@@ -141,22 +143,22 @@ template <> struct Prec<double> {
 // ---------------------------------------------------------------------------
 // Wavefront sum without LDS traffic: DPP exchanges inside each row of 16
 // lanes (quad swaps, then half-row and row mirrors leave every lane with its
-// row's sum), then the four row sums read from lanes 0, 16, 32, 48.  The
-// result is uniform and its summation order fixed.
-template <int C>
+// row's sum), then row broadcasts: lane 15 of rows 0 and 2 is added into
+// rows 1 and 3, lane 31 into rows 2 and 3, and lane 63 holds
+// (r2 + r3) + (r0 + r1).  The result is uniform and its summation order
+// fixed.  Rows outside a broadcast's row mask add the zero of `old`.
+template <int C, int RowMask = 0xF>
 __device__ __forceinline__ float dpp_mov(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), C, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), C, RowMask, 0xF, false));
 }
 __device__ __forceinline__ float wave_sum(float v) {
-  v += dpp_mov<0xB1>(v);   // quad_perm [1, 0, 3, 2]
-  v += dpp_mov<0x4E>(v);   // quad_perm [2, 3, 0, 1]
-  v += dpp_mov<0x141>(v);  // row_half_mirror
-  v += dpp_mov<0x140>(v);  // row_mirror
-  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
-  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
-  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
-  return (r0 + r1) + (r2 + r3);
+  v += dpp_mov<0xB1>(v);        // quad_perm [1, 0, 3, 2]
+  v += dpp_mov<0x4E>(v);        // quad_perm [2, 3, 0, 1]
+  v += dpp_mov<0x141>(v);       // row_half_mirror
+  v += dpp_mov<0x140>(v);       // row_mirror
+  v += dpp_mov<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_mov<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 __device__ __forceinline__ float4 wave_reduce4(float4 v) {
   return make_float4(wave_sum(v.x), wave_sum(v.y), wave_sum(v.z), wave_sum(v.w));
@@ -194,6 +196,24 @@ __device__ __forceinline__ int ring_phase(long long step, int Rn) {
   return r == 0 ? 0 : Rn - r;
 }
 
+// a mod d for 32-bit a by multiplication with M = floor((2^64 - 1) / d) + 1
+// (Lemire, Kaser and Kurz, "Faster remainder by direct computation", 2019):
+// the high 64 bits of the 96-bit product (M a mod 2^64) d.  Every operand is
+// uniform in the FP32 conv, so this runs on the scalar unit.
+__device__ __forceinline__ unsigned fastmod_u32(unsigned a, unsigned long long M, unsigned d) {
+  const unsigned long long low = M * a;
+  const unsigned lo = (unsigned)low, hi = (unsigned)(low >> 32);
+  const unsigned long long t = (unsigned long long)hi * d + __umulhi(lo, d);
+  return (unsigned)(t >> 32);
+}
+// ring_phase with the multiplier of R (steps beyond 2^32 take the FP64 path)
+__device__ __forceinline__ int ring_phase_m(long long step, int Rn, unsigned long long M) {
+  const long long b = step - 1;
+  if (b < 0) return 1 % Rn;
+  const int r = b < (1LL << 32) ? (int)fastmod_u32((unsigned)b, M, (unsigned)Rn) : mod_pos(b, Rn);
+  return r == 0 ? 0 : Rn - r;
+}
+
 // One workgroup per task (a run of tiles of one fault): each wave sums tiles
 // of the task, the per-tile FP64 partials go to LDS, and after a barrier the
 // first thread of each (task, mode) run adds its tiles in order and stores
@@ -204,7 +224,7 @@ struct TaskLds {
   int id[kTaskTiles];
 };
 
-__device__ __forceinline__ void finish_task(const FaultDev& fd, const TaskLds& L, int nt) {
+__device__ __forceinline__ void finish_task(double4* parts, const TaskLds& L, int nt) {
   const int k = threadIdx.x;
   if (k < nt && (k == 0 || L.id[k - 1] != L.id[k])) {
     double4 a = L.part[k];
@@ -220,8 +240,11 @@ __device__ __forceinline__ void finish_task(const FaultDev& fd, const TaskLds& L
     typedef double d4v __attribute__((ext_vector_type(4)));
     typedef __attribute__((address_space(1))) d4v* gd4p;
     const d4v v = {a.x, a.y, a.z, a.w};
-    ((gd4p)(d4v*)fd.parts)[L.id[k]] = v;
+    ((gd4p)(d4v*)parts)[L.id[k]] = v;
   }
+}
+__device__ __forceinline__ void finish_task(const FaultDev& fd, const TaskLds& L, int nt) {
+  finish_task(fd.parts, L, nt);
 }
 
 __global__ void __launch_bounds__(kConvThreads)
@@ -297,6 +320,15 @@ k_conv64(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
 // learned closure).  The records of the next task's tiles are requested as
 // soon as the registers of the current tile are free, so loads stay in
 // flight across the weighting, the wave reductions and the task's barriers.
+//
+// Everything a task needs besides its records (its tile descriptors, its
+// fault's step counter, failure flag and output pointer) is requested one
+// task ahead as well: the descriptors stream from HBM once per step, and a
+// scalar load's result cannot be awaited apart from other scalar loads, so
+// a descriptor fetched right before its records' loads would stall the wave
+// for a full memory round trip once per tile.  The K descriptors of a wave's
+// next tiles are fetched together after its first tile is weighed (one round
+// trip per task), the next task's indices at the end of the task before.
 
 // Per-fault words that a launch only reads (failure flag, step counter) are
 // read with scalar loads: the vector-memory counter then tracks record loads
@@ -309,36 +341,65 @@ __device__ __forceinline__ long long read_word(const long long* p) {
 }
 
 // The ring is streamed once per step: non-temporal loads keep it from
-// displacing the tables and spectra other launches reuse.  Records are read
-// through a global-segment pointer (global loads wait on
-// the vector-memory counter only, so LDS reads of the table never wait for
-// records still in flight).  Lanes past the tile's end re-read its last
-// record (same cache line, no extra traffic); their weight is zero.  A wave
-// without a tile still issues its loads, from the first nodes of the table
-// (cached, never weighed): every pass of the task loop then issues the same
-// number of loads, so the wait for a tile's records counts exactly the loads
-// issued after them and never drains the next task's loads.
+// displacing the tables and spectra other launches reuse.  A tile's records
+// are read through a buffer resource that spans exactly its len records:
+// lanes past the tile's end (and every lane of a wave without a tile, whose
+// range is empty) fall outside the range check, read 0 and touch no memory,
+// while every pass of the task loop still issues the same number of loads,
+// so the wait for a tile's records counts exactly the loads issued after
+// them and never drains the next task's loads.  Buffer loads wait on the
+// vector-memory counter only, so LDS reads of the table never wait for
+// records still in flight.
 typedef float f4v __attribute__((ext_vector_type(4)));
-typedef const __attribute__((address_space(1))) f4v* gf4p;
+constexpr int kBufferWord3 = 0x00020000;  // raw 32-bit buffer, gfx9 family
+constexpr int kLoadNT = 2;                // non-temporal cache policy
+
+// The fields of a tile the FP32 conv keeps in scalar registers: those that
+// address its records, fetched first, and those that weigh them.
+struct TileR {
+  const void* rec;
+  int p0, len;
+  int Rn, part, MT, MN;
+  double th;
+  unsigned long long rmagic;
+};
+__device__ __forceinline__ void tile_address(TileR& r, const Tile* tp) {
+  r.rec = tp->rec;
+  r.p0 = tp->p0;
+  r.len = tp->len;
+}
+__device__ __forceinline__ void tile_weights(TileR& r, const Tile* tp) {
+  r.Rn = tp->Rn;
+  r.part = tp->part;
+  r.MT = tp->MT;
+  r.MN = tp->MN;
+  r.th = tp->th;
+  r.rmagic = tp->rmagic;
+}
+
 template <int U>
-__device__ __forceinline__ void conv32_load(const Tile& tl, bool has, int lane, const float4* dummy,
-                                            float4 (&h)[U]) {
-  const gf4p rec = has ? (gf4p)(const float4*)tl.rec + tl.p0 : (gf4p)dummy;
-  const int last = has ? tl.len - 1 : 3;
+__device__ __forceinline__ void conv32_load(const TileR& tl, bool has, int lane, float4 (&h)[U]) {
+  const float4* base = (const float4*)tl.rec + (has ? tl.p0 : 0);
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)base, 0, has ? tl.len * 16 : 0, kBufferWord3);
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const f4v t = __builtin_nontemporal_load(rec + min(lane + 64 * u, last));
+    // the whole offset stays in the address register (not the instruction's
+    // offset field), where the range check certainly applies
+    int off = (lane + 64 * u) * 16;
+    asm volatile("" : "+v"(off));
+    const f4v t = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kLoadNT));
     h[u] = make_float4(t.x, t.y, t.z, t.w);
   }
 }
 
 template <int U>
-__device__ __forceinline__ float4 conv32_weigh(const Tile& tl, long long step, int lane,
+__device__ __forceinline__ float4 conv32_weigh(const TileR& tl, long long step, int lane,
                                                const float4 (&h)[U], const float4* tab,
                                                int table_len) {
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
   const int Rn = tl.Rn;
-  const int o = ring_phase(step, Rn);
+  const int o = ring_phase_m(step, Rn, tl.rmagic);
   const double th = tl.th;
   const int end = tl.p0 + tl.len;
 #pragma unroll
@@ -395,18 +456,32 @@ k_conv32(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
   int task = blockIdx.x;
   int nxt = blockIdx.x + gridDim.x;
   const int dyn0 = 2 * gridDim.x;
-  ConvTask tk = task < ntasks ? tasks[task] : ConvTask{0, 0};
+  const ConvTask none{0, 0, 0, 0};
+  ConvTask tk = task < ntasks ? tasks[task] : none;
+  ConvTask nk = nxt < ntasks ? tasks[nxt] : none;
   static_assert(U * K == 16, "16 rows in flight per wave");
-  Tile t[K];
+  TileR t[K];
   bool has[K];
   float4 h[K][U];
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     has[i] = task < ntasks && wave + wpb * i < tk.t1 - tk.t0;
-    t[i] = has[i] ? tiles[tk.t0 + wave + wpb * i] : Tile{};
+    const Tile* tp = tiles + (has[i] ? tk.t0 + wave + wpb * i : 0);
+    tile_address(t[i], tp);
+    tile_weights(t[i], tp);
 #pragma unroll
     for (int u = 0; u < U; ++u) h[i][u] = make_float4(0.f, 0.f, 0.f, 0.f);
-    conv32_load(t[i], has[i], lane, table, h[i]);
+    conv32_load(t[i], has[i], lane, h[i]);
+  }
+  // the current task's fault words
+  int err = 0;
+  long long step = 0;
+  double4* parts = nullptr;
+  if (task < ntasks) {
+    const FaultDev& fd = faults[tk.fault];
+    err = read_word(fd.err);
+    step = read_word(fd.step) + ahead;
+    parts = fd.parts;
   }
   // the table is staged while the first records are in flight
   for (int i = threadIdx.x; i < table_len; i += kConvThreads) tab[i] = table[i];
@@ -416,19 +491,35 @@ k_conv32(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
     int got = 0;
     if (threadIdx.x == 0 && more) got = atomicAdd(ctr, 1);  // used after the tiles are weighed
     const int nt = tk.t1 - tk.t0;
-    const FaultDev& fd = faults[tiles[tk.t0].fault];
-    const int err = read_word(fd.err);
-    const long long step = read_word(fd.step) + ahead;
-    const ConvTask nk = more ? tasks[nxt] : ConvTask{0, 0};
+    TileR un[K];
+    int nidx[K];
+    bool nh[K];
+    int nerr;
+    long long nstep;
+    double4* nparts;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       // weigh tile i, then reuse its registers for the next task's tile i
       float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
       if (has[i] && !err) acc = conv32_weigh(t[i], step, lane, h[i], tab, table_len);
       __builtin_amdgcn_sched_barrier(0);
-      const bool nh = more && wave + wpb * i < nk.t1 - nk.t0;
-      const Tile u = nh ? tiles[nk.t0 + wave + wpb * i] : Tile{};
-      conv32_load(u, nh, lane, table, h[i]);
+      if (i == 0) {
+        // the addressing fields of the next task's tiles, all requested
+        // before the first wait (a wave without a next tile reads tile 0
+        // and never uses it); their weighing fields follow after the last
+        // tile of this task, when this task's have been used
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          nh[j] = more && wave + wpb * j < nk.t1 - nk.t0;
+          nidx[j] = nh[j] ? nk.t0 + wave + wpb * j : 0;
+          tile_address(un[j], tiles + nidx[j]);
+        }
+        const FaultDev& nfd = faults[more ? nk.fault : tk.fault];
+        nerr = read_word(nfd.err);
+        nstep = read_word(nfd.step) + ahead;
+        nparts = nfd.parts;
+      }
+      conv32_load(un[i], nh[i], lane, h[i]);
       if (has[i]) {
         acc = wave_reduce4(acc);
         if (lane == 0) {
@@ -436,17 +527,229 @@ k_conv32(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
           L.id[wave + wpb * i] = t[i].part;
         }
       }
-      t[i] = u;
-      has[i] = nh;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      t[i] = un[i];
+      tile_weights(t[i], tiles + nidx[i]);
+      has[i] = nh[i];
     }
     if (threadIdx.x == 0) s_next = more ? dyn0 + got : ntasks;  // written and read between the two barriers
     __syncthreads();
-    finish_task(fd, L, nt);
     const int after_all = __builtin_amdgcn_readfirstlane(s_next);
+    const ConvTask nnk = after_all < ntasks ? tasks[after_all] : none;
+    finish_task(parts, L, nt);
     __syncthreads();
     task = nxt;
     nxt = after_all;
     tk = nk;
+    nk = nnk;
+    err = nerr;
+    step = nstep;
+    parts = nparts;
+  }
+}
+
+// Packed rows.  Each wave weighs 16 rows of 64 records per task, the rows of
+// one mode and then of the next ones, so no row lies past a mode's end.  A
+// row's parameters come with it (RowDesc); a wave's 16 descriptors (768 B)
+// are held in three registers, three words per lane, and read out with
+// lane reads.  They are requested two tasks ahead, before the records of the
+// task in between: in-order completion of vector loads then makes every wait
+// for them free, and they never drain records in flight.  Tasks are taken in
+// grid order (all tasks have 128 rows, so none is longer than another).
+//
+// The running wave sum of a partial sum (task, mode) is reduced at the last
+// row of the partial sum in the wave and at the wave's last row, into the LDS
+// slot the host assigned (slots count the task's wave sums in row order);
+// after the barrier the first slot of each run adds its run in order, so every
+// sum has a fixed order.
+struct PackLds {
+  double4 part[kTaskRows];
+  int2 meta[kTaskRows];   // (partial sum, run length at a run's first slot)
+};
+static_assert(sizeof(PackLds) + 64 <= kConvStaticLds && sizeof(TaskLds) + 64 <= kConvStaticLds,
+              "static LDS of the FP32 conv kernels");
+
+struct RowBlock {
+  int a, b, c;            // words 3 lane, 3 lane + 1, 3 lane + 2 of the wave's rows
+};
+__device__ __forceinline__ RowBlock load_rows(const RowDesc* rows, int task, int ntasks, int wave,
+                                              int lane) {
+  const int t = task < ntasks ? task : 0;   // past the last task: never used
+  const int* w = (const int*)(rows + (size_t)t * kTaskRows + kPackRows * wave) + 3 * lane;
+  return RowBlock{w[0], w[1], w[2]};
+}
+// word F of row U of a block
+template <int U, int F>
+__device__ __forceinline__ unsigned row_word(const RowBlock& b) {
+  static_assert(U < kPackRows && F < 12, "row descriptor word");
+  const int v = F % 3 == 0 ? b.a : (F % 3 == 1 ? b.b : b.c);
+  return (unsigned)__builtin_amdgcn_readlane(v, 4 * U + F / 3);
+}
+template <int U>
+__device__ __forceinline__ void row_load(const RowBlock& b, bool live, int lane, float4& h) {
+  const unsigned long long rec =
+      (unsigned long long)row_word<U, 1>(b) << 32 | (unsigned long long)row_word<U, 0>(b);
+  const int len = (int)(row_word<U, 2>(b) & 0xFFu);
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(uintptr_t)rec, 0, live ? len * 16 : 0, kBufferWord3);
+  int off = lane * 16;
+  asm volatile("" : "+v"(off));
+  const f4v t = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kLoadNT));
+  h = make_float4(t.x, t.y, t.z, t.w);
+}
+
+// The weights of one row's records (lane: record p0 + lane of the mode's
+// ring), added to acc; as in conv32_weigh.
+template <int U>
+__device__ __forceinline__ float4 row_weigh(const RowBlock& b, long long step, int lane,
+                                            const float4& hv, const float4* tab, int table_len,
+                                            float4 acc) {
+  const int len = (int)(row_word<U, 2>(b) & 0xFFu);
+  const int p0 = (int)row_word<U, 3>(b);
+  const int Rn = (int)row_word<U, 4>(b);
+  const int MT = (int)row_word<U, 5>(b);
+  const int MN = (int)row_word<U, 6>(b);
+  const double th = __builtin_bit_cast(
+      double, (unsigned long long)row_word<U, 9>(b) << 32 | (unsigned long long)row_word<U, 8>(b));
+  const unsigned long long M =
+      (unsigned long long)row_word<U, 11>(b) << 32 | (unsigned long long)row_word<U, 10>(b);
+  const int o = ring_phase_m(step, Rn, M);
+  const int p = p0 + lane;
+  int q = p + o;
+  q -= (q >= Rn) ? Rn : 0;
+  const int j = Rn - q + 1;                         // lag (q = 0: skipped slot)
+  const double x = (double)(2 * j + 1) * th;
+  // lanes past the row's end (weight 0) may have j <= 0: keep their node in the table
+  const int i = min(max((int)x, 0), table_len - 2);
+  const float f = (float)(x - (double)i);
+  const float4 n0 = tab[i], n1 = tab[i + 1];
+  const float f2 = f * f, f3 = f2 * f;
+  const float h00 = 2.f * f3 - 3.f * f2 + 1.f;
+  const float h10 = f3 - 2.f * f2 + f;
+  const float h01 = 3.f * f2 - 2.f * f3;
+  const float h11 = f3 - f2;
+  float wT = h00 * n0.x + h10 * n0.y + h01 * n1.x + h11 * n1.y;
+  float wN = h00 * n0.z + h10 * n0.w + h01 * n1.z + h11 * n1.w;
+  const bool use = (q != 0) && (lane < len);
+  wT = (use && j < MT) ? wT : 0.f;
+  wN = (use && j < MN) ? wN : 0.f;
+  acc.x = fmaf(wT, hv.x, acc.x);
+  acc.y = fmaf(wT, hv.y, acc.y);
+  acc.z = fmaf(wN, hv.z, acc.z);
+  acc.w = fmaf(wN, hv.w, acc.w);
+  return acc;
+}
+
+__device__ __forceinline__ void finish_packed(double4* parts, const PackLds& L, int nsum) {
+  const int k = threadIdx.x;
+  if (k < nsum) {
+    const int2 m = L.meta[k];
+    if (m.y > 0) {
+      double4 a = L.part[k];
+      for (int j = 1; j < m.y; ++j) {
+        const double4 b = L.part[k + j];
+        a.x += b.x;
+        a.y += b.y;
+        a.z += b.z;
+        a.w += b.w;
+      }
+      typedef double d4v __attribute__((ext_vector_type(4)));
+      typedef __attribute__((address_space(1))) d4v* gd4p;
+      const d4v v = {a.x, a.y, a.z, a.w};
+      ((gd4p)(d4v*)parts)[m.x] = v;
+    }
+  }
+}
+
+template <int U>
+__device__ __forceinline__ void pack_row(const RowBlock& dc, const RowBlock& dn, bool weigh,
+                                         bool more, long long step, int lane, float4 (&h)[kPackRows],
+                                         const float4* tab, int table_len, float4& acc, PackLds& L) {
+  const unsigned word = row_word<U, 2>(dc);
+  if (weigh && (word & 0xFFu) != 0u)
+    acc = row_weigh<U>(dc, step, lane, h[U], tab, table_len, acc);
+  else
+    asm volatile("" ::"v"(h[U].x), "v"(h[U].y), "v"(h[U].z), "v"(h[U].w));
+  __builtin_amdgcn_sched_barrier(0);
+  row_load<U>(dn, more, lane, h[U]);
+  const int slot = (int)((word >> 8) & 0xFFu) - 1;
+  if (slot >= 0) {
+    const float4 r = wave_reduce4(acc);
+    if (lane == 0) {
+      L.part[slot] = make_double4(r.x, r.y, r.z, r.w);
+      L.meta[slot] = make_int2((int)row_word<U, 7>(dc), (int)(word >> 16));
+    }
+    acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+template <int... Us>
+__device__ __forceinline__ void pack_rows(std::integer_sequence<int, Us...>, const RowBlock& dc,
+                                          const RowBlock& dn, bool weigh, bool more, long long step,
+                                          int lane, float4 (&h)[kPackRows], const float4* tab,
+                                          int table_len, float4& acc, PackLds& L) {
+  (pack_row<Us>(dc, dn, weigh, more, step, lane, h, tab, table_len, acc, L), ...);
+}
+
+template <int... Us>
+__device__ __forceinline__ void pack_first(std::integer_sequence<int, Us...>, const RowBlock& d,
+                                           bool live, int lane, float4 (&h)[kPackRows]) {
+  (row_load<Us>(d, live, lane, h[Us]), ...);
+}
+
+__global__ void __launch_bounds__(kConvThreads)
+k_conv32p(const FaultDev* __restrict__ faults, const RowDesc* __restrict__ rows,
+          const ConvTask* __restrict__ tasks, int ntasks, const float4* __restrict__ table,
+          int table_len, int ahead) {
+  extern __shared__ float4 tab[];
+  __shared__ PackLds L;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int G = gridDim.x;
+  const ConvTask none{0, 0, 0, 0};
+  int task = blockIdx.x;
+  RowBlock dc = load_rows(rows, task, ntasks, wave, lane);
+  RowBlock dn = load_rows(rows, task + G, ntasks, wave, lane);
+  float4 h[kPackRows];
+  pack_first(std::make_integer_sequence<int, kPackRows>{}, dc, task < ntasks, lane, h);
+  ConvTask tk = task < ntasks ? tasks[task] : none;
+  int err = 0;
+  long long step = 0;
+  double4* parts = nullptr;
+  if (task < ntasks) {
+    const FaultDev& fd = faults[tk.fault];
+    err = read_word(fd.err);
+    step = read_word(fd.step) + ahead;
+    parts = fd.parts;
+  }
+  // the table is staged while the first records are in flight
+  for (int i = threadIdx.x; i < table_len; i += kConvThreads) tab[i] = table[i];
+  __syncthreads();
+  while (task < ntasks) {
+    const int nxt = task + G;
+    const bool more = nxt < ntasks;
+    const RowBlock dnn = load_rows(rows, nxt + G, ntasks, wave, lane);
+    const ConvTask nk = more ? tasks[nxt] : none;
+    const FaultDev& nfd = faults[more ? nk.fault : tk.fault];
+    const int nerr = read_word(nfd.err);
+    const long long nstep = read_word(nfd.step) + ahead;
+    double4* const nparts = nfd.parts;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    pack_rows(std::make_integer_sequence<int, kPackRows>{}, dc, dn, !err, more, step, lane, h,
+              tab, table_len, acc, L);
+    __syncthreads();
+    finish_packed(parts, L, tk.nsum);
+    __syncthreads();
+    task = nxt;
+    tk = nk;
+    dc = dn;
+    dn = dnn;
+    err = nerr;
+    step = nstep;
+    parts = nparts;
   }
 }
 
@@ -1407,15 +1710,28 @@ k_conv_var(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
         // newest last, so lane 63 takes it from lane 0 of the chunk after;
         // only the tile's last slot and the slot of the newest interval b
         // (whose successor slot holds the oldest one) evaluate it directly.
-        double nxT = 0.0, nxN = 0.0;  // P at lane 0's start in the chunk after
+        // every slot's log entry and record are requested before any is
+        // used, so that a wave has all of its tile's loads in flight at once
+        double2 ivs[U];
+        Rec recs[U];
+        bool valids[U];
 #pragma unroll
-        for (int u = U - 1; u >= 0; --u) {
+        for (int u = 0; u < U; ++u) {
           const int p = tl.p0 + lane + 64 * u;
           bool valid = live && p < end;
           const long long I =
               valid ? b - (long long)mod_pos(b - p + (long long)Rn * 4, Rn) : -1;
           valid = valid && I >= 0;
-          const double2 iv = valid ? fd.tlog[I % fd.tlog_cap] : make_double2(0.0, 0.0);
+          valids[u] = valid;
+          ivs[u] = valid ? fd.tlog[I % fd.tlog_cap] : make_double2(0.0, 0.0);
+          if (valid) recs[u] = ring[p];
+        }
+        double nxT = 0.0, nxN = 0.0;  // P at lane 0's start in the chunk after
+#pragma unroll
+        for (int u = U - 1; u >= 0; --u) {
+          const int p = tl.p0 + lane + 64 * u;
+          const bool valid = valids[u];
+          const double2 iv = ivs[u];
           const double Ta = csk * (va.t_new - iv.y), Tb = csk * (va.t_new - iv.x);
           double pTb = 0.0, pNb = 0.0, qNb = 0.0;  // q: the normal kind's own cut
           if (valid) {
@@ -1445,7 +1761,7 @@ k_conv_var(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
           if (!inwin) continue;
           const double wT = (pTb - pTa) * inv;
           const double wN = (qNb - qNa) * inv;
-          const Rec r = ring[p];
+          const Rec r = recs[u];
           if constexpr (sizeof(R) == 4) {
             ax = fma(wT, (double)r.x, ax);
             ay = fma(wT, (double)r.y, ay);
@@ -1667,6 +1983,9 @@ hipError_t setup_kernel_attributes(int precision) {
   if (!e && idx)
     e = hipFuncSetAttribute((const void*)k_conv32<16, 1>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+  if (!e && idx)
+    e = hipFuncSetAttribute((const void*)k_conv32p, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kMaxLdsBytes - kConvStaticLds);
   if (!e) done[idx] = true;
   return e;
 }
@@ -1680,7 +1999,7 @@ int conv_grid_size(int precision, int ntasks, int table_len, int reserve) {
     // launches of the step, which run beside the convolution, find no CU
     // until it ends; `reserve` workgroups fewer leave that many CUs with
     // one, where the stages run in the convolution's shadow.
-    const int per_cu = (int)(kMaxLdsBytes / ((size_t)table_len * sizeof(float4) + 1024));
+    const int per_cu = (int)(kMaxLdsBytes / ((size_t)table_len * sizeof(float4) + kConvStaticLds));
     int cap = 256 * (per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu));
     cap = std::max(256, cap - std::max(0, reserve));
     return need < cap ? (need < 1 ? 1 : need) : cap;
@@ -1702,7 +2021,11 @@ hipError_t launch_conv(const Exec& ex, int ahead, hipStream_t s) {
     static_assert(kTileSlots32 == 8 * 64 && kWaveTiles32 == 2, "tile shape");
     static_assert(kTileSlots32s == 4 * 64 && kWaveTiles32s == 4, "short tile shape");
     static_assert(kTileSlots32l == 16 * 64, "long tile shape");
-    if (ex.tile_rows == 4)
+    if (ex.tile_rows == 1)
+      hipLaunchKernelGGL(k_conv32p, dim3(ex.conv_grid), dim3(kConvThreads), lds, s, ex.d_faults,
+                         (const RowDesc*)ex.d_tiles, ex.d_tasks, ex.ntasks, ex.table, ex.table_len,
+                         ahead);
+    else if (ex.tile_rows == 4)
       hipLaunchKernelGGL((k_conv32<4, 4>), dim3(ex.conv_grid), dim3(kConvThreads), lds, s,
                          ex.d_faults, ex.d_tiles, ex.d_tasks, ex.ntasks, ex.table, ex.table_len,
                          ahead, ex.conv_ctr);

@@ -2,6 +2,7 @@
 // device buffers, state upload/download and the stress-only path.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <complex>
 #include <cstring>
 #include <sstream>
@@ -226,9 +227,93 @@ void lag_weights(const sbiem_plan* p, int n, double dt, int MT, int MN, int j0, 
 // first piece of mode n at parts[mode_pos(n)], further pieces from N/2 + 1
 // on).  FP32 tiles keep 16 rows of 64 records in flight per wave, so a task
 // is 8192 records whatever the tile.  Returns the number of partial sums.
+// Packed FP32 rows: every row of every mode in order, 128 to a task, a task
+// ending wherever its 128th row falls (a mode cut by a task boundary gets one
+// partial sum per task, ordered as above; the last task is padded with empty
+// rows).  A wave sum ends at the last row of a partial sum in a wave and at a
+// wave's last row; its LDS slot counts the task's wave sums in row order, so
+// the slots of one partial sum are consecutive.
+static int build_rows(const sbiem_plan* p, DtData* d, long double th_unit) {
+  const int half = (int)(p->N / 2);
+  d->tile_slots = kTileSlots32p;
+  d->tiles.clear();
+  d->tasks.clear();
+  d->row_meta.clear();
+  d->part0.assign(half + 1, 0);
+  d->nparts.assign(half + 1, 0);
+  int extra = half + 1;
+  auto open_task = [&]() {
+    const int at = (int)d->tiles.size();
+    d->tasks.push_back(ConvTask{at, at, 0, 0});
+  };
+  for (int n = 1; n <= half; ++n) {
+    const int rows = (d->Rn[n] + 63) / 64;
+    if (rows == 0) continue;
+    const int extra0 = extra;
+    int part = mode_pos(n, p->log2P, p->log2Q);
+    for (int r = 0; r < rows; ++r) {
+      if (d->tasks.empty() || d->tasks.back().t1 - d->tasks.back().t0 == kTaskRows) {
+        if (r > 0) part = extra++;   // the mode continues in a new task
+        open_task();
+      }
+      Tile t{};
+      t.mode = n;
+      t.p0 = 64 * r;
+      t.len = std::min(64, d->Rn[n] - 64 * r);
+      t.Rn = d->Rn[n];
+      t.part = part;
+      t.MT = d->MT[n];
+      t.MN = d->MN[n];
+      t.ring_off = d->ring_off[n];
+      t.th = (double)(th_unit * n);
+      t.rmagic = UINT64_MAX / (uint64_t)t.Rn + 1;
+      d->tiles.push_back(t);
+      d->tasks.back().t1 = (int)d->tiles.size();
+    }
+    d->part0[n] = extra0;
+    d->nparts[n] = 1 + (extra - extra0);
+  }
+  // pad the last task; empty rows have len 0 and no partial sum
+  if (!d->tasks.empty())
+    while (d->tasks.back().t1 - d->tasks.back().t0 < kTaskRows) {
+      Tile t{};
+      t.part = -1;
+      t.Rn = 1;
+      t.rmagic = 0;
+      d->tiles.push_back(t);
+      d->tasks.back().t1 = (int)d->tiles.size();
+    }
+  // wave sums: slots in row order; the run length at a partial sum's first
+  d->row_meta.assign(d->tiles.size(), make_int2(-1, 0));
+  for (ConvTask& k : d->tasks) {
+    int slot = 0;
+    for (int i = k.t0; i < k.t1; ++i) {
+      const Tile& t = d->tiles[i];
+      if (t.len == 0) continue;
+      const bool wave_end = (i - k.t0) % kPackRows == kPackRows - 1;
+      const bool last = i + 1 == k.t1 || d->tiles[i + 1].len == 0 || d->tiles[i + 1].part != t.part;
+      if (wave_end || last) d->row_meta[i].x = slot++;
+    }
+    // run lengths: consecutive slots of one partial sum
+    int run_row = -1, run_part = -2;
+    for (int i = k.t0; i < k.t1; ++i) {
+      if (d->row_meta[i].x < 0) continue;
+      if (d->tiles[i].part != run_part) {
+        run_row = i;
+        run_part = d->tiles[i].part;
+      }
+      d->row_meta[run_row].y += 1;
+    }
+    k.nsum = slot;
+  }
+  return extra;
+}
+
 int build_tiles(const sbiem_plan* p, DtData* d, int tile, long double th_unit) {
   const int half = (int)(p->N / 2);
   const bool fp32 = p->precision == SBIEM_FP32CONV && !d->var;
+  if (fp32 && tile == kTileSlots32p) return build_rows(p, d, th_unit);
+  d->row_meta.clear();
   const int task_tiles = fp32 ? (16 / (tile / 64)) * (kConvThreads / 64) : kTaskTiles64;
   d->tile_slots = tile;
   d->tiles.clear();
@@ -238,7 +323,7 @@ int build_tiles(const sbiem_plan* p, DtData* d, int tile, long double th_unit) {
   int extra = half + 1;
   int cur_tiles = 0;
   auto open_task = [&]() {
-    d->tasks.push_back(ConvTask{(int)d->tiles.size(), (int)d->tiles.size()});
+    d->tasks.push_back(ConvTask{(int)d->tiles.size(), (int)d->tiles.size(), 0, 0});
     cur_tiles = 0;
   };
   for (int n = 1; n <= half; ++n) {
@@ -263,6 +348,7 @@ int build_tiles(const sbiem_plan* p, DtData* d, int tile, long double th_unit) {
       t.MN = d->MN[n];
       t.ring_off = d->ring_off[n];
       t.th = (double)(th_unit * n);
+      t.rmagic = UINT64_MAX / (uint64_t)t.Rn + 1;
       d->tiles.push_back(t);
       d->tasks.back().t1 = (int)d->tiles.size();
       ++cur_tiles;
@@ -442,7 +528,7 @@ int build_dt_data(sbiem_plan* p, double dt, DtData** out) {
     for (int n = 1; n <= half; ++n)
       Tmax = std::max(Tmax, (double)(theta_unit * n) * (2.0 * (d->Rn[n] + 1) + 3.0));
     const int K = (int)std::ceil(Tmax / kTableStep) + 3;
-    if ((size_t)K * sizeof(float4) > (size_t)kMaxDynLds) {
+    if ((size_t)K * sizeof(float4) > (size_t)(kMaxLdsBytes - kConvStaticLds)) {
       e = hipErrorInvalidValue;
     } else {
       std::vector<float4> tab(K);
@@ -999,8 +1085,8 @@ int sbiem_kernel_primitive_eval(double cs, double cp, const double* T, int64_t n
 int sbiem_set_conv_tile(sbiem_plan* p, int records) {
   if (int s = check_plan(p)) return s;
   if (records != 0 && records != kTileSlots32s && records != kTileSlots32 &&
-      records != kTileSlots32l)
-    return fail(p, SBIEM_EINVAL, "set_conv_tile: records must be 0, 256, 512 or 1024");
+      records != kTileSlots32l && records != kTileSlots32p)
+    return fail(p, SBIEM_EINVAL, "set_conv_tile: records must be 0, 64, 256, 512 or 1024");
   if (p->batch_refs > 0) return fail(p, SBIEM_EINVAL, "set_conv_tile: plan is used by a batch");
   p->conv_tile = records;
   p->conv_tile_set = records != 0;

@@ -110,17 +110,20 @@ def test_training_pairs_match_oracle():
     assert ey < 1e-4
 
 
-def test_step_with_closure_matches_oracle():
-    """Closure-on steps against the oracle with the same networks.  The
-    networks are untrained with outputs scaled to the size of a real tail
-    (large random tails drive the rupture unstably and amplify the bfloat16
-    rounding differences of the network inputs step after step)."""
+@pytest.mark.parametrize("tile", [0, 64])
+def test_step_with_closure_matches_oracle(tile):
+    """Closure-on steps against the oracle with the same networks (tile 64:
+    the packed rows of the short kept windows).  The networks are untrained
+    with outputs scaled to the size of a real tail (large random tails drive
+    the rupture unstably and amplify the bfloat16 rounding differences of the
+    network inputs step after step)."""
     from oracle.stepper import OracleFault
     pkg = _pkg()
     sc = _rupture(N=256, seed=7)
     pT, pN = _params(11, 0.02, 0.05), _params(12, 0.02, 0.05)
     p = make_plan(sc, pkg.SBIEM_FP32CONV)
     p.set_closure(pT.astype(np.float32), pN.astype(np.float32), 0.25)
+    p.set_conv_tile(tile)
     o = OracleFault(sc.N, sc.L, MU, CS, CP, dt=sc.dt, friction=fields(sc), h=sc.h,
                     theta_mode=sc.theta_mode, transform="fft",
                     closure=(pT.astype(np.float32).astype(np.float64),
@@ -133,7 +136,7 @@ def test_step_with_closure_matches_oracle():
         worst["tau_el"] = max(worst["tau_el"], rel_parts(g["tau_el"], o.tau_el, o.tau_static))
         worst["sigma_el"] = max(worst["sigma_el"], rel_parts(g["sigma_el"], o.sigma_el, o.sigma_static))
         worst["V"] = max(worst["V"], rel(g["V"], o.V))
-    print("closure step vs oracle", worst)
+    print("closure step vs oracle (tile %d)" % tile, worst)
     assert worst["tau_el"] < 1e-5 and worst["sigma_el"] < 1e-5, worst
 
 

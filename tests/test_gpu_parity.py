@@ -57,10 +57,13 @@ def test_stress_fp64_matches_oracle(N, nt):
 
 
 @pytest.mark.parametrize("N,nt,tile", [(1024, 300, 0), (512, 1100, 0), (1024, 1500, 256),
-                                        (1024, 1500, 1024)])
+                                        (1024, 1500, 1024), (1024, 1500, 64), (512, 300, 64),
+                                        (256, 2100, 64)])
 def test_stress_fp32_matches_oracle(N, nt, tile):
-    """FP32 stress path against the oracle; the last two cases put windows of
-    up to 2048 records through tiles of 256 and 1024 records."""
+    """FP32 stress path against the oracle; the later cases put windows of up
+    to 2048 records through tiles of 256 and 1024 records and through packed
+    rows (tile 64: modes of one to 32 rows sharing waves and tasks, a mode
+    cut by a task boundary, a padded last task)."""
     from oracle.spectral import curvature
     from oracle.stress import stress_from_history
     from oracle.windows import midpoint_weights
@@ -121,7 +124,8 @@ def test_step_fp64_dynamic_rupture():
     assert worst < 1e-10, worst
 
 
-def test_step_fp32_dynamic_rupture_N1024():
+@pytest.mark.parametrize("tile", [0, 64])
+def test_step_fp32_dynamic_rupture_N1024(tile):
     pkg = _pkg()
     N = 1024
     L = 10.0 * N
@@ -129,6 +133,7 @@ def test_step_fp32_dynamic_rupture_N1024():
     h = rough_10km(N, seed=3, alpha=3e-3) * (L / 10e3)
     sc = Scenario(N, L, 0.5 * (L / N) / CS, h, spec=spec, theta_mode="exp", consistent_V0=True)
     p = make_plan(sc, pkg.SBIEM_FP32CONV)
+    p.set_conv_tile(tile)
     o = make_oracle(sc)
     worst = {"tau_el": 0.0, "sigma_el": 0.0, "slip": 0.0, "V": 0.0}
     for _ in range(4):
@@ -137,7 +142,7 @@ def test_step_fp32_dynamic_rupture_N1024():
         g = p.get_state()
         for k, ref in (("slip", o.slip), ("V", o.V), ("tau_el", o.tau_el), ("sigma_el", o.sigma_el)):
             worst[k] = max(worst[k], rel(g[k], ref))
-    print("fp32 N=1024 rupture worst relative errors", worst)
+    print("fp32 N=1024 rupture (tile %d) worst relative errors" % tile, worst)
     assert worst["tau_el"] < 1e-5 and worst["sigma_el"] < 1e-5, worst
 
 
@@ -211,7 +216,8 @@ def test_failure_leaves_state_at_start_of_step():
         assert np.array_equal(before[k], after[k])
 
 
-def test_batch_matches_individual_plans_bitwise():
+@pytest.mark.parametrize("tile", [0, 64])
+def test_batch_matches_individual_plans_bitwise(tile):
     pkg = _pkg()
     plans_a, plans_b = [], []
     for N, seed in ((256, 1), (1024, 2), (512, 3)):
@@ -221,6 +227,9 @@ def test_batch_matches_individual_plans_bitwise():
                       consistent_V0=True)
         plans_a.append(make_plan(sc, pkg.SBIEM_FP32CONV))
         plans_b.append(make_plan(sc, pkg.SBIEM_FP32CONV))
+        if tile:
+            plans_a[-1].set_conv_tile(tile)
+            plans_b[-1].set_conv_tile(tile)
     dt = 0.5 * 10.0 / CS
     batch = pkg.Batch(plans_a)
     batch.run(40)
@@ -252,9 +261,10 @@ def _workload_plan_and_oracle(w, nsteps):
     return p, o
 
 
-@pytest.mark.parametrize("name", ["seamount-N8192", "ensemble64-N16384", "rough-N65536",
-                                  "ensemble16-N262144"])
-def test_step_fp32_full_size_matches_oracle(name):
+@pytest.mark.parametrize("name,tile", [("seamount-N8192", 0), ("ensemble64-N16384", 0),
+                                       ("rough-N65536", 0), ("ensemble16-N262144", 0),
+                                       ("rough-N65536", 64), ("ensemble16-N262144", 64)])
+def test_step_fp32_full_size_matches_oracle(name, tile):
     """The first 20 steps of the full-size workloads (graph replay, as in
     bench.py) against the oracle, compared after a 16-step graph replay and
     after 4 single steps.  The tractions are then tiny (the fault is still
@@ -268,6 +278,7 @@ def test_step_fp32_full_size_matches_oracle(name):
     else:
         w = workload(name)
     p, o = _workload_plan_and_oracle(w, 20)
+    p.set_conv_tile(tile)
     worst = {"tau_el": 0.0, "sigma_el": 0.0, "slip": 0.0, "V": 0.0,
              "tau_el_plain": 0.0, "sigma_el_plain": 0.0}
     for chunk in (16, 4):
@@ -280,7 +291,7 @@ def test_step_fp32_full_size_matches_oracle(name):
         worst["sigma_el"] = max(worst["sigma_el"], rel_parts(g["sigma_el"], o.sigma_el, o.sigma_static))
         worst["tau_el_plain"] = max(worst["tau_el_plain"], rel(g["tau_el"], o.tau_el))
         worst["sigma_el_plain"] = max(worst["sigma_el_plain"], rel(g["sigma_el"], o.sigma_el))
-    print(name, "worst relative errors", worst)
+    print(name, "tile", tile, "worst relative errors", worst)
     assert worst["tau_el"] < 1e-5 and worst["sigma_el"] < 1e-5, worst
     assert worst["slip"] < 1e-10 and worst["V"] < 1e-10, worst
 
