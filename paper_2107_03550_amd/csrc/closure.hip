@@ -49,11 +49,10 @@ __device__ __forceinline__ float gelu_infer(float z) {
   return 0.5f * z * (1.f + copysignf(erf_ax, x));
 }
 
-// float -> bfloat16 bits, round to nearest even
+// float -> bfloat16 bits, round to nearest even (the conversion instruction,
+// two values per instruction where the compiler pairs them)
 __device__ __forceinline__ short bf16_bits(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (short)(u >> 16);
+  return __builtin_bit_cast(short, (__bf16)x);
 }
 static unsigned short bf16_bits_host(float x) {
   unsigned u;
