@@ -58,9 +58,11 @@ def _pieces(M, task_records):
     return -(-(M - 1) // task_records)
 
 
-def test_stress_fp32_long_windows_in_three_pieces():
+@pytest.mark.parametrize("tile", [0, 64])
+def test_stress_fp32_long_windows_in_three_pieces(tile):
     """N = 64 at beta = 1/320: every window holds about 20480 lags, three
-    FP32 tasks of 8192 ring records; 21000 intervals fill every record (the
+    FP32 tasks of 8192 ring records (tile 64: packed rows, a mode across
+    three or four 128-row tasks); 21000 intervals fill every record (the
     fill wraps) with random rates."""
     from oracle.spectral import curvature_fft
     from oracle.stress import stress_from_history
@@ -73,13 +75,14 @@ def test_stress_fp32_long_windows_in_three_pieces():
     h = rough_10km(N, seed=11, alpha=5e-3) * (L / 10e3)
     p = pkg.Plan(N, L, MU, NU, CS, CP, h)
     p.set_precision(pkg.SBIEM_FP32CONV)
+    p.set_conv_tile(tile)
     M = p.window_lengths(dt)
     assert M.min() > 16385 and _pieces(M.max(), 8192) == 3 and nt > M.max()
     hist = _random_history(N, nt, seed=21)
     tau, sig = p.stress(hist, dt)
     w = midpoint_weights(N, L, CS, CP, dt)
     rt, rs = stress_from_history(hist, dt, L, MU, CS, CP, curvature_fft(h, L), w, transform="fft")
-    print("fp32 three-piece windows:", rel(tau, rt), rel(sig, rs))
+    print("fp32 three-piece windows (tile %d):" % tile, rel(tau, rt), rel(sig, rs))
     assert rel(tau, rt) < 1e-5 and rel(sig, rs) < 1e-5, (rel(tau, rt), rel(sig, rs))
 
 
