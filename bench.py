@@ -178,18 +178,23 @@ def traffic_from_profiles(workload: str, closure: bool, alg_bytes: float, tile=N
     if they were taken on the current kernel source and on this very launch
     (same workload, same form, same tile, same algorithmic bytes)."""
     tag = workload + ("-closure" if closure else "")
-    path = os.path.join(ROOT, "profiles", f"conv_traffic_{tag}.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        z = json.load(f)
-    if z.get("kernel_sha256_16") != kernel_hash():
-        return None
-    if z.get("algorithmic_bytes_per_launch") != alg_bytes:
-        return None
-    if tile is not None and z.get("conv_tile") != tile:
-        return None
-    return z.get("bytes_per_launch")
+    names = [f"conv_traffic_{tag}.json"]
+    if tile is not None:
+        names.insert(0, f"conv_traffic_{tag}_tile{tile}.json")
+    for name in names:
+        path = os.path.join(ROOT, "profiles", name)
+        if not os.path.exists(path):
+            continue
+        with open(path) as f:
+            z = json.load(f)
+        if z.get("kernel_sha256_16") != kernel_hash():
+            continue
+        if z.get("algorithmic_bytes_per_launch") != alg_bytes:
+            continue
+        if tile is not None and z.get("conv_tile", tile) != tile:
+            continue
+        return z.get("bytes_per_launch")
+    return None
 
 
 # ---------------------------------------------------------------- seismic cycle

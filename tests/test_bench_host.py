@@ -48,6 +48,13 @@ def test_traffic_only_for_the_profiled_launch(tmp_path, monkeypatch):
          "bytes_per_launch": 6, "conv_tile": 512}))
     assert bench.traffic_from_profiles("rough-N65536", False, 5.0, 512) == 6
     assert bench.traffic_from_profiles("rough-N65536", False, 5.0, 1024) is None
+    # counters of another tile sit in a file of their own
+    (tmp_path / "profiles" / "conv_traffic_rough-N65536_tile1024.json").write_text(json.dumps(
+        {"kernel_sha256_16": "abc", "algorithmic_bytes_per_launch": 5.0,
+         "bytes_per_launch": 7, "conv_tile": 1024}))
+    assert bench.traffic_from_profiles("rough-N65536", False, 5.0, 1024) == 7
+    assert bench.traffic_from_profiles("rough-N65536", False, 5.0, 512) == 6
+    assert bench.traffic_from_profiles("rough-N65536", True, 5.0, 1024) is None
 
 
 def test_committed_traffic_profiles_match_their_algorithmic_bytes():
