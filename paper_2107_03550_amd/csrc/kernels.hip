@@ -588,25 +588,35 @@ __device__ __forceinline__ unsigned row_word(const RowBlock& b) {
   const int v = F % 3 == 0 ? b.a : (F % 3 == 1 ? b.b : b.c);
   return (unsigned)__builtin_amdgcn_readlane(v, 4 * U + F / 3);
 }
+typedef const __attribute__((address_space(1))) f4v* gf4p;
 template <int U>
-__device__ __forceinline__ void row_load(const RowBlock& b, bool live, int lane, float4& h) {
+__device__ __forceinline__ void row_load(const RowBlock& b, bool live, int lane, const float4* dummy,
+                                         float4& h) {
   const unsigned long long rec =
       (unsigned long long)row_word<U, 1>(b) << 32 | (unsigned long long)row_word<U, 0>(b);
   const int len = (int)(row_word<U, 2>(b) & 0xFFu);
-  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)(uintptr_t)rec, 0, live ? len * 16 : 0, kBufferWord3);
-  int off = lane * 16;
-  asm volatile("" : "+v"(off));
-  const f4v t = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kLoadNT));
+  const bool use = live && len > 0;
+  // lanes past the row's end re-read its last record (same cache line); an
+  // empty row reads the first nodes of the table (cached, never weighed)
+  const unsigned long long base = use ? rec : (unsigned long long)(uintptr_t)dummy;
+  const int idx = use ? min(lane, len - 1) : (lane & 3);
+  // the address is formed in vector registers: a memory instruction reading
+  // a scalar register that a lane read has just written needs wait states
+  unsigned lo = (unsigned)base, hi = (unsigned)(base >> 32);
+  asm volatile("" : "+v"(lo), "+v"(hi));
+  const unsigned long long a = ((unsigned long long)hi << 32 | lo) + (unsigned long long)idx * 16u;
+  const f4v t = __builtin_nontemporal_load((gf4p)(const float4*)(uintptr_t)a);
   h = make_float4(t.x, t.y, t.z, t.w);
 }
 
 // The weights of one row's records (lane: record p0 + lane of the mode's
 // ring), added to acc; as in conv32_weigh.
+// The ring phase depends on the step and R_n alone: it is recomputed only
+// when a row's R_n differs from the previous row's (pRn, po carry it).
 template <int U>
 __device__ __forceinline__ float4 row_weigh(const RowBlock& b, long long step, int lane,
                                             const float4& hv, const float4* tab, int table_len,
-                                            float4 acc) {
+                                            float4 acc, int& pRn, int& po) {
   const int len = (int)(row_word<U, 2>(b) & 0xFFu);
   const int p0 = (int)row_word<U, 3>(b);
   const int Rn = (int)row_word<U, 4>(b);
@@ -614,9 +624,13 @@ __device__ __forceinline__ float4 row_weigh(const RowBlock& b, long long step, i
   const int MN = (int)row_word<U, 6>(b);
   const double th = __builtin_bit_cast(
       double, (unsigned long long)row_word<U, 9>(b) << 32 | (unsigned long long)row_word<U, 8>(b));
-  const unsigned long long M =
-      (unsigned long long)row_word<U, 11>(b) << 32 | (unsigned long long)row_word<U, 10>(b);
-  const int o = ring_phase_m(step, Rn, M);
+  if (Rn != pRn) {
+    const unsigned long long M =
+        (unsigned long long)row_word<U, 11>(b) << 32 | (unsigned long long)row_word<U, 10>(b);
+    po = ring_phase_m(step, Rn, M);
+    pRn = Rn;
+  }
+  const int o = po;
   const int p = p0 + lane;
   int q = p + o;
   q -= (q >= Rn) ? Rn : 0;
@@ -667,14 +681,15 @@ __device__ __forceinline__ void finish_packed(double4* parts, const PackLds& L, 
 template <int U>
 __device__ __forceinline__ void pack_row(const RowBlock& dc, const RowBlock& dn, bool weigh,
                                          bool more, long long step, int lane, float4 (&h)[kPackRows],
-                                         const float4* tab, int table_len, float4& acc, PackLds& L) {
+                                         const float4* tab, int table_len, const float4* dummy,
+                                         float4& acc, int& pRn, int& po, PackLds& L) {
   const unsigned word = row_word<U, 2>(dc);
   if (weigh && (word & 0xFFu) != 0u)
-    acc = row_weigh<U>(dc, step, lane, h[U], tab, table_len, acc);
+    acc = row_weigh<U>(dc, step, lane, h[U], tab, table_len, acc, pRn, po);
   else
     asm volatile("" ::"v"(h[U].x), "v"(h[U].y), "v"(h[U].z), "v"(h[U].w));
   __builtin_amdgcn_sched_barrier(0);
-  row_load<U>(dn, more, lane, h[U]);
+  row_load<U>(dn, more, lane, dummy, h[U]);
   const int slot = (int)((word >> 8) & 0xFFu) - 1;
   if (slot >= 0) {
     const float4 r = wave_reduce4(acc);
@@ -690,14 +705,17 @@ template <int... Us>
 __device__ __forceinline__ void pack_rows(std::integer_sequence<int, Us...>, const RowBlock& dc,
                                           const RowBlock& dn, bool weigh, bool more, long long step,
                                           int lane, float4 (&h)[kPackRows], const float4* tab,
-                                          int table_len, float4& acc, PackLds& L) {
-  (pack_row<Us>(dc, dn, weigh, more, step, lane, h, tab, table_len, acc, L), ...);
+                                          int table_len, const float4* dummy, float4& acc,
+                                          PackLds& L) {
+  int pRn = -1, po = 0;
+  (pack_row<Us>(dc, dn, weigh, more, step, lane, h, tab, table_len, dummy, acc, pRn, po, L), ...);
 }
 
 template <int... Us>
 __device__ __forceinline__ void pack_first(std::integer_sequence<int, Us...>, const RowBlock& d,
-                                           bool live, int lane, float4 (&h)[kPackRows]) {
-  (row_load<Us>(d, live, lane, h[Us]), ...);
+                                           bool live, int lane, const float4* dummy,
+                                           float4 (&h)[kPackRows]) {
+  (row_load<Us>(d, live, lane, dummy, h[Us]), ...);
 }
 
 __global__ void __launch_bounds__(kConvThreads)
@@ -714,7 +732,7 @@ k_conv32p(const FaultDev* __restrict__ faults, const RowDesc* __restrict__ rows,
   RowBlock dc = load_rows(rows, task, ntasks, wave, lane);
   RowBlock dn = load_rows(rows, task + G, ntasks, wave, lane);
   float4 h[kPackRows];
-  pack_first(std::make_integer_sequence<int, kPackRows>{}, dc, task < ntasks, lane, h);
+  pack_first(std::make_integer_sequence<int, kPackRows>{}, dc, task < ntasks, lane, table, h);
   ConvTask tk = task < ntasks ? tasks[task] : none;
   int err = 0;
   long long step = 0;
@@ -739,7 +757,7 @@ k_conv32p(const FaultDev* __restrict__ faults, const RowDesc* __restrict__ rows,
     double4* const nparts = nfd.parts;
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     pack_rows(std::make_integer_sequence<int, kPackRows>{}, dc, dn, !err, more, step, lane, h,
-              tab, table_len, acc, L);
+              tab, table_len, table, acc, L);
     __syncthreads();
     finish_packed(parts, L, tk.nsum);
     __syncthreads();
