@@ -384,8 +384,10 @@ int sbiem_batch_profile(sbiem_batch* b, double* conv_ms, int64_t* conv_launches,
  * first element launch enqueued first after the previous step's commit and,
  * with the learned closure on, with its network launched after the
  * convolution or before the first element launch, steps_per_trial steps
- * each (rounded up to the 16-step graph, plus one settling graph), and the
- * fastest is kept until the plan's tables are rebuilt (sbiem_set_dt,
+ * each (rounded up to the 16-step graph, plus one settling graph); the
+ * fastest is tried once more with the convolution's record loads on the
+ * default cache policy instead of the non-temporal one, and the faster of the
+ * two is kept until the plan's tables are rebuilt (sbiem_set_dt,
  * sbiem_set_precision, sbiem_set_closure).  Unless a member's tile was set
  * with sbiem_set_conv_tile, all of this is repeated for each FP32 tile
  * shape (256, 512 and 1024 ring records per tile; the ring itself does not
@@ -393,7 +395,7 @@ int sbiem_batch_profile(sbiem_batch* b, double* conv_ms, int64_t* conv_launches,
  * steps are ordinary steps: results do not depend on the launch shape or
  * order, and a tile change alters only the FP32 summation order of the
  * history sums; the state advances by about (steps_per_trial + 16) times the
- * number of candidates (at most 10, 20 with the closure, per tile).
+ * number of candidates (at most 11, 21 with the closure, per tile).
  * *conv_workgroups (may be NULL) receives the chosen grid
  * (sbiem_get_conv_tile the tile).  FP64 plans have nothing to tune (OK).
  * Errors as sbiem_run; a plan used by a batch is tuned through the batch. */

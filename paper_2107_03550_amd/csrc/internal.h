@@ -356,6 +356,7 @@ struct Exec {
   int tile_rows = kTileSlots32 / 64;  // FP32: 64-record rows per conv tile (8, or 4 for short windows)
   bool stages_first = false;     // enqueue a step's first stage launch before its conv launch
   bool closure_main = false;     // closure network on the stage stream (before the first stage)
+  bool cached_loads = false;     // FP32 conv record loads with the default cache policy (else streamed)
   int* conv_ctr = nullptr;        // FP32 conv: dynamic task counter (zeroed by the mode launch after it)
   ClosureMode* closure_modes = nullptr;  // closed modes of every fault (null: no closure)
   int nclosure = 0;

@@ -341,11 +341,12 @@ __device__ __forceinline__ long long read_word(const long long* p) {
 }
 
 // The ring is streamed once per step.  Its loads take the cache policy POL:
-// non-temporal under the learned closure, whose network runs beside the
-// conv and rereads the kept records; the default policy in the plain form,
-// where it makes the whole step faster (measured on the largest workload:
-// plain steps 2 % faster with default loads, closure steps 1.3 % slower; the
-// conv launch itself unchanged).  A tile's records
+// non-temporal by default, which keeps the ring from displacing what the
+// stage launches beside the conv reuse; the autotuner also tries the default
+// policy, which shortens the step where the ring is far larger than the
+// caches (measured: the plain ensemble16-N262144 step 2 % faster, the conv
+// launch itself unchanged; rough-N65536, ensemble64 and seamount-N8192 5-7 %
+// slower, the closure form 1.3 % slower).  A tile's records
 // are read through a buffer resource that spans exactly its len records:
 // lanes past the tile's end (and every lane of a wave without a tile, whose
 // range is empty) fall outside the range check, read 0 and touch no memory,
@@ -2041,10 +2042,10 @@ int default_conv_reserve(double bytes) {
   return bytes < 4e9 ? 64 : 0;
 }
 
-// the tiled FP32 conv with the cache policy of the form (closure: streamed)
+// the tiled FP32 conv with the cache policy the context uses
 template <int U, int K>
 static void launch_conv32(const Exec& ex, int ahead, hipStream_t s, size_t lds) {
-  if (ex.nclosure > 0)
+  if (!ex.cached_loads)
     hipLaunchKernelGGL((k_conv32<U, K, kLoadStream>), dim3(ex.conv_grid), dim3(kConvThreads), lds,
                        s, ex.d_faults, ex.d_tiles, ex.d_tasks, ex.ntasks, ex.table, ex.table_len,
                        ahead, ex.conv_ctr);
