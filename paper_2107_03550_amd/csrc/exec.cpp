@@ -756,24 +756,29 @@ hipError_t tune_conv(Exec* ex, int64_t steps_per_trial, hipStream_t s, int* chos
   *what = "creating tuning events";
   e = hipEventCreate(&a);
   if (!e) e = hipEventCreate(&b);
+  // one trial: the step graph of a shape, settled by one replay, then timed
+  auto trial = [&](const Shape& g, bool cached, float* ms) {
+    ex->drop_graph();
+    ex->conv_grid = g.grid;
+    ex->stages_first = g.first;
+    ex->closure_main = g.cmain;
+    ex->cached_loads = cached;
+    *what = "capturing the step graph";
+    hipError_t r = ensure_graph(ex, s);
+    *what = "launching tuning steps";
+    if (!r) r = hipGraphLaunch(ex->graph, s);  // settles the new grid
+    if (!r) r = hipEventRecord(a, s);
+    for (int64_t k = 0; k < chunks && !r; ++k) r = hipGraphLaunch(ex->graph, s);
+    if (!r) r = hipEventRecord(b, s);
+    if (!r) r = hipEventSynchronize(b);
+    if (!r) r = hipEventElapsedTime(ms, a, b);
+    return r;
+  };
   float best_ms = 0.f;
   Shape best{ex->conv_grid, ex->stages_first, ex->closure_main};
   for (size_t c = 0; c < cand.size() && !e; ++c) {
-    ex->drop_graph();
-    ex->conv_grid = cand[c].grid;
-    ex->stages_first = cand[c].first;
-    ex->closure_main = cand[c].cmain;
-    ex->cached_loads = false;
-    *what = "capturing the step graph";
-    e = ensure_graph(ex, s);
-    *what = "launching tuning steps";
-    if (!e) e = hipGraphLaunch(ex->graph, s);  // settles the new grid
-    if (!e) e = hipEventRecord(a, s);
-    for (int64_t k = 0; k < chunks && !e; ++k) e = hipGraphLaunch(ex->graph, s);
-    if (!e) e = hipEventRecord(b, s);
-    if (!e) e = hipEventSynchronize(b);
     float ms = 0.f;
-    if (!e) e = hipEventElapsedTime(&ms, a, b);
+    e = trial(cand[c], false, &ms);
     if (!e && (c == 0 || ms < best_ms)) {
       best_ms = ms;
       best = cand[c];
@@ -783,21 +788,8 @@ hipError_t tune_conv(Exec* ex, int64_t steps_per_trial, hipStream_t s, int* chos
   // policy (kept only if faster)
   bool cached = false;
   if (!e) {
-    ex->drop_graph();
-    ex->conv_grid = best.grid;
-    ex->stages_first = best.first;
-    ex->closure_main = best.cmain;
-    ex->cached_loads = true;
-    *what = "capturing the step graph";
-    e = ensure_graph(ex, s);
-    *what = "launching tuning steps";
-    if (!e) e = hipGraphLaunch(ex->graph, s);
-    if (!e) e = hipEventRecord(a, s);
-    for (int64_t k = 0; k < chunks && !e; ++k) e = hipGraphLaunch(ex->graph, s);
-    if (!e) e = hipEventRecord(b, s);
-    if (!e) e = hipEventSynchronize(b);
     float ms = 0.f;
-    if (!e) e = hipEventElapsedTime(&ms, a, b);
+    e = trial(best, true, &ms);
     if (!e && ms < best_ms) {
       best_ms = ms;
       cached = true;
