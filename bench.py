@@ -173,14 +173,16 @@ def roofline(m, workload, closure, fp64):
     }
 
 
-def traffic_from_profiles(workload: str, closure: bool, alg_bytes: float, tile=None):
+def traffic_from_profiles(workload: str, closure: bool, alg_bytes: float, tile=None,
+                          prefix: str = "conv_traffic_"):
     """HBM bytes per conv launch from committed rocprofv3 counter summaries,
     if they were taken on the current kernel source and on this very launch
-    (same workload, same form, same tile, same algorithmic bytes)."""
+    (same workload, same form, same tile, same algorithmic bytes); prefix
+    "var_traffic_" holds those of the variable-step conv."""
     tag = workload + ("-closure" if closure else "")
-    names = [f"conv_traffic_{tag}.json"]
+    names = [f"{prefix}{tag}.json"]
     if tile is not None:
-        names.insert(0, f"conv_traffic_{tag}_tile{tile}.json")
+        names.insert(0, f"{prefix}{tag}_tile{tile}.json")
     for name in names:
         path = os.path.join(ROOT, "profiles", name)
         if not os.path.exists(path):
@@ -189,7 +191,8 @@ def traffic_from_profiles(workload: str, closure: bool, alg_bytes: float, tile=N
             z = json.load(f)
         if z.get("kernel_sha256_16") != kernel_hash():
             continue
-        if z.get("algorithmic_bytes_per_launch") != alg_bytes:
+        alg = z.get("algorithmic_bytes_per_launch")
+        if alg is None or abs(alg - alg_bytes) > 1e-9 * abs(alg_bytes):
             continue
         if tile is not None and z.get("conv_tile", tile) != tile:
             continue
@@ -253,7 +256,9 @@ def measure_cycle(pkg, years):
     if n:
         achieved = b / (ms / n * 1e-3) / 1e9
         conv = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_from_profiles(CYCLE_WORKLOAD, False, round(b, 1),
+                                                 prefix="var_traffic_"),
                 "kernel": "k_conv_var<double>", "bytes_per_launch": round(b, 1),
                 "avg_launch_us": round(ms / n * 1e3, 3), "launches": n,
                 "pass": f"all launches of the first {PROFILE_YEARS:g} simulated years (evented)"}

@@ -55,6 +55,15 @@ def test_traffic_only_for_the_profiled_launch(tmp_path, monkeypatch):
     assert bench.traffic_from_profiles("rough-N65536", False, 5.0, 1024) == 7
     assert bench.traffic_from_profiles("rough-N65536", False, 5.0, 512) == 6
     assert bench.traffic_from_profiles("rough-N65536", True, 5.0, 1024) is None
+    # the variable-step conv's counters sit under their own prefix
+    (tmp_path / "profiles" / "var_traffic_sine-cycle-N4096.json").write_text(json.dumps(
+        {"kernel_sha256_16": "abc", "algorithmic_bytes_per_launch": 43415915.9,
+         "bytes_per_launch": 61878122}))
+    assert bench.traffic_from_profiles("sine-cycle-N4096", False, 43415915.9,
+                                       prefix="var_traffic_") == 61878122
+    assert bench.traffic_from_profiles("sine-cycle-N4096", False, 43415915.9) is None
+    assert bench.traffic_from_profiles("sine-cycle-N4096", False, 43415916.9,
+                                       prefix="var_traffic_") is None
 
 
 def test_committed_traffic_profiles_match_their_algorithmic_bytes():
@@ -69,3 +78,16 @@ def test_committed_traffic_profiles_match_their_algorithmic_bytes():
         ratio = z["bytes_per_launch"] / z["algorithmic_bytes_per_launch"]
         assert 1.0 <= ratio < 1.1, (f, ratio)
         assert len(z["kernel_sha256_16"]) == 16
+
+
+def test_committed_variable_step_traffic():
+    """The variable-step conv's counter summary: its algorithmic bytes are
+    the records inside the windows only; the kernel also fetches the records
+    of a live tile's slots past the window (requested before the window test,
+    weighed zero), so its traffic is above them, but within 1.5 times."""
+    with open(os.path.join(ROOT, "profiles", "var_traffic_sine-cycle-N4096.json")) as fh:
+        z = json.load(fh)
+    ratio = z["bytes_per_launch"] / z["algorithmic_bytes_per_launch"]
+    assert 1.0 <= ratio < 1.5, ratio
+    assert z["dispatches"][0] == z["dispatches"][1] > 0
+    assert len(z["kernel_sha256_16"]) == 16
