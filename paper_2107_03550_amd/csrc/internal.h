@@ -522,6 +522,11 @@ hipError_t launch_closure(const Exec& ex, int ahead, hipStream_t s);
 void closure_pack(const float* params, std::vector<unsigned short>* frag, std::vector<float>* bias);
 // kept lags M' = ceil(cut M) of a window of M lags, or M when the mode stays open
 int closure_kept(int M, double cut);
+// window lengths M_n (steps) of modes n = 0..N/2 for the cut-off k_c L
+std::vector<int> window_steps(int64_t N, double L, double cs, double dt, double kcL);
+// the conv work lists of a fault's ring (tiles or packed rows, tasks, partial
+// sum indices, part0/nparts); returns the number of partial sums
+int build_tiles(const sbiem_plan* p, DtData* d, int tile, long double th_unit);
 int conv_grid_size(int precision, int ntasks, int table_len, int reserve);
 int default_conv_reserve(double conv_bytes);
 hipError_t setup_kernel_attributes(int precision);

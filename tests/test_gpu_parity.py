@@ -357,19 +357,22 @@ def test_batch_of_full_size_faults_matches_individual_plans_bitwise():
     batch.close()
 
 
-def test_tuned_runs_equal_untuned_runs_bitwise():
+@pytest.mark.parametrize("tile", [512, 64])
+def test_tuned_runs_equal_untuned_runs_bitwise(tile):
     """Autotuning replays ordinary steps with several convolution grids and
     launch orders; with the tile fixed (sbiem_set_conv_tile) results do not
     depend on them, so a tuned plan ends where an untuned one run for the
-    same number of steps does (plans and batches)."""
+    same number of steps does (plans and batches; tile 64: packed rows,
+    whose grids and orders are tuned like the tiles')."""
     pkg = _pkg()
     sc = Scenario(512, 10e3, 0.5 * (10e3 / 512) / CS, rough_10km(512, seed=6), theta_mode="exp",
                   spec=FrictionSpec(overstress=8e6), consistent_V0=True)
     a = make_plan(sc, pkg.SBIEM_FP32CONV)
     b = make_plan(sc, pkg.SBIEM_FP32CONV)
-    a.set_conv_tile(512)
+    a.set_conv_tile(tile)
+    b.set_conv_tile(tile)
     grid = a.tune(sc.dt, 16)
-    assert a.conv_tile() == 512
+    assert a.conv_tile() == tile
     assert grid >= 1
     a.run(sc.dt, 37)
     done = a.steps_done()
@@ -380,13 +383,15 @@ def test_tuned_runs_equal_untuned_runs_bitwise():
         assert np.array_equal(ga[k], gb[k]), k
     # a batch of two faults against its members stepped alone
     p1, p2 = make_plan(sc, pkg.SBIEM_FP32CONV), make_plan(sc, pkg.SBIEM_FP32CONV)
-    p1.set_conv_tile(512)
+    p1.set_conv_tile(tile)
+    p2.set_conv_tile(tile)
     bt = pkg.Batch([p1, p2])
     bt.tune(16)
-    assert p1.conv_tile() == p2.conv_tile() == 512
+    assert p1.conv_tile() == p2.conv_tile() == tile
     n = p1.steps_done()
     assert n == p2.steps_done() > 0
     q = make_plan(sc, pkg.SBIEM_FP32CONV)
+    q.set_conv_tile(tile)
     q.run(sc.dt, n)
     g1, gq = p1.get_state(), q.get_state()
     for k in ("slip", "V", "theta", "tau_el", "sigma_el"):
