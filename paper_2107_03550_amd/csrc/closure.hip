@@ -135,34 +135,60 @@ __global__ void __launch_bounds__(256) k_mlp_eval(NetDev net, const float* __res
 // history sums are computed for (the committed-step counter plus ahead).
 // Ring slot of lag j: p = (b - j + 1) mod R with b = that step - 1.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_closure(const FaultDev* __restrict__ faults,
-                                                 const ClosureMode* __restrict__ cm, int ncm,
-                                                 NetDev netT, NetDev netN, int ahead) {
-  // both networks staged in LDS once per workgroup; each wave then loops
-  // over groups of 16 closed modes
+// The words of one fault that the closure reads (its step counter and error
+// word do not change while the closure runs: they are read once per launch).
+struct ClosureFault {
+  const float4* ring;
+  double4* tails;
+  long long b;  // the step the tails are for, minus one
+  int err, nmodes;
+};
+
+__device__ __forceinline__ ClosureFault closure_fault(const FaultDev& fd, int ahead) {
+  ClosureFault w;
+  w.ring = (const float4*)fd.ring;
+  w.tails = fd.tails;
+  w.b = *(const __attribute__((address_space(1))) long long*)fd.step + ahead - 1;
+  w.err = *(const __attribute__((address_space(1))) int*)fd.err;
+  w.nmodes = fd.nmodes;
+  return w;
+}
+
+__global__ void __launch_bounds__(kClosureThreads) k_closure(const FaultDev* __restrict__ faults,
+                                                             int nfaults,
+                                                             const ClosureMode* __restrict__ cm,
+                                                             int ncm, NetDev netT, NetDev netN,
+                                                             int ahead) {
+  // both networks and the words of the first kClosureFaults faults staged in
+  // LDS once per workgroup; each wave then loops over groups of 16 closed
+  // modes
   __shared__ v4s sfrag[2][32 * 64];
   __shared__ float sbias[2][132];
-  for (int i = threadIdx.x; i < 32 * 64; i += 256) {
+  __shared__ ClosureFault sfault[kClosureFaults];
+  for (int i = threadIdx.x; i < 32 * 64; i += kClosureThreads) {
     sfrag[0][i] = netT.frag[i];
     sfrag[1][i] = netN.frag[i];
   }
-  for (int i = threadIdx.x; i < 130; i += 256) {
+  for (int i = threadIdx.x; i < 130; i += kClosureThreads) {
     sbias[0][i] = netT.bias[i];
     sbias[1][i] = netN.bias[i];
   }
+  const int nstaged = min(nfaults, kClosureFaults);
+  for (int i = threadIdx.x; i < nstaged; i += kClosureThreads) sfault[i] = closure_fault(faults[i], ahead);
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int q = lane >> 4, j = lane & 15;
   const int ngroups = (ncm + 15) / 16;
-  for (int grp = blockIdx.x * 4 + (threadIdx.x >> 6); grp < ngroups; grp += gridDim.x * 4) {
+  constexpr int wpb = kClosureThreads / 64;
+  for (int grp = blockIdx.x * wpb + (threadIdx.x >> 6); grp < ngroups; grp += gridDim.x * wpb) {
     const int m = grp * 16 + j;
     const bool valid = m < ncm;
     const ClosureMode c = cm[valid ? m : 0];
-    const FaultDev& fd = faults[c.fault];
-    const int err = *(const __attribute__((address_space(1))) int*)fd.err;
-    const long long b = *(const __attribute__((address_space(1))) long long*)fd.step + ahead - 1;
+    const ClosureFault fw = c.fault < nstaged ? sfault[c.fault] : closure_fault(faults[c.fault], ahead);
+    const int err = fw.err;
+    const long long b = fw.b;
     typedef const __attribute__((address_space(1))) v4f* gring;
-    const gring ring = (gring)((const float4*)fd.ring + c.ring_off);
+    const gring ring = (gring)(fw.ring + c.ring_off);
     // ring slot of lag M'_n - 16 (the first input); lag M'_n - 16 + k sits k
     // slots before it (cyclically)
     const int Rn = c.Rn;
@@ -218,8 +244,8 @@ __global__ void __launch_bounds__(256) k_closure(const FaultDev* __restrict__ fa
       // tail = D a_15 + y r / (c_s |k_n|), a_15 the oldest kept record (lag M'_n - 1)
       const double sT_ = (double)rT * c.inv_csk, sN_ = (double)rN * c.inv_csk;
       // the Nyquist coefficient of a real signal is real
-      const double im = c.pm == fd.nmodes ? 0.0 : 1.0;
-      fd.tails[c.pm] = make_double4(c.dT * a.x + yT0 * sT_, im * (c.dT * a.y + yT1 * sT_),
+      const double im = c.pm == fw.nmodes ? 0.0 : 1.0;
+      fw.tails[c.pm] = make_double4(c.dT * a.x + yT0 * sT_, im * (c.dT * a.y + yT1 * sT_),
                                     c.dN * a.z + yN0 * sN_, im * (c.dN * a.w + yN1 * sN_));
     }
   }
@@ -479,10 +505,12 @@ hipError_t launch_closure(const Exec& ex, int ahead, hipStream_t s) {
   if (!ex.closure_modes || ex.nclosure == 0) return hipSuccess;
   NetDev T{(const v4s*)ex.net_frag[0], ex.net_bias[0]};
   NetDev N{(const v4s*)ex.net_frag[1], ex.net_bias[1]};
+  constexpr int wpb = kClosureThreads / 64;
   const int groups = (ex.nclosure + 15) / 16;  // one wave per 16 modes and pass
-  const int blocks = std::min((groups + 3) / 4, 4 * 256);
-  hipLaunchKernelGGL(k_closure, dim3(blocks), dim3(256), 0, s, ex.d_faults, ex.closure_modes,
-                     ex.nclosure, T, N, ahead);
+  // persistent: the workgroups resident at once (three per CU: LDS and registers)
+  const int blocks = std::min((groups + wpb - 1) / wpb, 3 * 256);
+  hipLaunchKernelGGL(k_closure, dim3(blocks), dim3(kClosureThreads), 0, s, ex.d_faults,
+                     ex.nfaults, ex.closure_modes, ex.nclosure, T, N, ahead);
   return hipGetLastError();
 }
 

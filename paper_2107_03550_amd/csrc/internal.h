@@ -55,6 +55,8 @@ struct ClosureMode {
   double dT, dN;      // sums of the discarded weights, lags M'_n .. M_n - 1
 };
 constexpr int kClosureParams = 6466;  // 33*64 + 64 + 64*64 + 64 + 64*2 + 2
+constexpr int kClosureThreads = 512;  // closure inference workgroups (8 waves)
+constexpr int kClosureFaults = 64;    // faults whose words a closure workgroup stages in LDS
 
 // ---------------------------------------------------------------------------
 // Device-visible description of one fault at one time step.  One array of
