@@ -140,6 +140,33 @@ def test_step_with_closure_matches_oracle(tile):
     assert worst["tau_el"] < 1e-5 and worst["sigma_el"] < 1e-5, worst
 
 
+def test_closure_batch_beyond_staged_faults():
+    """A batch of 66 faults with the closure against each fault stepped
+    alone, bit for bit: the closure launch stages the words of the first 64
+    faults of a launch in LDS and reads those of the others directly, so
+    both paths must give the same tails."""
+    pkg = _pkg()
+    pT, pN = _params(21, 0.02, 0.05), _params(22, 0.02, 0.05)
+    scs = [_rupture(N=64, seed=100 + i) for i in range(66)]
+    a, b = [], []
+    for sc in scs:
+        for lst in (a, b):
+            q = make_plan(sc, pkg.SBIEM_FP32CONV)
+            q.set_closure(pT.astype(np.float32), pN.astype(np.float32), 0.25)
+            lst.append(q)
+    batch = pkg.Batch(a)
+    batch.run(30)
+    for q, sc in zip(b, scs):
+        q.run(sc.dt, 30)
+    for i, (qa, qb) in enumerate(zip(a, b)):
+        ga, gb = qa.get_state(), qb.get_state()
+        for k in ("slip", "V", "theta", "tau_el", "sigma_el"):
+            assert np.array_equal(ga[k], gb[k]), (i, k)
+    batch.close()
+    for q in a + b:
+        q.close()
+
+
 def _nucleating(N, seed, overstress):
     from sbiem_inputs import rough_fault
     L = 10.0 * N
