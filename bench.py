@@ -156,7 +156,7 @@ def time_form(form, steps, warmup, tune=True):
     return out
 
 
-CONV32_SHAPES = {64: "k_conv32p", 256: "k_conv32<4,4>", 512: "k_conv32<8,2>", 1024: "k_conv32<16,1>"}
+CONV32_SHAPES = {64: "k_conv32p", 256: "k_conv32<4,4>", 320: "k_conv32<5,4>", 512: "k_conv32<8,2>", 1024: "k_conv32<16,1>"}
 
 
 def roofline(m, workload, closure, fp64):
@@ -446,7 +446,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the closure's accuracy run through a rupture")
-    ap.add_argument("--conv-tile", type=int, default=0, choices=(0, 64, 256, 512, 1024),
+    ap.add_argument("--conv-tile", type=int, default=0, choices=(0, 64, 256, 320, 512, 1024),
                     help="fix the FP32 conv tile (records); 0: autotuned with the grid")
     ap.add_argument("--cycle-years", type=float, default=35.0,
                     help="simulated years of the sinusoidal-fault cycle measured beside the "

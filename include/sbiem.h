@@ -390,8 +390,8 @@ int sbiem_batch_profile(sbiem_batch* b, double* conv_ms, int64_t* conv_launches,
  * two is kept until the plan's tables are rebuilt (sbiem_set_dt,
  * sbiem_set_precision, sbiem_set_closure).  Unless a member's tile was set
  * with sbiem_set_conv_tile, all of this is repeated for each FP32 tile
- * shape (256, 512 and 1024 ring records per tile; the ring itself does not
- * change) and the fastest tile is kept with its grid and order.  The trial
+ * shape (256, 320, 512 and 1024 ring records per tile; the ring itself does
+ * not change) and the fastest tile is kept with its grid and order.  The trial
  * steps are ordinary steps: results do not depend on the launch shape or
  * order, and a tile change alters only the FP32 summation order of the
  * history sums; the state advances by about (steps_per_trial + 16) times the
@@ -403,7 +403,8 @@ int sbiem_tune(sbiem_plan* p, double dt, int64_t steps_per_trial, int32_t* conv_
 
 /* FP32 convolution tile: records = 256, 512 or 1024 ring records per
  * wavefront tile (16 rows of 64 records in flight per wave either way, so a
- * workgroup task stays 8192 records), or 0 for the default by window length
+ * workgroup task stays 8192 records), 320 (five rows, four tiles per wave:
+ * 20 rows in flight, tasks of 10240 records), or 0 for the default by window length
  * (512; 256 under the learned closure, whose kept windows are short).
  * records = 64 selects packed rows: every 64-record row of every mode in
  * order, 16 to a wave and 128 to a task, so no row lies past a mode's end

@@ -817,7 +817,7 @@ std::vector<int> tile_candidates(const std::vector<sbiem_plan*>& plans) {
     if (p->conv_tile_set) return c;
   // (packed rows, kTileSlots32p, only when set: slower on every workload
   // measured, their per-row descriptors costing more than they save)
-  for (int t : {kTileSlots32, kTileSlots32s, kTileSlots32l})
+  for (int t : {kTileSlots32, kTileSlots32s, kTileSlots32w, kTileSlots32l})
     if (t != c[0]) c.push_back(t);
   return c;
 }

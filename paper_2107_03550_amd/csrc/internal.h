@@ -152,6 +152,14 @@ constexpr int kTaskTiles32s = kWaveTiles32s * (kConvThreads / 64);
 // FP32 tile shapes the conv can take (records per tile; 16 rows in flight per
 // wave, so every task is 8192 records): 256 (short windows), 512, 1024
 constexpr int kTileSlots32l = 1024;
+// A wider shape: five rows per tile and four tiles per wave, 20 rows in flight
+// per wave (the most the vector registers hold at two workgroups per CU)
+constexpr int kTileSlots32w = 320;
+constexpr int kWaveTiles32w = 4;
+// FP32 tiles per wave of a tile shape (records per tile)
+constexpr int conv32_wave_tiles(int tile) {
+  return tile == kTileSlots32w ? kWaveTiles32w : 16 / (tile / 64);
+}
 // The packed FP32 layout: one 64-record row per unit, the rows of one mode
 // and of consecutive modes filling each wave's 16 rows (no row past a mode's
 // end); a task is 128 rows, whatever the modes.

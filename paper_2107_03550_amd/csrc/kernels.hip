@@ -465,7 +465,7 @@ k_conv32(const FaultDev* __restrict__ faults, const Tile* __restrict__ tiles,
   const ConvTask none{0, 0, 0, 0};
   ConvTask tk = task < ntasks ? tasks[task] : none;
   ConvTask nk = nxt < ntasks ? tasks[nxt] : none;
-  static_assert(U * K == 16, "16 rows in flight per wave");
+  static_assert(U * K == 16 || U * K == 20, "16 or 20 rows in flight per wave");
   TileR t[K];
   bool has[K];
   float4 h[K][U];
@@ -2011,6 +2011,7 @@ hipError_t setup_kernel_attributes(int precision) {
   if (!e && idx) e = conv32_attributes<8, 2>();
   if (!e && idx) e = conv32_attributes<4, 4>();
   if (!e && idx) e = conv32_attributes<16, 1>();
+  if (!e && idx) e = conv32_attributes<5, 4>();
   if (!e && idx)
     e = hipFuncSetAttribute((const void*)k_conv32p, hipFuncAttributeMaxDynamicSharedMemorySize,
                             kMaxLdsBytes - kConvStaticLds);
@@ -2062,6 +2063,8 @@ hipError_t launch_conv(const Exec& ex, int ahead, hipStream_t s) {
     static_assert(kTileSlots32 == 8 * 64 && kWaveTiles32 == 2, "tile shape");
     static_assert(kTileSlots32s == 4 * 64 && kWaveTiles32s == 4, "short tile shape");
     static_assert(kTileSlots32l == 16 * 64, "long tile shape");
+    static_assert(kTileSlots32w == 5 * 64 && conv32_wave_tiles(kTileSlots32w) == 4,
+                  "wide tile shape");
     if (ex.tile_rows == 1)
       hipLaunchKernelGGL(k_conv32p, dim3(ex.conv_grid), dim3(kConvThreads), lds, s, ex.d_faults,
                          (const RowDesc*)ex.d_tiles, ex.d_tasks, ex.ntasks, ex.table, ex.table_len,
@@ -2070,6 +2073,8 @@ hipError_t launch_conv(const Exec& ex, int ahead, hipStream_t s) {
       launch_conv32<4, 4>(ex, ahead, s, lds);
     else if (ex.tile_rows == 16)
       launch_conv32<16, 1>(ex, ahead, s, lds);
+    else if (ex.tile_rows == 5)
+      launch_conv32<5, 4>(ex, ahead, s, lds);
     else
       launch_conv32<8, 2>(ex, ahead, s, lds);
   } else {

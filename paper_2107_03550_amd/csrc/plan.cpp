@@ -314,7 +314,7 @@ int build_tiles(const sbiem_plan* p, DtData* d, int tile, long double th_unit) {
   const bool fp32 = p->precision == SBIEM_FP32CONV && !d->var;
   if (fp32 && tile == kTileSlots32p) return build_rows(p, d, th_unit);
   d->row_meta.clear();
-  const int task_tiles = fp32 ? (16 / (tile / 64)) * (kConvThreads / 64) : kTaskTiles64;
+  const int task_tiles = fp32 ? conv32_wave_tiles(tile) * (kConvThreads / 64) : kTaskTiles64;
   d->tile_slots = tile;
   d->tiles.clear();
   d->tasks.clear();
@@ -1085,8 +1085,8 @@ int sbiem_kernel_primitive_eval(double cs, double cp, const double* T, int64_t n
 int sbiem_set_conv_tile(sbiem_plan* p, int records) {
   if (int s = check_plan(p)) return s;
   if (records != 0 && records != kTileSlots32s && records != kTileSlots32 &&
-      records != kTileSlots32l && records != kTileSlots32p)
-    return fail(p, SBIEM_EINVAL, "set_conv_tile: records must be 0, 64, 256, 512 or 1024");
+      records != kTileSlots32l && records != kTileSlots32p && records != kTileSlots32w)
+    return fail(p, SBIEM_EINVAL, "set_conv_tile: records must be 0, 64, 256, 320, 512 or 1024");
   if (p->batch_refs > 0) return fail(p, SBIEM_EINVAL, "set_conv_tile: plan is used by a batch");
   p->conv_tile = records;
   p->conv_tile_set = records != 0;

@@ -104,7 +104,7 @@ void check_case(const Case& c) {
   const int extra = build_tiles(&p, &d, tile, th_unit);
   const int ntiles = (int)d.tiles.size();
   const int cap = packed ? kTaskRows
-                         : (fp32 ? (16 / (tile / 64)) * (kConvThreads / 64) : kTaskTiles64);
+                         : (fp32 ? conv32_wave_tiles(tile) * (kConvThreads / 64) : kTaskTiles64);
   char tag[160];
   std::snprintf(tag, sizeof tag, "N=2^%d L=%g beta=%g kc=(%g,%g) closure=%d var=%d tile=%d",
                 c.log2N, c.L, c.beta, c.kcT, c.kcN, (int)c.closure, (int)c.var, tile);
@@ -251,7 +251,7 @@ int main() {
         for (int cl = 0; cl < 2; ++cl) {
           const double L = (lg % 2 ? 10.0 : 40.0) * (double)(1 << lg);
           if (lg <= 14 || (beta == 0.5 && k[0] == 200.0)) {
-            for (int tile : {kTileSlots32p, kTileSlots32s, kTileSlots32, kTileSlots32l})
+            for (int tile : {kTileSlots32p, kTileSlots32s, kTileSlots32w, kTileSlots32, kTileSlots32l})
               cases.push_back({lg, L, beta, k[0], k[1], cl == 1, false, SBIEM_FP32CONV, tile});
             if (cl == 0) {
               cases.push_back({lg, L, beta, k[0], k[1], false, false, SBIEM_FP64, 0});
@@ -261,7 +261,7 @@ int main() {
         }
   // the benchmark's fault (N = 2^18, 2400 km, beta 0.5), plain and closed
   for (int cl = 0; cl < 2; ++cl)
-    for (int tile : {kTileSlots32p, kTileSlots32s, kTileSlots32})
+    for (int tile : {kTileSlots32p, kTileSlots32s, kTileSlots32w, kTileSlots32})
       cases.push_back({18, 2400e3, 0.5, 200.0, 200.0, cl == 1, false, SBIEM_FP32CONV, tile});
   for (const Case& c : cases) check_case(c);
   std::printf("%lld cases, %lld failures\n", g_cases, g_fail);

@@ -57,11 +57,12 @@ def test_stress_fp64_matches_oracle(N, nt):
 
 
 @pytest.mark.parametrize("N,nt,tile", [(1024, 300, 0), (512, 1100, 0), (1024, 1500, 256),
+                                        (1024, 1500, 320), (256, 2100, 320),
                                         (1024, 1500, 1024), (1024, 1500, 64), (512, 300, 64),
                                         (256, 2100, 64)])
 def test_stress_fp32_matches_oracle(N, nt, tile):
     """FP32 stress path against the oracle; the later cases put windows of up
-    to 2048 records through tiles of 256 and 1024 records and through packed
+    to 2048 records through tiles of 256, 320 and 1024 records and through packed
     rows (tile 64: modes of one to 32 rows sharing waves and tasks, a mode
     cut by a task boundary, a padded last task)."""
     from oracle.spectral import curvature
@@ -281,7 +282,8 @@ def _workload_plan_and_oracle(w, nsteps):
 
 @pytest.mark.parametrize("name,tile", [("seamount-N8192", 0), ("ensemble64-N16384", 0),
                                        ("rough-N65536", 0), ("ensemble16-N262144", 0),
-                                       ("rough-N65536", 64), ("ensemble16-N262144", 64)])
+                                       ("rough-N65536", 64), ("ensemble16-N262144", 64),
+                                       ("ensemble16-N262144", 320)])
 def test_step_fp32_full_size_matches_oracle(name, tile):
     """The first 20 steps of the full-size workloads (graph replay, as in
     bench.py) against the oracle, compared after a 16-step graph replay and
