@@ -401,7 +401,7 @@ def test_tuned_runs_equal_untuned_runs_bitwise(tile):
 
 
 def test_tuning_over_tile_shapes():
-    """Automatic tuning also tries the 256-, 512- and 1024-record tiles: the
+    """Automatic tuning also tries the 256-, 320-, 512- and 1024-record tiles: the
     plan and the batch keep one of them, and a run on the chosen tile stays
     within the FP32 tolerance of untuned runs (a tile only reorders the FP32
     history sums); a plan set to the chosen tile reproduces the steps after
@@ -412,7 +412,7 @@ def test_tuning_over_tile_shapes():
     a = make_plan(sc, pkg.SBIEM_FP32CONV)
     a.tune(sc.dt, 16)
     tile = a.conv_tile()
-    assert tile in (256, 512, 1024)
+    assert tile in (256, 320, 512, 1024)
     n = a.steps_done()
     b = make_plan(sc, pkg.SBIEM_FP32CONV)
     b.run(sc.dt, n)
@@ -435,7 +435,7 @@ def test_tuning_over_tile_shapes():
     p1, p2 = make_plan(sc, pkg.SBIEM_FP32CONV), make_plan(sc, pkg.SBIEM_FP32CONV)
     bt = pkg.Batch([p1, p2])
     bt.tune(16)
-    assert p1.conv_tile() == p2.conv_tile() in (256, 512, 1024)
+    assert p1.conv_tile() == p2.conv_tile() in (256, 320, 512, 1024)
     bt.run(20)
     g1, g2 = p1.get_state(), p2.get_state()
     for k in ("slip", "V", "tau_el", "sigma_el"):
