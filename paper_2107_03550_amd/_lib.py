@@ -402,7 +402,7 @@ class Plan:
         return ms.value, n.value, b.value
 
     def set_conv_tile(self, records):
-        """FP32 conv tile (256, 512, 1024 records; 0 = default by window)."""
+        """FP32 conv tile (64: packed rows, 256, 320, 512, 1024 records; 0 = default by window)."""
         self._c(lib.sbiem_set_conv_tile(self.handle, int(records)))
 
     def conv_tile(self):

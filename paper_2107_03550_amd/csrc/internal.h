@@ -477,7 +477,7 @@ FaultDev make_fault_desc(sbiem_plan* p, DtData* dtd, DynData* dyn, double V_pl, 
 // Allocate tables/ring for dt (host side computations + uploads).
 int build_dt_data(sbiem_plan* p, double dt, DtData** out);
 // Re-cut an FP32 fixed-step plan's conv work into tiles of `tile` records
-// (256, 512, 1024): tiles, tasks, partial indices and per-mode constants;
+// (64: packed rows, 256, 320, 512, 1024): tiles, tasks, partial indices and per-mode constants;
 // the ring is untouched.  The caller rebuilds the execution context and
 // clears `primed` (the pending sums are laid out by tile).
 int retile(sbiem_plan* p, int tile);
