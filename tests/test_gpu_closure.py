@@ -110,7 +110,7 @@ def test_training_pairs_match_oracle():
     assert ey < 1e-4
 
 
-@pytest.mark.parametrize("tile", [0, 64])
+@pytest.mark.parametrize("tile", [0, 64, 320])
 def test_step_with_closure_matches_oracle(tile):
     """Closure-on steps against the oracle with the same networks (tile 64:
     the packed rows of the short kept windows).  The networks are untrained

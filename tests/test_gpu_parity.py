@@ -125,7 +125,7 @@ def test_step_fp64_dynamic_rupture():
     assert worst < 1e-10, worst
 
 
-@pytest.mark.parametrize("tile", [0, 64])
+@pytest.mark.parametrize("tile", [0, 64, 320])
 def test_step_fp32_dynamic_rupture_N1024(tile):
     pkg = _pkg()
     N = 1024
@@ -235,7 +235,7 @@ def test_failure_leaves_state_at_start_of_step():
         assert np.array_equal(before[k], after[k])
 
 
-@pytest.mark.parametrize("tile", [0, 64])
+@pytest.mark.parametrize("tile", [0, 64, 320])
 def test_batch_matches_individual_plans_bitwise(tile):
     pkg = _pkg()
     plans_a, plans_b = [], []

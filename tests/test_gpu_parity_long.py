@@ -58,12 +58,13 @@ def _pieces(M, task_records):
     return -(-(M - 1) // task_records)
 
 
-@pytest.mark.parametrize("tile", [0, 64])
+@pytest.mark.parametrize("tile", [0, 64, 320])
 def test_stress_fp32_long_windows_in_three_pieces(tile):
     """N = 64 at beta = 1/320: every window holds about 20480 lags, three
     FP32 tasks of 8192 ring records (tile 64: packed rows, a mode across
-    three or four 128-row tasks); 21000 intervals fill every record (the
-    fill wraps) with random rates."""
+    three or four 128-row tasks; tile 320: tasks of 10240 records, two or
+    three pieces); 21000 intervals fill every record (the fill wraps) with
+    random rates."""
     from oracle.spectral import curvature_fft
     from oracle.stress import stress_from_history
     from oracle.windows import midpoint_weights
